@@ -1,0 +1,283 @@
+/*
+ * julia_oracle.c -- plain, slow, single-threaded CPU oracle.
+ *
+ * TEST INFRASTRUCTURE ONLY (see julia_oracle.h): used by tests, the smoke
+ * check and the benchmark's CPU-baseline leg; never by the product path.
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -fPIC -shared
+ * (oracle/build_oracle.py).  -ffp-contract=off keeps every a*b + c of the
+ * FP64 and FP32 paths as a rounded product followed by a rounded sum; fused
+ * multiply-adds appear only where fmaf() is called by name.  On x86-64 the
+ * float and double types evaluate in their own precision (SSE), so every
+ * operation below is one IEEE-754 round-to-nearest-even operation.
+ *
+ * Source of the method: Mayfield et al., Section 2 (escape-time iteration of
+ * Z_{n+1} = Z_n^2 + C over pixels scaled onto the complex plane, iteration
+ * cap) and Section 3 (Mandelbrot variant: C from the pixel, Z_0 = 0).
+ */
+#include "julia_oracle.h"
+
+#include <math.h>
+
+/* ------------------------------------------------------------------------ */
+/* Pixel -> complex plane ("region-covering routine", Section 2).            */
+/* The pixel centre is cx + (2i+1-W)*hx; row 0 is the top of the window.     */
+/* ------------------------------------------------------------------------ */
+void jro_pixel_center(double re_min, double re_max, double im_min, double im_max,
+                      int32_t W, int32_t H, int32_t i, int32_t j,
+                      double *x, double *y)
+{
+    double hx = (re_max - re_min) / (2.0 * (double)W);
+    double hy = (im_max - im_min) / (2.0 * (double)H);
+    double cx = 0.5 * (re_min + re_max);
+    double cy = 0.5 * (im_min + im_max);
+    double oi = (double)(2 * (int64_t)i + 1 - W);
+    double oj = (double)(2 * (int64_t)j + 1 - H);
+    double px = oi * hx;
+    double py = oj * hy;
+    *x = cx + px;
+    *y = cy - py;
+}
+
+/* ------------------------------------------------------------------------ */
+/* FP64: the definition itself.                                              */
+/* n counts how many times Z has been advanced; the loop stops at the first  */
+/* iterate with |Z|^2 > 4 or when n reaches the cap.                         */
+/* ------------------------------------------------------------------------ */
+static int32_t count_fp64(double x, double y, double cr, double ci, int32_t max_iter)
+{
+    int32_t n = 0;
+    while (n < max_iter) {
+        double x2 = x * x;
+        double y2 = y * y;
+        double m = x2 + y2;
+        if (m > 4.0)
+            break;
+        double re = x2 - y2;
+        double xn = re + cr;        /* Re(Z^2 + C) */
+        double tx = 2.0 * x;        /* exact */
+        double im = tx * y;
+        double yn = im + ci;        /* Im(Z^2 + C) = 2xy + Im C */
+        x = xn;
+        y = yn;
+        n = n + 1;
+    }
+    return n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* FP32 formulation (fixed so a GPU kernel can be compared bit for bit):     */
+/*   |Z|^2   = fma(x, x, y*y)                                                */
+/*   Re Z'   = fma(-y, y, fma(x, x, cr))                                     */
+/*   Im Z'   = fma(x + x, y, ci)                                             */
+/* Z_0 and C are the binary64 values rounded once to binary32.               */
+/* ------------------------------------------------------------------------ */
+static int32_t count_fp32(float x, float y, float cr, float ci, int32_t max_iter)
+{
+    int32_t n = 0;
+    while (n < max_iter) {
+        float yy = y * y;
+        float m = fmaf(x, x, yy);
+        if (m > 4.0f)
+            break;
+        float t = fmaf(x, x, cr);
+        float xn = fmaf(-y, y, t);
+        float tx = x + x;
+        float yn = fmaf(tx, y, ci);
+        x = xn;
+        y = yn;
+        n = n + 1;
+    }
+    return n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Float-float ("double-single") arithmetic: a value is hi + lo with two     */
+/* binary32 numbers, |lo| <= ulp(hi)/2.  Built from error-free transforms:   */
+/*   TwoSum (Knuth; Moller): s = RN(a+b), e = (a+b) - s exactly.             */
+/*   Fast2Sum (Dekker 1971): the same when |a| >= |b| or a == 0.             */
+/*   TwoProd with FMA: p = RN(ab), e = fma(a, b, -p) = ab - p exactly.       */
+/* Double-word sum and product follow Joldes, Muller and Popescu, "Tight and */
+/* rigorous error bounds for basic building blocks of double-word            */
+/* arithmetic" (ACM TOMS 2017): the accurate sum of two double-words         */
+/* (relative error below 3u^2, also under cancellation, which x^2 - y^2      */
+/* needs) and the FMA-based product of two double-words (below 4u^2).        */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    float hi, lo;
+} dw;
+
+void jro_two_sum(float a, float b, float *s, float *e)
+{
+    float sum = a + b;
+    float b_part = sum - a;          /* what of b made it into sum */
+    float a_part = sum - b_part;     /* what of a made it into sum */
+    float a_err = a - a_part;
+    float b_err = b - b_part;
+    *s = sum;
+    *e = a_err + b_err;
+}
+
+void jro_fast_two_sum(float a, float b, float *s, float *e)
+{
+    float sum = a + b;
+    float b_part = sum - a;
+    *s = sum;
+    *e = b - b_part;
+}
+
+void jro_two_prod(float a, float b, float *p, float *e)
+{
+    float prod = a * b;
+    *p = prod;
+    *e = fmaf(a, b, -prod);
+}
+
+static dw dw_add(dw x, dw y)
+{
+    float sh, sl, th, tl, vh, vl;
+    dw z;
+    jro_two_sum(x.hi, y.hi, &sh, &sl);       /* high parts, exactly   */
+    jro_two_sum(x.lo, y.lo, &th, &tl);       /* low parts, exactly    */
+    float c = sl + th;
+    jro_fast_two_sum(sh, c, &vh, &vl);       /* renormalise           */
+    float w = tl + vl;
+    jro_fast_two_sum(vh, w, &z.hi, &z.lo);   /* renormalise again     */
+    return z;
+}
+
+static dw dw_mul(dw x, dw y)
+{
+    float ch, cl1;
+    dw z;
+    jro_two_prod(x.hi, y.hi, &ch, &cl1);     /* hi*hi, exactly        */
+    float low_low = x.lo * y.lo;
+    float cross1 = fmaf(x.hi, y.lo, low_low);
+    float cross = fmaf(x.lo, y.hi, cross1);  /* hi*lo + lo*hi + lo*lo */
+    float cl = cl1 + cross;
+    jro_fast_two_sum(ch, cl, &z.hi, &z.lo);
+    return z;
+}
+
+static dw dw_neg(dw x)
+{
+    dw z;
+    z.hi = -x.hi;
+    z.lo = -x.lo;
+    return z;
+}
+
+static dw dw_twice(dw x)
+{
+    dw z;
+    z.hi = 2.0f * x.hi; /* exact */
+    z.lo = 2.0f * x.lo; /* exact */
+    return z;
+}
+
+/* hi = RN32(v), lo = RN32(v - hi); v - hi is exact in binary64. */
+static dw dw_from_double(double v)
+{
+    dw z;
+    z.hi = (float)v;
+    z.lo = (float)(v - (double)z.hi);
+    return z;
+}
+
+void jro_dw_add(float xh, float xl, float yh, float yl, float *zh, float *zl)
+{
+    dw x = {xh, xl}, y = {yh, yl};
+    dw z = dw_add(x, y);
+    *zh = z.hi;
+    *zl = z.lo;
+}
+
+void jro_dw_mul(float xh, float xl, float yh, float yl, float *zh, float *zl)
+{
+    dw x = {xh, xl}, y = {yh, yl};
+    dw z = dw_mul(x, y);
+    *zh = z.hi;
+    *zl = z.lo;
+}
+
+void jro_dw_split(double v, float *hi, float *lo)
+{
+    dw z = dw_from_double(v);
+    *hi = z.hi;
+    *lo = z.lo;
+}
+
+/* |Z|^2 <= 4 for a double-word m: hi < 4, or hi == 4 and lo <= 0. */
+static int dw_not_above_four(dw m)
+{
+    return (m.hi < 4.0f) || (m.hi == 4.0f && m.lo <= 0.0f);
+}
+
+/* Float-float formulation of the same iteration:                           */
+/*   |Z|^2 = x*x + y*y,  Re Z' = (x*x + (-(y*y))) + cr,                      */
+/*   Im Z' = (2x)*y + ci,   each + and * a double-word operation above.      */
+static int32_t count_ff(dw x, dw y, dw cr, dw ci, int32_t max_iter)
+{
+    int32_t n = 0;
+    while (n < max_iter) {
+        dw x2 = dw_mul(x, x);
+        dw y2 = dw_mul(y, y);
+        dw m = dw_add(x2, y2);
+        if (!dw_not_above_four(m))
+            break;
+        dw re = dw_add(x2, dw_neg(y2));
+        dw xn = dw_add(re, cr);
+        dw im = dw_mul(dw_twice(x), y);
+        dw yn = dw_add(im, ci);
+        x = xn;
+        y = yn;
+        n = n + 1;
+    }
+    return n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One orbit in the chosen formulation.                                      */
+/* ------------------------------------------------------------------------ */
+int32_t jro_count(int32_t dtype, double x0, double y0, double cr, double ci,
+                  int32_t max_iter)
+{
+    if (dtype == JRO_FP32)
+        return count_fp32((float)x0, (float)y0, (float)cr, (float)ci, max_iter);
+    if (dtype == JRO_FF)
+        return count_ff(dw_from_double(x0), dw_from_double(y0),
+                        dw_from_double(cr), dw_from_double(ci), max_iter);
+    return count_fp64(x0, y0, cr, ci, max_iter);
+}
+
+static int32_t pixel_count(int32_t dtype, int32_t mode, double cr, double ci,
+                           double re_min, double re_max, double im_min, double im_max,
+                           int32_t W, int32_t H, int32_t max_iter, int32_t i, int32_t j)
+{
+    double x, y;
+    jro_pixel_center(re_min, re_max, im_min, im_max, W, H, i, j, &x, &y);
+    if (mode == JRO_MANDELBROT)
+        return jro_count(dtype, 0.0, 0.0, x, y, max_iter); /* Z_0 = 0, C = pixel */
+    return jro_count(dtype, x, y, cr, ci, max_iter);       /* Z_0 = pixel       */
+}
+
+/* The sequential version of Section 2: one main loop over the pixel region. */
+void jro_render(int32_t dtype, int32_t mode, double cr, double ci,
+                double re_min, double re_max, double im_min, double im_max,
+                int32_t W, int32_t H, int32_t max_iter, int32_t *out)
+{
+    for (int32_t j = 0; j < H; j++)
+        for (int32_t i = 0; i < W; i++)
+            out[(int64_t)j * W + i] = pixel_count(dtype, mode, cr, ci, re_min, re_max,
+                                                  im_min, im_max, W, H, max_iter, i, j);
+}
+
+void jro_render_pixels(int32_t dtype, int32_t mode, double cr, double ci,
+                       double re_min, double re_max, double im_min, double im_max,
+                       int32_t W, int32_t H, int32_t max_iter, int64_t n,
+                       const int32_t *ii, const int32_t *jj, int32_t *out)
+{
+    for (int64_t k = 0; k < n; k++)
+        out[k] = pixel_count(dtype, mode, cr, ci, re_min, re_max, im_min, im_max,
+                             W, H, max_iter, ii[k], jj[k]);
+}

@@ -1,0 +1,86 @@
+/*
+ * julia_oracle.h -- plain CPU oracle for escape-time Julia / Mandelbrot counts.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the GPU library
+ * against the definition of the method.  It shares no code, header, table or
+ * helper with the GPU library; only tests, the smoke check and the benchmark's
+ * CPU-baseline leg may load it.  Nothing in the product path calls it.
+ *
+ * Method (Mayfield et al., "Fractal Art Generation using GPUs", Section 2):
+ * every pixel of the image is scaled onto a window of the complex plane to give
+ * an initial point Z_0; the map Z_{n+1} = Z_n^2 + C is iterated and the pixel
+ * records how many iterations it takes to diverge, with a cap on the number of
+ * iterations (the paper's cap is 100).  Section 3: in the Mandelbrot variant
+ * the pixel supplies C and Z_0 = 0.
+ *
+ * Readings of the paper taken here (the paper leaves them open):
+ *   - count = index n of the first iterate with |Z_n|^2 > 4 (strict), tested
+ *     as fl(fl(x*x) + fl(y*y)) > 4 before Z_n is advanced; count = max_iter if
+ *     no iterate below max_iter escapes; max_iter = 0 gives 0 everywhere.
+ *   - pixel (i, j) (column i, row j, row 0 on top) has its centre at
+ *       x = cx + (2i + 1 - W) * hx,   y = cy - (2j + 1 - H) * hy
+ *     with hx = (re_max - re_min) / (2W), hy = (im_max - im_min) / (2H),
+ *     cx = (re_min + re_max) / 2, cy = (im_min + im_max) / 2; every product is
+ *     rounded before the sum (no fused multiply-add).
+ *   - the FP64 update is x' = (x*x - y*y) + cr, y' = ((2x) * y) + ci, each
+ *     operation rounded to binary64.
+ *   - FP32 and float-float are two further arithmetic formulations of the same
+ *     iteration, fixed here so that a GPU kernel using them can be checked
+ *     bit for bit (see julia_oracle.c).
+ *
+ * All functions are synchronous, single-threaded and take host pointers.
+ * Arguments are not validated: callers pass W, H >= 1 and max_iter >= 0.
+ */
+#ifndef JULIA_ORACLE_H
+#define JULIA_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Arithmetic formulations. */
+#define JRO_FP64 0
+#define JRO_FP32 1
+#define JRO_FF   2
+
+/* Which quantity the pixel supplies. */
+#define JRO_JULIA      0 /* Z_0 = pixel, C = given constant      (Section 2) */
+#define JRO_MANDELBROT 1 /* Z_0 = 0,     C = pixel               (Section 3) */
+
+/* Full image, row-major (H rows of W counts), row 0 = im_max. */
+void jro_render(int32_t dtype, int32_t mode, double cr, double ci,
+                double re_min, double re_max, double im_min, double im_max,
+                int32_t W, int32_t H, int32_t max_iter, int32_t *out);
+
+/* Counts of n listed pixels (column ii[k], row jj[k]) of the same image. */
+void jro_render_pixels(int32_t dtype, int32_t mode, double cr, double ci,
+                       double re_min, double re_max, double im_min, double im_max,
+                       int32_t W, int32_t H, int32_t max_iter, int64_t n,
+                       const int32_t *ii, const int32_t *jj, int32_t *out);
+
+/* Centre of pixel (i, j) in binary64. */
+void jro_pixel_center(double re_min, double re_max, double im_min, double im_max,
+                      int32_t W, int32_t H, int32_t i, int32_t j,
+                      double *x, double *y);
+
+/* Count for one orbit with explicit Z_0 = x0 + i y0 and C = cr + i ci
+ * (both given in binary64 and converted per formulation). */
+int32_t jro_count(int32_t dtype, double x0, double y0, double cr, double ci,
+                  int32_t max_iter);
+
+/* Float-float building blocks, exported so that their error-free and
+ * error-bound properties can be checked against exact rational arithmetic. */
+void jro_two_sum(float a, float b, float *s, float *e);
+void jro_fast_two_sum(float a, float b, float *s, float *e);
+void jro_two_prod(float a, float b, float *p, float *e);
+void jro_dw_add(float xh, float xl, float yh, float yl, float *zh, float *zl);
+void jro_dw_mul(float xh, float xl, float yh, float yl, float *zh, float *zl);
+void jro_dw_split(double v, float *hi, float *lo);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JULIA_ORACLE_H */

@@ -1,0 +1,89 @@
+"""Planted mistakes in the oracle must be caught by its pins.
+
+Each case copies oracle/julia_oracle.c, changes one line the way a plausible
+slip would (a dropped term, a wrong sign, an off-by-one index, a non-strict
+comparison, a lost error term), builds the copy on the CPU into a temporary
+directory and runs a fast subset of the pins of test_oracle_pins.py against
+it.  Every mutant has to fail at least one pin; the real oracle passes them all.
+"""
+import os
+import subprocess
+
+import pytest
+
+import oracle
+import test_oracle_pins as pins
+from oracle import build_oracle
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "julia_oracle.c")
+
+MUTANTS = {
+    "non_strict_escape": ("if (m > 4.0)", "if (m >= 4.0)"),
+    "minus_cr": ("double xn = re + cr;", "double xn = re - cr;"),
+    "plus_y2": ("double re = x2 - y2;", "double re = x2 + y2;"),
+    "dropped_two": ("double tx = 2.0 * x;", "double tx = x;"),
+    "ci_to_cr": ("double yn = im + ci;", "double yn = im + cr;"),
+    "row_flip": ("*y = cy - py;", "*y = cy + py;"),
+    "pixel_corner": ("double oi = (double)(2 * (int64_t)i + 1 - W);",
+                     "double oi = (double)(2 * (int64_t)i - W);"),
+    "hx_off_by_one": ("double hx = (re_max - re_min) / (2.0 * (double)W);",
+                      "double hx = (re_max - re_min) / (2.0 * (double)W - 2.0);"),
+    "cap_plus_one": ("    while (n < max_iter) {\n        double x2",
+                     "    while (n <= max_iter) {\n        double x2"),
+    "fp32_unfused_norm": ("float m = fmaf(x, x, yy);", "float m = x * x + yy;"),
+    "fp32_sign": ("float xn = fmaf(-y, y, t);", "float xn = fmaf(y, y, t);"),
+    "ff_lost_sl": ("float c = sl + th;", "float c = th;"),
+    "ff_lost_cross": ("float cross = fmaf(x.lo, y.hi, cross1);", "float cross = cross1;"),
+    "ff_lost_tl": ("float w = tl + vl;", "float w = vl;"),
+    "ff_escape_lo": ("(m.hi == 4.0f && m.lo <= 0.0f)", "(m.hi == 4.0f)"),
+    "mandel_z0_is_c": ("return jro_count(dtype, 0.0, 0.0, x, y, max_iter);",
+                       "return jro_count(dtype, x, y, x, y, max_iter);"),
+}
+
+
+def _battery():
+    """Fast subset of the pins; returns the names of those that fail."""
+    failed = []
+    checks = [("orbits_" + d, pins.test_exact_small_orbits, (d,)) for d in pins.DTYPES]
+    checks += [("numpy_%s_%d" % (d, k), pins.test_matches_numpy_reimplementation, (d, k))
+               for d in pins.DTYPES for k in (1, 3)]
+    checks += [("fingerprint", pins.test_c1_fingerprint, ()),
+               ("centres", pins.test_pixel_centres, ()),
+               ("sub_ulp_escape", pins.test_escape_by_less_than_fp32_ulp, ()),
+               ("fp32_fused", pins.test_fp32_escape_test_is_fused, ()),
+               ("cap01_fp64", pins.test_cap_zero_and_one, ("fp64",)),
+               ("eft", pins.test_error_free_transforms, ()),
+               ("dw_bounds", pins.test_double_word_error_bounds, ())]
+    for name, fn, args in checks:
+        try:
+            fn(*args)
+        except AssertionError:
+            failed.append(name)
+    return failed
+
+
+@pytest.fixture
+def swap_lib():
+    saved = oracle._load()
+    yield
+    oracle._lib = saved
+
+
+def test_real_oracle_passes_battery():
+    assert _battery() == []
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path, swap_lib):
+    old, new = MUTANTS[name]
+    text = open(SRC).read()
+    assert text.count(old) == 1, "mutation site must be unique: %r" % old
+    src = tmp_path / "julia_oracle.c"
+    src.write_text(text.replace(old, new))
+    (tmp_path / "julia_oracle.h").write_text(open(SRC[:-2] + ".h").read())
+    lib = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", *build_oracle.CFLAGS, str(src), "-o", str(lib), "-lm"],
+                   check=True, capture_output=True)
+    oracle._lib = oracle._open(str(lib))
+    failed = _battery()
+    assert failed, "mutant %s passed every pin" % name
