@@ -1,0 +1,194 @@
+/*
+ * julia.h -- C ABI of the MI355X (gfx950) escape-time renderer, libjulia.so.
+ *
+ * The operation (Mayfield et al., "Fractal Art Generation using GPUs",
+ * Section 2): every pixel of a width x height image is scaled onto a window of
+ * the complex plane to give Z_0 ("region-covering"), the map
+ * Z_{n+1} = Z_n^2 + C is iterated, and the pixel receives the number of
+ * iterations taken before |Z_n|^2 > 4, capped at max_iter (the paper caps at
+ * 100).  Section 3 adds the Mandelbrot variant: the pixel gives C and Z_0 = 0.
+ *
+ * Conventions shared by every entry point
+ *   - Counts are int32, row-major, row 0 = the top of the window (im_max),
+ *     column 0 = re_min.  Count n in [0, max_iter] is the index of the first
+ *     iterate with |Z_n|^2 > 4 (strict); max_iter when none below max_iter is.
+ *   - Pixel (i, j) has its centre at
+ *       x = cx + (2i + 1 - W) hx,  y = cy - (2j + 1 - H) hy,
+ *       hx = (re_max - re_min) / 2W, hy = (im_max - im_min) / 2H,
+ *       cx = (re_min + re_max) / 2,  cy = (im_min + im_max) / 2,
+ *     computed in binary64 with every product rounded before the sum.
+ *   - dtype selects the arithmetic of the iteration:
+ *       JR_FP64  binary64, each operation rounded: x' = (x*x - y*y) + cr,
+ *                y' = ((2x)*y) + ci, test fl(x*x + y*y) > 4.  Exact counts.
+ *       JR_FP32  binary32 with fused multiply-add: test fma(x,x,y*y) > 4,
+ *                x' = fma(-y, y, fma(x, x, cr)), y' = fma(x+x, y, ci);
+ *                Z_0 and C are the binary64 values rounded to binary32.
+ *       JR_FF    float-float (a value is hi + lo of two binary32 numbers),
+ *                error-free sums and products, for narrow (deep-zoom) windows.
+ *     The three give the same count on most pixels; FP32 and FF differ from
+ *     FP64 on a small fraction of pixels near the set's boundary.
+ *   - Memory: `out` / `out_base` are DEVICE pointers owned by the caller
+ *     (for example torch int32 tensors), 4-byte aligned, not aliased by a call
+ *     still in flight.  The library never frees caller memory.  Host arrays
+ *     passed in (frames, schedules) are copied before the call returns.
+ *   - Streams: `stream` is a hipStream_t (NULL = the null stream).  Calls are
+ *     stream-ordered and asynchronous; the return code reports argument and
+ *     launch errors only.  A device fault shows at the caller's next
+ *     synchronisation, as in HIP.
+ *   - Errors: every function returns an int, JR_OK (0) on success or a
+ *     negative JR_E* code; jr_strerror() names it and jr_last_error_message()
+ *     gives the detail of the last failure on the calling thread.  Arguments
+ *     are validated before any HIP call, so an invalid call touches no device.
+ *   - Thread safety: calls may come from several host threads.  Work on one
+ *     stream is ordered; calls on different streams use separate workspaces.
+ */
+#ifndef JULIA_H
+#define JULIA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    JR_OK = 0,
+    JR_EINVAL = -1,    /* an argument is out of range, non-finite or null  */
+    JR_ENOMEM = -2,    /* device or pinned-host allocation failed          */
+    JR_ENODEV = -3,    /* no usable gfx950 device                          */
+    JR_ELAUNCH = -4,   /* a HIP launch, copy or graph call failed          */
+    JR_EINTERNAL = -5  /* broken invariant inside the library              */
+};
+
+typedef enum { JR_FP64 = 0, JR_FP32 = 1, JR_FF = 2 } jr_dtype;
+typedef enum { JR_JULIA = 0, JR_MANDELBROT = 1 } jr_mode;
+typedef enum { JR_ORDER_TABLE = 0, JR_ORDER_COST = 1 } jr_order;
+
+typedef struct { double re, im; } jr_complex;
+/* Window of the complex plane: re_min < re_max, im_min < im_max, finite. */
+typedef struct { double re_min, re_max, im_min, im_max; } jr_window;
+
+/*
+ * One image of a batch.  The image occupies width*height consecutive int32
+ * elements of the output arena starting at element out_offset; only rows
+ * [row_begin, row_end) are computed by this call (row_end = 0 means height),
+ * so a large frame can be split over several calls.  `c` is ignored in
+ * Mandelbrot mode.  Limits: width, height >= 1, width*height < 2^31,
+ * 0 <= max_iter < 2^31, out_offset >= 0, out_offset + width*height <=
+ * out_capacity.
+ */
+typedef struct {
+    jr_complex c;
+    jr_window w;
+    int32_t width, height;
+    int32_t max_iter;
+    int32_t dtype;      /* jr_dtype */
+    int32_t mode;       /* jr_mode  */
+    int32_t row_begin;  /* first row computed (0 = top)        */
+    int32_t row_end;    /* one past the last row; 0 = height   */
+    int32_t reserved;   /* must be 0                           */
+    int64_t out_offset; /* element offset of pixel (0, 0)      */
+} jr_frame;
+
+/*
+ * Schedule of the persistent kernel.  None of these fields changes a count:
+ * they decide which lane computes which pixel and when, never the arithmetic.
+ *   tile_w, tile_h  pixels per work tile claimed from the global tile
+ *                   counter: 1 <= tile_w <= 4096, 1 <= tile_h, and
+ *                   tile_w * tile_h <= 65536.
+ *   unroll          iterations between two escape tests: 1, 4, 8 or 16.
+ *                   With unroll > 1 a lane that escaped inside the block is
+ *                   replayed from its saved state, so counts are unchanged;
+ *                   frames where escape is not known to be absorbing
+ *                   (|C| > 1.9 somewhere) always run with 1.
+ *   refill          idle lanes in a wave that trigger a refill round, 1..64:
+ *                   finished lanes store their count and take the tile's next
+ *                   pixels.
+ *   waves_per_cu    resident waves per compute unit the grid is sized for
+ *                   (4..32, a multiple of 4).
+ *   order           JR_ORDER_TABLE: frames in the order given;
+ *                   JR_ORDER_COST: most expensive frames first (estimated
+ *                   from size, cap and dtype).
+ */
+typedef struct {
+    int32_t tile_w, tile_h;
+    int32_t unroll;
+    int32_t refill;
+    int32_t waves_per_cu;
+    int32_t order;
+} jr_schedule;
+
+/*
+ * Render one Julia image (Section 2) with the tuned persistent kernel.
+ * out: device, width*height int32, row-major.  The schedule is the library's
+ * default for (dtype, max_iter) (see jr_set_default_schedule).
+ */
+int julia_render(jr_complex c, jr_window w, int32_t width, int32_t height,
+                 int32_t max_iter, int32_t dtype, int32_t *out, void *stream);
+
+/*
+ * Same image and the same counts with the plain kernel: one thread per pixel
+ * on a 2-D grid of 16x16 workgroups, escape test on every iteration.  The
+ * comparator the tuned kernels are measured against.
+ */
+int julia_render_plain(jr_complex c, jr_window w, int32_t width, int32_t height,
+                       int32_t max_iter, int32_t dtype, int32_t *out, void *stream);
+
+/* Mandelbrot image (Section 3: C = pixel, Z_0 = 0), tuned and plain kernels. */
+int mandelbrot_render(jr_window w, int32_t width, int32_t height, int32_t max_iter,
+                      int32_t dtype, int32_t *out, void *stream);
+int mandelbrot_render_plain(jr_window w, int32_t width, int32_t height,
+                            int32_t max_iter, int32_t dtype, int32_t *out,
+                            void *stream);
+
+/*
+ * Render n frames (any mix of sizes, caps, dtypes and modes) in ONE launch of
+ * the persistent work-stealing kernel.  frames: host array of n >= 1
+ * descriptors, copied before return.  out_base: device arena of out_capacity
+ * int32 elements holding every frame at its out_offset.  sched: NULL for the
+ * default schedule of the batch's dominant dtype.  Frames must not overlap in
+ * the arena where their computed rows overlap.
+ */
+int julia_render_batch(const jr_frame *frames, int32_t n, int32_t *out_base,
+                       int64_t out_capacity, const jr_schedule *sched, void *stream);
+
+/*
+ * Prepared batch: validates and uploads the frame table once (synchronously),
+ * so that repeated launches or a captured hipGraph replay cost one kernel
+ * launch.  A plan's launches must not overlap each other (they share the
+ * plan's tile counter); run them on one stream or order them.
+ */
+typedef struct jr_plan jr_plan;
+int jr_plan_create(const jr_frame *frames, int32_t n, int32_t *out_base,
+                   int64_t out_capacity, const jr_schedule *sched, jr_plan **plan);
+int jr_plan_launch(jr_plan *plan, void *stream);
+/* Capture one launch into a hipGraph on `stream` (once), then replay it. */
+int jr_plan_capture(jr_plan *plan, void *stream);
+int jr_plan_replay(jr_plan *plan, void *stream);
+/* Number of tiles of the plan and the grid it launches (for accounting). */
+int jr_plan_info(const jr_plan *plan, int64_t *tiles, int32_t *workgroups);
+void jr_plan_destroy(jr_plan *plan);
+
+/* Library default schedule per dtype, used when sched is NULL. */
+int jr_get_default_schedule(int32_t dtype, int32_t max_iter, jr_schedule *out);
+int jr_set_default_schedule(int32_t dtype, const jr_schedule *sched);
+
+/* Validate a schedule or a frame table without touching the device. */
+int jr_check_schedule(const jr_schedule *sched);
+int jr_check_frames(const jr_frame *frames, int32_t n, int64_t out_capacity);
+
+const char *jr_strerror(int code);
+const char *jr_last_error_message(void);
+
+/* Compute units and HBM bytes of the current device (for admission control). */
+int jr_device_info(int32_t *num_cus, int64_t *hbm_bytes);
+
+/* Free the library's per-stream workspaces (frame tables, counters, staging).
+ * No call may be in flight. */
+void jr_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JULIA_H */

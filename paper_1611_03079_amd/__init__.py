@@ -1,0 +1,307 @@
+"""Python binding of libjulia.so: escape-time Julia / Mandelbrot counts on MI355X.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``csrc/``; torch supplies device memory and streams.  The library
+must be built (``python -m paper_1611_03079_amd.build``); importing this module
+without it raises, and nothing here falls back to a CPU path.
+
+Method: Mayfield et al., Section 2 (iterate Z^2 + C from pixels scaled onto a
+window, count iterations until |Z|^2 > 4, capped) and Section 3 (Mandelbrot
+variant).  Conventions are those of ``include/julia.h``.
+"""
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence, Tuple
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libjulia.so")
+
+JR_OK, JR_EINVAL, JR_ENOMEM, JR_ENODEV, JR_ELAUNCH, JR_EINTERNAL = 0, -1, -2, -3, -4, -5
+DTYPES = {"fp64": 0, "fp32": 1, "ff": 2}
+MODES = {"julia": 0, "mandelbrot": 1}
+ORDERS = {"table": 0, "cost": 1}
+
+
+class JuliaError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__("%s (%d): %s" % (_strerror(code), code, message))
+        self.code = code
+
+
+class jr_complex(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+class jr_window(ctypes.Structure):
+    _fields_ = [("re_min", ctypes.c_double), ("re_max", ctypes.c_double),
+                ("im_min", ctypes.c_double), ("im_max", ctypes.c_double)]
+
+
+class jr_frame(ctypes.Structure):
+    _fields_ = [("c", jr_complex), ("w", jr_window),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("row_begin", ctypes.c_int32),
+                ("row_end", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("out_offset", ctypes.c_int64)]
+
+
+class jr_schedule(ctypes.Structure):
+    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
+                ("unroll", ctypes.c_int32), ("refill", ctypes.c_int32),
+                ("waves_per_cu", ctypes.c_int32), ("order", ctypes.c_int32)]
+
+
+assert ctypes.sizeof(jr_frame) == 88
+
+
+@dataclass(frozen=True)
+class Schedule:
+    """Schedule of the persistent kernel (see include/julia.h); never changes counts."""
+    tile_w: int = 64
+    tile_h: int = 16
+    unroll: int = 4
+    refill: int = 16
+    waves_per_cu: int = 16
+    order: str = "cost"
+
+    def to_c(self) -> jr_schedule:
+        return jr_schedule(self.tile_w, self.tile_h, self.unroll, self.refill,
+                           self.waves_per_cu, ORDERS[self.order])
+
+    @staticmethod
+    def from_c(s: jr_schedule) -> "Schedule":
+        inv = {v: k for k, v in ORDERS.items()}
+        return Schedule(s.tile_w, s.tile_h, s.unroll, s.refill, s.waves_per_cu, inv[s.order])
+
+
+EXPORTS = (
+    "julia_render", "julia_render_plain", "mandelbrot_render", "mandelbrot_render_plain",
+    "julia_render_batch", "jr_plan_create", "jr_plan_launch", "jr_plan_capture",
+    "jr_plan_replay", "jr_plan_info", "jr_plan_destroy", "jr_get_default_schedule",
+    "jr_set_default_schedule", "jr_check_schedule", "jr_check_frames", "jr_strerror",
+    "jr_last_error_message", "jr_device_info", "jr_shutdown",
+)
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libjulia.so is not built (%s); run python -m paper_1611_03079_amd.build"
+                          % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    i32, i64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    P = ctypes.POINTER
+    img = [jr_complex, jr_window, i32, i32, i32, i32, vp, vp]
+    for name in ("julia_render", "julia_render_plain"):
+        getattr(lib, name).argtypes = img
+        getattr(lib, name).restype = ctypes.c_int
+    for name in ("mandelbrot_render", "mandelbrot_render_plain"):
+        getattr(lib, name).argtypes = img[1:]
+        getattr(lib, name).restype = ctypes.c_int
+    lib.julia_render_batch.argtypes = [P(jr_frame), i32, vp, i64, P(jr_schedule), vp]
+    lib.julia_render_batch.restype = ctypes.c_int
+    lib.jr_plan_create.argtypes = [P(jr_frame), i32, vp, i64, P(jr_schedule), P(vp)]
+    lib.jr_plan_create.restype = ctypes.c_int
+    for name in ("jr_plan_launch", "jr_plan_capture", "jr_plan_replay"):
+        getattr(lib, name).argtypes = [vp, vp]
+        getattr(lib, name).restype = ctypes.c_int
+    lib.jr_plan_info.argtypes = [vp, P(i64), P(i32)]
+    lib.jr_plan_info.restype = ctypes.c_int
+    lib.jr_plan_destroy.argtypes = [vp]
+    lib.jr_plan_destroy.restype = None
+    lib.jr_get_default_schedule.argtypes = [i32, i32, P(jr_schedule)]
+    lib.jr_get_default_schedule.restype = ctypes.c_int
+    lib.jr_set_default_schedule.argtypes = [i32, P(jr_schedule)]
+    lib.jr_set_default_schedule.restype = ctypes.c_int
+    lib.jr_check_schedule.argtypes = [P(jr_schedule)]
+    lib.jr_check_schedule.restype = ctypes.c_int
+    lib.jr_check_frames.argtypes = [P(jr_frame), i32, i64]
+    lib.jr_check_frames.restype = ctypes.c_int
+    lib.jr_strerror.argtypes = [ctypes.c_int]
+    lib.jr_strerror.restype = ctypes.c_char_p
+    lib.jr_last_error_message.argtypes = []
+    lib.jr_last_error_message.restype = ctypes.c_char_p
+    lib.jr_device_info.argtypes = [P(i32), P(i64)]
+    lib.jr_device_info.restype = ctypes.c_int
+    lib.jr_shutdown.argtypes = []
+    lib.jr_shutdown.restype = None
+    return lib
+
+
+lib = _load()
+
+
+def _strerror(code: int) -> str:
+    return lib.jr_strerror(code).decode()
+
+
+def _check(rc: int):
+    if rc != JR_OK:
+        raise JuliaError(rc, lib.jr_last_error_message().decode())
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _window(window) -> jr_window:
+    return jr_window(*[float(v) for v in window])
+
+
+def _out_tensor(out, shape):
+    import torch
+    if out is None:
+        return torch.empty(shape, dtype=torch.int32, device="cuda")
+    if out.dtype != torch.int32 or not out.is_cuda or not out.is_contiguous():
+        raise ValueError("out must be a contiguous int32 CUDA tensor")
+    if out.numel() < shape[0] * shape[1]:
+        raise ValueError("out holds %d elements, need %d" % (out.numel(), shape[0] * shape[1]))
+    return out
+
+
+def render(c, window, width: int, height: int, max_iter: int, dtype: str = "fp64",
+           out=None, stream=None, mode: str = "julia", plain: bool = False):
+    """Counts of one image as an int32 (height, width) CUDA tensor (row 0 = im_max).
+
+    ``plain=True`` uses the one-thread-per-pixel comparator kernel.
+    """
+    out = _out_tensor(out, (height, width))
+    st = _stream_ptr(stream)
+    dt = DTYPES[dtype]
+    if mode == "julia":
+        c = complex(c)
+        fn = lib.julia_render_plain if plain else lib.julia_render
+        rc = fn(jr_complex(c.real, c.imag), _window(window), width, height, max_iter, dt,
+                ctypes.c_void_p(out.data_ptr()), st)
+    elif mode == "mandelbrot":
+        fn = lib.mandelbrot_render_plain if plain else lib.mandelbrot_render
+        rc = fn(_window(window), width, height, max_iter, dt, ctypes.c_void_p(out.data_ptr()), st)
+    else:
+        raise ValueError("mode must be 'julia' or 'mandelbrot'")
+    _check(rc)
+    return out.view(-1)[: width * height].view(height, width)
+
+
+def _frames_array(frames, offsets, rows=None):
+    arr = (jr_frame * len(frames))()
+    for k, f in enumerate(frames):
+        c = complex(f.c)
+        rb, re_ = (0, 0) if rows is None else rows[k]
+        arr[k] = jr_frame(jr_complex(c.real, c.imag), _window(f.window), f.width, f.height,
+                          f.max_iter, DTYPES[f.dtype], MODES[getattr(f, "mode", "julia")],
+                          rb, re_, 0, int(offsets[k]))
+    return arr
+
+
+def arena_layout(frames) -> Tuple[list, int]:
+    """Element offsets of consecutive frames in one arena, and its size."""
+    offs, total = [], 0
+    for f in frames:
+        offs.append(total)
+        total += f.width * f.height
+    return offs, total
+
+
+def render_batch(frames: Sequence, schedule: Optional[Schedule] = None, arena=None,
+                 offsets=None, stream=None, rows=None):
+    """Render frames (objects with c, window, width, height, max_iter, dtype, mode)
+    in one persistent launch.  Returns (arena, views): views[k] is frame k's
+    (height, width) counts inside the int32 arena."""
+    import torch
+    if offsets is None:
+        offsets, total = arena_layout(frames)
+    else:
+        total = max(int(o) + f.width * f.height for o, f in zip(offsets, frames))
+    if arena is None:
+        arena = torch.empty(total, dtype=torch.int32, device="cuda")
+    arr = _frames_array(frames, offsets, rows)
+    sched = ctypes.byref(schedule.to_c()) if schedule is not None else None
+    rc = lib.julia_render_batch(arr, len(frames), ctypes.c_void_p(arena.data_ptr()),
+                                arena.numel(), sched, _stream_ptr(stream))
+    _check(rc)
+    views = [arena[o: o + f.width * f.height].view(f.height, f.width)
+             for o, f in zip(offsets, frames)]
+    return arena, views
+
+
+class Plan:
+    """A prepared batch: frame table uploaded once; launch() or a captured hipGraph."""
+
+    def __init__(self, frames: Sequence, schedule: Optional[Schedule] = None, arena=None,
+                 offsets=None):
+        import torch
+        if offsets is None:
+            offsets, total = arena_layout(frames)
+        else:
+            total = max(int(o) + f.width * f.height for o, f in zip(offsets, frames))
+        self.arena = arena if arena is not None else torch.empty(total, dtype=torch.int32,
+                                                                 device="cuda")
+        self.frames = list(frames)
+        self.offsets = list(offsets)
+        arr = _frames_array(frames, offsets)
+        sched = ctypes.byref(schedule.to_c()) if schedule is not None else None
+        h = ctypes.c_void_p()
+        _check(lib.jr_plan_create(arr, len(frames), ctypes.c_void_p(self.arena.data_ptr()),
+                                  self.arena.numel(), sched, ctypes.byref(h)))
+        self._h = h
+        self.views = [self.arena[o: o + f.width * f.height].view(f.height, f.width)
+                      for o, f in zip(self.offsets, self.frames)]
+
+    def launch(self, stream=None):
+        _check(lib.jr_plan_launch(self._h, _stream_ptr(stream)))
+
+    def capture(self, stream=None):
+        _check(lib.jr_plan_capture(self._h, ctypes.c_void_p(0) if stream is None
+                                   else _stream_ptr(stream)))
+
+    def replay(self, stream=None):
+        _check(lib.jr_plan_replay(self._h, _stream_ptr(stream)))
+
+    def info(self):
+        t, w = ctypes.c_int64(), ctypes.c_int32()
+        _check(lib.jr_plan_info(self._h, ctypes.byref(t), ctypes.byref(w)))
+        return {"tiles": t.value, "workgroups": w.value}
+
+    def close(self):
+        if self._h:
+            lib.jr_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def default_schedule(dtype: str, max_iter: int = 100) -> Schedule:
+    s = jr_schedule()
+    _check(lib.jr_get_default_schedule(DTYPES[dtype], max_iter, ctypes.byref(s)))
+    return Schedule.from_c(s)
+
+
+def set_default_schedule(dtype: str, schedule: Schedule):
+    _check(lib.jr_set_default_schedule(DTYPES[dtype], ctypes.byref(schedule.to_c())))
+
+
+def check_schedule(schedule: Schedule) -> int:
+    return lib.jr_check_schedule(ctypes.byref(schedule.to_c()))
+
+
+def check_frames(frames, offsets, capacity: int, rows=None) -> int:
+    arr = _frames_array(frames, offsets, rows)
+    return lib.jr_check_frames(arr, len(frames), capacity)
+
+
+def device_info():
+    n, m = ctypes.c_int32(), ctypes.c_int64()
+    _check(lib.jr_device_info(ctypes.byref(n), ctypes.byref(m)))
+    return {"num_cus": n.value, "hbm_bytes": m.value}
+
+
+def last_error() -> str:
+    return lib.jr_last_error_message().decode()

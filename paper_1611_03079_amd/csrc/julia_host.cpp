@@ -1,0 +1,636 @@
+// julia_host.cpp -- host runtime and C ABI of libjulia.so (see include/julia.h).
+//
+// Frame setup (pixel-centre mapping scalars in binary64), argument validation,
+// per-(device, stream) workspaces with a pinned staging ring for the frame
+// table, the self-resetting tile counter of the persistent kernel, prepared
+// plans and their hipGraph capture.  Compiled with -ffp-contract=off so that
+// the mapping scalars are the same rounded expressions on every build.
+
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "julia.h"
+#include "julia_device.h"
+
+using jr::DevFrame;
+
+namespace {
+
+thread_local std::string g_last_msg;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_msg = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    int code = (e == hipErrorOutOfMemory) ? JR_ENOMEM
+               : (e == hipErrorNoDevice || e == hipErrorInvalidDevice) ? JR_ENODEV
+                                                                      : JR_ELAUNCH;
+    return fail(code, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                          \
+    do {                                             \
+        hipError_t e_ = (expr);                      \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+// Escape is absorbing when |C| <= 1.9: |Z| > 2 gives |Z^2 + C| >= |Z|^2 - |C|
+// > 4 - 1.9 > 2, with a margin far above rounding in every formulation.
+constexpr double kAbsorbingC = 1.9;
+constexpr int32_t kMaxFrames = 1 << 22;
+
+// ------------------------------------------------------------- validation
+bool finite(double v) { return std::isfinite(v); }
+
+int check_window(const jr_window& w, const char* who) {
+    if (!finite(w.re_min) || !finite(w.re_max) || !finite(w.im_min) || !finite(w.im_max))
+        return fail(JR_EINVAL, "%s: window bounds must be finite", who);
+    if (!(w.re_min < w.re_max) || !(w.im_min < w.im_max))
+        return fail(JR_EINVAL, "%s: window needs re_min < re_max and im_min < im_max", who);
+    if (!finite(w.re_max - w.re_min) || !finite(w.im_max - w.im_min))
+        return fail(JR_EINVAL, "%s: window extent overflows binary64", who);
+    return JR_OK;
+}
+
+int check_image(int32_t W, int32_t H, int32_t max_iter, int32_t dtype, int32_t mode,
+                const jr_complex& c, const jr_window& w, const char* who) {
+    if (W < 1 || H < 1)
+        return fail(JR_EINVAL, "%s: width and height must be >= 1 (got %d x %d)", who, W, H);
+    if ((int64_t)W * (int64_t)H > (int64_t)INT32_MAX)
+        return fail(JR_EINVAL, "%s: width*height must be < 2^31", who);
+    if (max_iter < 0) return fail(JR_EINVAL, "%s: max_iter must be >= 0", who);
+    if (dtype != JR_FP64 && dtype != JR_FP32 && dtype != JR_FF)
+        return fail(JR_EINVAL, "%s: unknown dtype %d", who, dtype);
+    if (mode != JR_JULIA && mode != JR_MANDELBROT)
+        return fail(JR_EINVAL, "%s: unknown mode %d", who, mode);
+    if (mode == JR_JULIA && (!finite(c.re) || !finite(c.im)))
+        return fail(JR_EINVAL, "%s: C must be finite", who);
+    return check_window(w, who);
+}
+
+int check_out(const void* p, const char* who) {
+    if (p == nullptr) return fail(JR_EINVAL, "%s: output pointer is null", who);
+    if (((uintptr_t)p & 3u) != 0) return fail(JR_EINVAL, "%s: output pointer not 4-byte aligned", who);
+    return JR_OK;
+}
+
+int check_schedule(const jr_schedule& s) {
+    if (s.tile_w < 1 || s.tile_w > 4096 || s.tile_h < 1 || (int64_t)s.tile_w * s.tile_h > 65536)
+        return fail(JR_EINVAL, "schedule: tile %d x %d out of range", s.tile_w, s.tile_h);
+    if (s.unroll != 1 && s.unroll != 4 && s.unroll != 8 && s.unroll != 16)
+        return fail(JR_EINVAL, "schedule: unroll must be 1, 4, 8 or 16 (got %d)", s.unroll);
+    if (s.refill < 1 || s.refill > 64)
+        return fail(JR_EINVAL, "schedule: refill must be in 1..64 (got %d)", s.refill);
+    if (s.waves_per_cu < 4 || s.waves_per_cu > 32 || (s.waves_per_cu % 4) != 0)
+        return fail(JR_EINVAL, "schedule: waves_per_cu must be 4..32, a multiple of 4");
+    if (s.order != JR_ORDER_TABLE && s.order != JR_ORDER_COST)
+        return fail(JR_EINVAL, "schedule: unknown order %d", s.order);
+    return JR_OK;
+}
+
+int check_frames(const jr_frame* frames, int32_t n, int64_t capacity) {
+    if (frames == nullptr) return fail(JR_EINVAL, "batch: frames is null");
+    if (n < 1 || n > kMaxFrames) return fail(JR_EINVAL, "batch: n must be in 1..%d", kMaxFrames);
+    if (capacity < 0) return fail(JR_EINVAL, "batch: out_capacity must be >= 0");
+    for (int32_t k = 0; k < n; ++k) {
+        const jr_frame& f = frames[k];
+        char who[48];
+        snprintf(who, sizeof who, "frame %d", k);
+        int rc = check_image(f.width, f.height, f.max_iter, f.dtype, f.mode, f.c, f.w, who);
+        if (rc) return rc;
+        const int32_t rend = f.row_end == 0 ? f.height : f.row_end;
+        if (f.row_begin < 0 || rend > f.height || f.row_begin >= rend)
+            return fail(JR_EINVAL, "%s: rows [%d, %d) outside [0, %d)", who, f.row_begin, rend, f.height);
+        if (f.reserved != 0) return fail(JR_EINVAL, "%s: reserved must be 0", who);
+        if (f.out_offset < 0) return fail(JR_EINVAL, "%s: out_offset must be >= 0", who);
+        const int64_t px = (int64_t)f.width * f.height;
+        if (f.out_offset > capacity - px)
+            return fail(JR_EINVAL, "%s: out_offset + width*height exceeds out_capacity", who);
+    }
+    return JR_OK;
+}
+
+// ------------------------------------------------------------- schedules
+std::mutex g_sched_mu;
+// Defaults per dtype; the autotuner can replace them (jr_set_default_schedule).
+jr_schedule g_default[3] = {
+    {64, 16, 8, 16, 16, JR_ORDER_COST},  // FP64
+    {64, 16, 4, 16, 16, JR_ORDER_COST},  // FP32
+    {64, 8, 4, 16, 16, JR_ORDER_COST},   // FF
+};
+
+jr_schedule default_schedule(int dtype) {
+    std::lock_guard<std::mutex> g(g_sched_mu);
+    return g_default[dtype];
+}
+
+// ------------------------------------------------------------- frame table
+double dtype_cost(int dtype) {
+    // Relative cost of one pixel-iteration (vector-ALU instructions).
+    return dtype == JR_FF ? 20.0 : dtype == JR_FP64 ? 1.75 : 1.0;
+}
+
+double frame_cost(const jr_frame& f) {
+    const int32_t rend = f.row_end == 0 ? f.height : f.row_end;
+    const double px = (double)f.width * (double)(rend - f.row_begin);
+    return px * (4.0 + std::min<double>(f.max_iter, 256.0)) * dtype_cost(f.dtype);
+}
+
+bool absorbing(const jr_frame& f) {
+    if (f.mode == JR_JULIA) return std::hypot(f.c.re, f.c.im) <= kAbsorbingC;
+    // Mandelbrot: C ranges over the window; its largest modulus is at a corner.
+    const double xs[2] = {f.w.re_min, f.w.re_max}, ys[2] = {f.w.im_min, f.w.im_max};
+    double m = 0.0;
+    for (double x : xs)
+        for (double y : ys) m = std::max(m, std::hypot(x, y));
+    return m <= kAbsorbingC;
+}
+
+struct Table {
+    std::vector<DevFrame> rows;
+    int64_t total_tiles = 0;
+    int dtmask = 0;
+};
+
+void build_table(const jr_frame* frames, int32_t n, const jr_schedule& s, Table& t) {
+    std::vector<int32_t> idx(n);
+    std::iota(idx.begin(), idx.end(), 0);
+    if (s.order == JR_ORDER_COST)
+        std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) {
+            return frame_cost(frames[a]) > frame_cost(frames[b]);
+        });
+    t.rows.resize(n);
+    t.total_tiles = 0;
+    t.dtmask = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        const jr_frame& f = frames[idx[k]];
+        DevFrame& d = t.rows[k];
+        std::memset(&d, 0, sizeof d);
+        const double W = (double)f.width, H = (double)f.height;
+        d.hx = (f.w.re_max - f.w.re_min) / (2.0 * W);
+        d.hy = (f.w.im_max - f.w.im_min) / (2.0 * H);
+        d.cx = 0.5 * (f.w.re_min + f.w.re_max);
+        d.cy = 0.5 * (f.w.im_min + f.w.im_max);
+        d.cr = f.mode == JR_JULIA ? f.c.re : 0.0;
+        d.ci = f.mode == JR_JULIA ? f.c.im : 0.0;
+        d.out_offset = f.out_offset;
+        d.width = f.width;
+        d.height = f.height;
+        d.max_iter = f.max_iter;
+        d.dtype = f.dtype;
+        d.mode = f.mode;
+        d.defer = (s.unroll > 1 && absorbing(f)) ? 1 : 0;
+        d.row_begin = f.row_begin;
+        d.row_end = f.row_end == 0 ? f.height : f.row_end;
+        d.tile_w = std::min(s.tile_w, f.width);
+        d.tile_h = s.tile_h;
+        d.tiles_x = (f.width + d.tile_w - 1) / d.tile_w;
+        const int64_t tiles_y = (d.row_end - d.row_begin + d.tile_h - 1) / d.tile_h;
+        d.tile_begin = t.total_tiles;
+        t.total_tiles += (int64_t)d.tiles_x * tiles_y;
+        // Tiles per atomic claim: several cheap tiles at once, one expensive.
+        const double tile_cost = (double)d.tile_w * d.tile_h *
+                                 (4.0 + std::min<double>(f.max_iter, 64.0)) * dtype_cost(f.dtype);
+        d.claim = (int32_t)std::max(1.0, std::min(16.0, std::floor(262144.0 / tile_cost)));
+        t.dtmask |= 1 << f.dtype;
+    }
+}
+
+// ------------------------------------------------------------- devices
+struct DeviceInfo {
+    bool probed = false;
+    int rc = JR_OK;
+    int num_cus = 0;
+    int64_t hbm = 0;
+};
+std::mutex g_dev_mu;
+std::map<int, DeviceInfo> g_dev;
+
+int current_device(int* dev, DeviceInfo* info) {
+    hipError_t e = hipGetDevice(dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> g(g_dev_mu);
+    DeviceInfo& d = g_dev[*dev];
+    if (!d.probed) {
+        d.probed = true;
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, *dev);
+        if (e != hipSuccess) {
+            d.rc = hip_fail(e, "hipGetDeviceProperties");
+        } else if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+            d.rc = fail(JR_ENODEV, "device %d is %s; libjulia.so is built for gfx950 only",
+                        *dev, prop.gcnArchName);
+        } else {
+            d.num_cus = prop.multiProcessorCount;
+            d.hbm = (int64_t)prop.totalGlobalMem;
+        }
+    }
+    if (d.rc != JR_OK) return fail(d.rc, "device %d unusable", *dev);
+    *info = d;
+    return JR_OK;
+}
+
+// ------------------------------------------------------------- workspaces
+constexpr int kStages = 4;
+
+struct Workspace {
+    std::mutex mu;
+    DevFrame* d_table = nullptr;
+    size_t table_cap = 0;
+    unsigned long long* d_ctr = nullptr;
+    DevFrame* h_stage[kStages] = {};
+    size_t stage_cap[kStages] = {};
+    hipEvent_t ev[kStages] = {};
+    bool ev_used[kStages] = {};
+    int slot = 0;
+};
+
+std::mutex g_ws_mu;
+std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
+
+int get_workspace(int dev, hipStream_t stream, Workspace** out) {
+    std::lock_guard<std::mutex> g(g_ws_mu);
+    auto key = std::make_pair(dev, stream);
+    auto it = g_ws.find(key);
+    if (it != g_ws.end()) {
+        *out = it->second;
+        return JR_OK;
+    }
+    Workspace* ws = new Workspace();
+    hipError_t e = hipMalloc((void**)&ws->d_ctr, 2 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemset(ws->d_ctr, 0, 2 * sizeof(unsigned long long));
+    for (int k = 0; k < kStages && e == hipSuccess; ++k)
+        e = hipEventCreateWithFlags(&ws->ev[k], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        if (ws->d_ctr) (void)hipFree(ws->d_ctr);
+        for (int k = 0; k < kStages; ++k)
+            if (ws->ev[k]) (void)hipEventDestroy(ws->ev[k]);
+        delete ws;
+        return hip_fail(e, "workspace setup");
+    }
+    g_ws[key] = ws;
+    *out = ws;
+    return JR_OK;
+}
+
+int grid_blocks(const DeviceInfo& info, const jr_schedule& s, int64_t total_tiles) {
+    int64_t blocks = (int64_t)info.num_cus * (s.waves_per_cu / 4);
+    // No more waves than tiles: extra waves would only claim and leave.
+    const int64_t need = (total_tiles + 3) / 4;
+    blocks = std::max<int64_t>(1, std::min(blocks, need));
+    return (int)blocks;
+}
+
+int enqueue_batch(const jr_frame* frames, int32_t n, int32_t* out_base, int64_t capacity,
+                  const jr_schedule* sched, hipStream_t stream) {
+    int rc = check_frames(frames, n, capacity);
+    if (rc) return rc;
+    if ((rc = check_out(out_base, "batch"))) return rc;
+    jr_schedule s;
+    if (sched) {
+        s = *sched;
+        if ((rc = check_schedule(s))) return rc;
+    } else {
+        // default of the dtype with the most estimated work
+        double w[3] = {0, 0, 0};
+        for (int32_t k = 0; k < n; ++k) w[frames[k].dtype] += frame_cost(frames[k]);
+        s = default_schedule((int)(std::max_element(w, w + 3) - w));
+    }
+    int dev;
+    DeviceInfo info;
+    if ((rc = current_device(&dev, &info))) return rc;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(stream, &cap), "hipStreamIsCapturing");
+    if (cap != hipStreamCaptureStatusNone)
+        return fail(JR_EINVAL, "batch: stream is being captured; use jr_plan_capture for graphs");
+
+    Table t;
+    build_table(frames, n, s, t);
+    Workspace* ws;
+    if ((rc = get_workspace(dev, stream, &ws))) return rc;
+    std::lock_guard<std::mutex> g(ws->mu);
+    const size_t bytes = (size_t)n * sizeof(DevFrame);
+    if (ws->table_cap < bytes) {
+        // The old table may still be read by work queued on this stream.
+        HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+        if (ws->d_table) HIP_TRY(hipFree(ws->d_table), "hipFree");
+        ws->d_table = nullptr;
+        ws->table_cap = 0;
+        size_t cap_bytes = std::max<size_t>(bytes, 64 * sizeof(DevFrame));
+        HIP_TRY(hipMalloc((void**)&ws->d_table, cap_bytes), "hipMalloc frame table");
+        ws->table_cap = cap_bytes;
+    }
+    const int k = ws->slot;
+    ws->slot = (ws->slot + 1) % kStages;
+    if (ws->ev_used[k]) HIP_TRY(hipEventSynchronize(ws->ev[k]), "hipEventSynchronize");
+    if (ws->stage_cap[k] < bytes) {
+        if (ws->h_stage[k]) HIP_TRY(hipHostFree(ws->h_stage[k]), "hipHostFree");
+        ws->h_stage[k] = nullptr;
+        ws->stage_cap[k] = 0;
+        size_t cap_bytes = std::max<size_t>(bytes, 64 * sizeof(DevFrame));
+        HIP_TRY(hipHostMalloc((void**)&ws->h_stage[k], cap_bytes, hipHostMallocDefault),
+                "hipHostMalloc staging");
+        ws->stage_cap[k] = cap_bytes;
+    }
+    std::memcpy(ws->h_stage[k], t.rows.data(), bytes);
+    HIP_TRY(hipMemcpyAsync(ws->d_table, ws->h_stage[k], bytes, hipMemcpyHostToDevice, stream),
+            "hipMemcpyAsync frame table");
+    HIP_TRY(hipEventRecord(ws->ev[k], stream), "hipEventRecord");
+    ws->ev_used[k] = true;
+    const int blocks = grid_blocks(info, s, t.total_tiles);
+    hipError_t e = jr::launch_persistent(s.unroll, t.dtmask, blocks, ws->d_table, n,
+                                         t.total_tiles, out_base, ws->d_ctr, s.refill, stream);
+    if (e != hipSuccess) return hip_fail(e, "persistent kernel launch");
+    return JR_OK;
+}
+
+jr_frame single_frame(jr_complex c, jr_window w, int32_t W, int32_t H, int32_t max_iter,
+                      int32_t dtype, int32_t mode) {
+    jr_frame f;
+    std::memset(&f, 0, sizeof f);
+    f.c = c;
+    f.w = w;
+    f.width = W;
+    f.height = H;
+    f.max_iter = max_iter;
+    f.dtype = dtype;
+    f.mode = mode;
+    return f;
+}
+
+int render_one(jr_complex c, jr_window w, int32_t W, int32_t H, int32_t max_iter, int32_t dtype,
+               int32_t mode, int32_t* out, void* stream, const char* who) {
+    int rc = check_image(W, H, max_iter, dtype, mode, c, w, who);
+    if (rc) return rc;
+    if ((rc = check_out(out, who))) return rc;
+    jr_frame f = single_frame(c, w, W, H, max_iter, dtype, mode);
+    jr_schedule s = default_schedule(dtype);
+    return enqueue_batch(&f, 1, out, (int64_t)W * H, &s, (hipStream_t)stream);
+}
+
+int render_plain(jr_complex c, jr_window w, int32_t W, int32_t H, int32_t max_iter,
+                 int32_t dtype, int32_t mode, int32_t* out, void* stream, const char* who) {
+    int rc = check_image(W, H, max_iter, dtype, mode, c, w, who);
+    if (rc) return rc;
+    if ((rc = check_out(out, who))) return rc;
+    int dev;
+    DeviceInfo info;
+    if ((rc = current_device(&dev, &info))) return rc;
+    jr::PlainArgs a;
+    a.out = out;
+    a.hx = (w.re_max - w.re_min) / (2.0 * (double)W);
+    a.hy = (w.im_max - w.im_min) / (2.0 * (double)H);
+    a.cx = 0.5 * (w.re_min + w.re_max);
+    a.cy = 0.5 * (w.im_min + w.im_max);
+    a.cr = mode == JR_JULIA ? c.re : 0.0;
+    a.ci = mode == JR_JULIA ? c.im : 0.0;
+    a.W = W;
+    a.H = H;
+    a.max_iter = max_iter;
+    a.mode = mode;
+    hipError_t e = jr::launch_plain(dtype, a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "plain kernel launch");
+    return JR_OK;
+}
+
+}  // namespace
+
+// ======================================================================== C ABI
+struct jr_plan {
+    int dev = 0;
+    DevFrame* d_table = nullptr;
+    unsigned long long* d_ctr = nullptr;
+    int32_t n = 0;
+    int64_t total_tiles = 0;
+    int dtmask = 0;
+    int unroll = 1, refill = 1, blocks = 1;
+    int32_t* out = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+const char* jr_strerror(int code) {
+    switch (code) {
+        case JR_OK: return "success";
+        case JR_EINVAL: return "invalid argument";
+        case JR_ENOMEM: return "out of memory";
+        case JR_ENODEV: return "no usable gfx950 device";
+        case JR_ELAUNCH: return "HIP launch or copy failed";
+        case JR_EINTERNAL: return "internal error";
+        default: return "unknown error code";
+    }
+}
+
+const char* jr_last_error_message(void) { return g_last_msg.c_str(); }
+
+int jr_check_schedule(const jr_schedule* s) {
+    if (!s) return fail(JR_EINVAL, "schedule is null");
+    return check_schedule(*s);
+}
+
+int jr_check_frames(const jr_frame* frames, int32_t n, int64_t out_capacity) {
+    return check_frames(frames, n, out_capacity);
+}
+
+int jr_get_default_schedule(int32_t dtype, int32_t max_iter, jr_schedule* out) {
+    (void)max_iter;
+    if (!out) return fail(JR_EINVAL, "out is null");
+    if (dtype < 0 || dtype > 2) return fail(JR_EINVAL, "unknown dtype %d", dtype);
+    *out = default_schedule(dtype);
+    return JR_OK;
+}
+
+int jr_set_default_schedule(int32_t dtype, const jr_schedule* s) {
+    if (!s) return fail(JR_EINVAL, "schedule is null");
+    if (dtype < 0 || dtype > 2) return fail(JR_EINVAL, "unknown dtype %d", dtype);
+    int rc = check_schedule(*s);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> g(g_sched_mu);
+    g_default[dtype] = *s;
+    return JR_OK;
+}
+
+int julia_render(jr_complex c, jr_window w, int32_t width, int32_t height, int32_t max_iter,
+                 int32_t dtype, int32_t* out, void* stream) {
+    return render_one(c, w, width, height, max_iter, dtype, JR_JULIA, out, stream, "julia_render");
+}
+
+int julia_render_plain(jr_complex c, jr_window w, int32_t width, int32_t height,
+                       int32_t max_iter, int32_t dtype, int32_t* out, void* stream) {
+    return render_plain(c, w, width, height, max_iter, dtype, JR_JULIA, out, stream,
+                        "julia_render_plain");
+}
+
+int mandelbrot_render(jr_window w, int32_t width, int32_t height, int32_t max_iter,
+                      int32_t dtype, int32_t* out, void* stream) {
+    return render_one(jr_complex{0.0, 0.0}, w, width, height, max_iter, dtype, JR_MANDELBROT,
+                      out, stream, "mandelbrot_render");
+}
+
+int mandelbrot_render_plain(jr_window w, int32_t width, int32_t height, int32_t max_iter,
+                            int32_t dtype, int32_t* out, void* stream) {
+    return render_plain(jr_complex{0.0, 0.0}, w, width, height, max_iter, dtype, JR_MANDELBROT,
+                        out, stream, "mandelbrot_render_plain");
+}
+
+int julia_render_batch(const jr_frame* frames, int32_t n, int32_t* out_base,
+                       int64_t out_capacity, const jr_schedule* sched, void* stream) {
+    return enqueue_batch(frames, n, out_base, out_capacity, sched, (hipStream_t)stream);
+}
+
+int jr_plan_create(const jr_frame* frames, int32_t n, int32_t* out_base, int64_t out_capacity,
+                   const jr_schedule* sched, jr_plan** plan) {
+    if (!plan) return fail(JR_EINVAL, "plan is null");
+    *plan = nullptr;
+    int rc = check_frames(frames, n, out_capacity);
+    if (rc) return rc;
+    if ((rc = check_out(out_base, "plan"))) return rc;
+    jr_schedule s;
+    if (sched) {
+        s = *sched;
+        if ((rc = check_schedule(s))) return rc;
+    } else {
+        double w[3] = {0, 0, 0};
+        for (int32_t k = 0; k < n; ++k) w[frames[k].dtype] += frame_cost(frames[k]);
+        s = default_schedule((int)(std::max_element(w, w + 3) - w));
+    }
+    int dev;
+    DeviceInfo info;
+    if ((rc = current_device(&dev, &info))) return rc;
+    Table t;
+    build_table(frames, n, s, t);
+    jr_plan* p = new jr_plan();
+    p->dev = dev;
+    p->n = n;
+    p->total_tiles = t.total_tiles;
+    p->dtmask = t.dtmask;
+    p->unroll = s.unroll;
+    p->refill = s.refill;
+    p->blocks = grid_blocks(info, s, t.total_tiles);
+    p->out = out_base;
+    const size_t bytes = (size_t)n * sizeof(DevFrame);
+    hipError_t e = hipMalloc((void**)&p->d_table, bytes);
+    if (e == hipSuccess) e = hipMemcpy(p->d_table, t.rows.data(), bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_ctr, 2 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemset(p->d_ctr, 0, 2 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        jr_plan_destroy(p);
+        return hip_fail(e, "plan setup");
+    }
+    *plan = p;
+    return JR_OK;
+}
+
+int jr_plan_launch(jr_plan* p, void* stream) {
+    if (!p) return fail(JR_EINVAL, "plan is null");
+    hipError_t e = jr::launch_persistent(p->unroll, p->dtmask, p->blocks, p->d_table, p->n,
+                                         p->total_tiles, p->out, p->d_ctr, p->refill,
+                                         (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "plan launch");
+    return JR_OK;
+}
+
+int jr_plan_capture(jr_plan* p, void* stream) {
+    if (!p) return fail(JR_EINVAL, "plan is null");
+    if (p->exec) return JR_OK;
+    hipStream_t s = (hipStream_t)stream;
+    hipStream_t own = nullptr;
+    if (s == nullptr) {
+        HIP_TRY(hipStreamCreateWithFlags(&own, hipStreamNonBlocking), "hipStreamCreate");
+        s = own;
+    }
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = jr::launch_persistent(p->unroll, p->dtmask, p->blocks, p->d_table, p->n,
+                                              p->total_tiles, p->out, p->d_ctr, p->refill, s);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(s, &g);
+        if (e == hipSuccess && le != hipSuccess) e = le;
+        if (e == hipSuccess) {
+            p->graph = g;
+            e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
+        } else if (g) {
+            (void)hipGraphDestroy(g);
+        }
+    }
+    if (own) (void)hipStreamDestroy(own);
+    if (e != hipSuccess) return hip_fail(e, "plan capture");
+    return JR_OK;
+}
+
+int jr_plan_replay(jr_plan* p, void* stream) {
+    if (!p) return fail(JR_EINVAL, "plan is null");
+    if (!p->exec) return fail(JR_EINVAL, "plan has no captured graph; call jr_plan_capture");
+    HIP_TRY(hipGraphLaunch(p->exec, (hipStream_t)stream), "hipGraphLaunch");
+    return JR_OK;
+}
+
+int jr_plan_info(const jr_plan* p, int64_t* tiles, int32_t* workgroups) {
+    if (!p) return fail(JR_EINVAL, "plan is null");
+    if (tiles) *tiles = p->total_tiles;
+    if (workgroups) *workgroups = p->blocks;
+    return JR_OK;
+}
+
+void jr_plan_destroy(jr_plan* p) {
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->d_table) (void)hipFree(p->d_table);
+    if (p->d_ctr) (void)hipFree(p->d_ctr);
+    delete p;
+}
+
+int jr_device_info(int32_t* num_cus, int64_t* hbm_bytes) {
+    int dev;
+    DeviceInfo info;
+    int rc = current_device(&dev, &info);
+    if (rc) return rc;
+    if (num_cus) *num_cus = info.num_cus;
+    if (hbm_bytes) *hbm_bytes = info.hbm;
+    return JR_OK;
+}
+
+void jr_shutdown(void) {
+    std::lock_guard<std::mutex> g(g_ws_mu);
+    for (auto& kv : g_ws) {
+        Workspace* ws = kv.second;
+        int prev = -1;
+        (void)hipGetDevice(&prev);
+        (void)hipSetDevice(kv.first.first);
+        for (int k = 0; k < kStages; ++k) {
+            if (ws->ev_used[k]) (void)hipEventSynchronize(ws->ev[k]);
+            if (ws->ev[k]) (void)hipEventDestroy(ws->ev[k]);
+            if (ws->h_stage[k]) (void)hipHostFree(ws->h_stage[k]);
+        }
+        if (ws->d_table) (void)hipFree(ws->d_table);
+        if (ws->d_ctr) (void)hipFree(ws->d_ctr);
+        if (prev >= 0) (void)hipSetDevice(prev);
+        delete ws;
+    }
+    g_ws.clear();
+}
+
+}  // extern "C"

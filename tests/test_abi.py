@@ -1,0 +1,147 @@
+"""CPU checks of the C ABI: the library loads, exports what include/julia.h
+declares, and rejects invalid arguments before touching any device."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "julia.h")
+
+
+def _ensure_built():
+    from paper_1611_03079_amd import build as b
+    if not os.path.exists(b.LIB):
+        b.build()
+
+
+_ensure_built()
+import paper_1611_03079_amd as jr  # noqa: E402
+from workloads import Frame  # noqa: E402
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([a-z_][a-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_functions_are_exported():
+    names = declared_functions()
+    assert len(names) >= 19, names
+    for n in names:
+        assert hasattr(jr.lib, n), n  # ctypes resolves the symbol or raises
+    assert set(names) == set(jr.EXPORTS)
+
+
+def test_strerror_names_every_code():
+    for code in (0, -1, -2, -3, -4, -5):
+        assert jr._strerror(code) and "unknown" not in jr._strerror(code)
+    assert "unknown" in jr._strerror(-99)
+
+
+FAKE_OUT = ctypes.c_void_p(0x10000)  # never dereferenced: validation fails first
+
+
+def _render(**kw):
+    args = dict(c=jr.jr_complex(-0.8, 0.156), w=jr.jr_window(-1.5, 1.5, -1.5, 1.5),
+                W=64, H=32, it=100, dt=0, out=FAKE_OUT)
+    args.update(kw)
+    return jr.lib.julia_render(args["c"], args["w"], args["W"], args["H"], args["it"],
+                               args["dt"], args["out"], None)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(W=0), dict(H=0), dict(W=-3), dict(W=65536, H=65536), dict(it=-1), dict(dt=3),
+    dict(dt=-1), dict(out=ctypes.c_void_p(0)), dict(out=ctypes.c_void_p(0x10002)),
+    dict(c=jr.jr_complex(math.nan, 0.0)), dict(c=jr.jr_complex(0.0, math.inf)),
+    dict(w=jr.jr_window(1.0, 1.0, -1.0, 1.0)), dict(w=jr.jr_window(-1.0, 1.0, 2.0, 1.0)),
+    dict(w=jr.jr_window(-math.inf, 1.0, -1.0, 1.0)), dict(w=jr.jr_window(-1e308, 1e308, -1, 1)),
+])
+def test_render_rejects_invalid_arguments(kw):
+    assert _render(**kw) == jr.JR_EINVAL
+    assert jr.last_error()
+
+
+def test_plain_and_mandelbrot_validate_too():
+    w = jr.jr_window(-2.0, 1.0, -1.0, 1.0)
+    assert jr.lib.julia_render_plain(jr.jr_complex(0, 0), w, 0, 4, 10, 0, FAKE_OUT, None) == jr.JR_EINVAL
+    assert jr.lib.mandelbrot_render(w, 4, 4, 10, 7, FAKE_OUT, None) == jr.JR_EINVAL
+    bad = jr.jr_window(1.0, -1.0, -1.0, 1.0)
+    assert jr.lib.mandelbrot_render_plain(bad, 4, 4, 10, 0, FAKE_OUT, None) == jr.JR_EINVAL
+
+
+def _frames():
+    return [Frame(complex(-0.8, 0.156), (-1.5, 1.5, -1.5, 1.5), 64, 48, 100, "fp32"),
+            Frame(0j, (-2.0, 1.0, -1.0, 1.0), 33, 17, 50, "ff", "mandelbrot")]
+
+
+def test_check_frames():
+    fr = _frames()
+    offs = [0, 64 * 48]
+    cap = 64 * 48 + 33 * 17
+    assert jr.check_frames(fr, offs, cap) == jr.JR_OK
+    assert jr.check_frames(fr, offs, cap - 1) == jr.JR_EINVAL          # overflows the arena
+    assert jr.check_frames(fr, [0, -1], cap) == jr.JR_EINVAL          # negative offset
+    assert jr.check_frames(fr, offs, cap, rows=[(0, 0), (5, 3)]) == jr.JR_EINVAL
+    assert jr.check_frames(fr, offs, cap, rows=[(0, 49), (0, 0)]) == jr.JR_EINVAL
+    assert jr.check_frames(fr, offs, cap, rows=[(47, 48), (16, 17)]) == jr.JR_OK
+    bad = [Frame(complex(-0.8, 0.156), (-1.5, 1.5, -1.5, 1.5), 64, 48, 100, "fp32")]
+    arr = jr._frames_array(bad, [0])
+    arr[0].reserved = 1
+    assert jr.lib.jr_check_frames(arr, 1, 10 ** 6) == jr.JR_EINVAL
+    arr[0].reserved = 0
+    arr[0].mode = 5
+    assert jr.lib.jr_check_frames(arr, 1, 10 ** 6) == jr.JR_EINVAL
+    assert jr.lib.jr_check_frames(arr, 0, 10 ** 6) == jr.JR_EINVAL
+    assert jr.lib.jr_check_frames(None, 1, 10 ** 6) == jr.JR_EINVAL
+
+
+@pytest.mark.parametrize("field,value", [
+    ("tile_w", 0), ("tile_w", 5000), ("tile_h", 0), ("tile_h", 100000), ("unroll", 2),
+    ("unroll", 32), ("refill", 0), ("refill", 65), ("waves_per_cu", 2),
+    ("waves_per_cu", 6), ("waves_per_cu", 36),
+])
+def test_check_schedule_rejects(field, value):
+    s = jr.Schedule()
+    assert jr.check_schedule(s) == jr.JR_OK
+    bad = jr.Schedule(**{**s.__dict__, field: value})
+    assert jr.check_schedule(bad) == jr.JR_EINVAL
+
+
+def test_default_schedules_are_valid_and_settable():
+    for dt in ("fp64", "fp32", "ff"):
+        s = jr.default_schedule(dt)
+        assert jr.check_schedule(s) == jr.JR_OK
+    old = jr.default_schedule("fp32")
+    new = jr.Schedule(32, 8, 8, 8, 24, "table")
+    jr.set_default_schedule("fp32", new)
+    assert jr.default_schedule("fp32") == new
+    jr.set_default_schedule("fp32", old)
+    with pytest.raises(jr.JuliaError):
+        jr.set_default_schedule("fp32", jr.Schedule(tile_w=0))
+
+
+def test_batch_rejects_before_device():
+    fr = _frames()
+    arr = jr._frames_array(fr, [0, 64 * 48])
+    rc = jr.lib.julia_render_batch(arr, 2, FAKE_OUT, 10, None, None)  # capacity too small
+    assert rc == jr.JR_EINVAL
+    h = ctypes.c_void_p()
+    rc = jr.lib.jr_plan_create(arr, 2, FAKE_OUT, 10, None, ctypes.byref(h))
+    assert rc == jr.JR_EINVAL and not h.value
+    assert jr.lib.jr_plan_launch(None, None) == jr.JR_EINVAL
+    assert jr.lib.jr_plan_replay(None, None) == jr.JR_EINVAL
+
+
+def test_valid_call_without_gpu_reports_no_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    rc = _render()
+    assert rc in (jr.JR_ENODEV, jr.JR_ELAUNCH), rc
+    assert jr.last_error()

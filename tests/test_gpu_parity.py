@@ -1,0 +1,255 @@
+"""GPU parity: the HIP kernels against the CPU oracle, element by element.
+
+Every call goes through the C ABI of libjulia.so.  FP64 counts must equal the
+oracle's FP64 counts exactly; the FP32 and float-float kernels must equal the
+oracle's FP32 and float-float formulations exactly, and their difference from
+FP64 is reported as a pixel fraction.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from workloads import Frame
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1611_03079_amd as jr  # noqa: E402
+
+UNIT = (-1.5, 1.5, -1.5, 1.5)
+C1 = complex(-0.8, 0.156)
+
+SCHEDULES = [
+    jr.Schedule(64, 16, 1, 16, 16, "cost"),
+    jr.Schedule(64, 16, 4, 16, 16, "cost"),
+    jr.Schedule(64, 8, 8, 1, 8, "table"),
+    jr.Schedule(32, 4, 16, 64, 32, "cost"),
+    jr.Schedule(13, 7, 4, 5, 4, "table"),   # ragged tiles, few waves
+    jr.Schedule(8, 8, 8, 32, 16, "cost"),
+]
+
+
+def gpu(c, win, W, H, it, dtype, mode="julia", plain=False):
+    out = jr.render(c, win, W, H, it, dtype, mode=mode, plain=plain)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def batch(frames, schedule=None, fill=None, offsets=None, rows=None):
+    offs, total = jr.arena_layout(frames) if offsets is None else (offsets, None)
+    if total is None:
+        total = max(o + f.width * f.height for o, f in zip(offs, frames))
+    arena = torch.full((total,), -7 if fill is None else fill, dtype=torch.int32, device="cuda")
+    arena, views = jr.render_batch(frames, schedule, arena=arena, offsets=offs, rows=rows)
+    torch.cuda.synchronize()
+    return arena.cpu().numpy(), [v.cpu().numpy() for v in views]
+
+
+def ref(f: Frame):
+    return oracle.render(f.c, f.window, f.width, f.height, f.max_iter, f.dtype, f.mode)
+
+
+# ------------------------------------------------------------- single images
+SHAPES = [(512, 512), (1, 1), (1, 97), (97, 1), (7, 13), (65, 33), (130, 67)]
+
+
+@pytest.mark.parametrize("plain", [True, False], ids=["plain", "tuned"])
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "%dx%d" % s)
+def test_fp64_bit_exact(shape, plain):
+    W, H = shape
+    got = gpu(C1, UNIT, W, H, 100, "fp64", plain=plain)
+    np.testing.assert_array_equal(got, oracle.render(C1, UNIT, W, H, 100, "fp64"))
+
+
+@pytest.mark.parametrize("plain", [True, False], ids=["plain", "tuned"])
+@pytest.mark.parametrize("dtype", ["fp32", "ff"])
+def test_reduced_precision_matches_formulation(dtype, plain):
+    W, H = (512, 512) if dtype == "fp32" else (256, 200)
+    got = gpu(C1, UNIT, W, H, 100, dtype, plain=plain)
+    np.testing.assert_array_equal(got, oracle.render(C1, UNIT, W, H, 100, dtype))
+    frac = float((got != oracle.render(C1, UNIT, W, H, 100, "fp64")).mean())
+    assert frac <= 0.005, frac
+
+
+@pytest.mark.parametrize("plain", [True, False], ids=["plain", "tuned"])
+@pytest.mark.parametrize("dtype", ["fp64", "fp32", "ff"])
+def test_mandelbrot(dtype, plain):
+    win = (-2.2, 0.8, -1.2, 1.3)
+    W, H = (300, 250) if dtype != "ff" else (150, 125)
+    got = gpu(0j, win, W, H, 200, dtype, mode="mandelbrot", plain=plain)
+    np.testing.assert_array_equal(got, oracle.render(0j, win, W, H, 200, dtype, "mandelbrot"))
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32", "ff"])
+@pytest.mark.parametrize("sched", range(len(SCHEDULES)))
+def test_schedules_do_not_change_counts(dtype, sched):
+    W, H = (200, 150) if dtype != "ff" else (120, 90)
+    f = Frame(complex(-0.4, 0.6), (-1.6, 1.6, -1.2, 1.2), W, H, 300, dtype)
+    _, views = batch([f], SCHEDULES[sched])
+    np.testing.assert_array_equal(views[0], ref(f))
+
+
+@pytest.mark.parametrize("c", [complex(-2.0, 0.0), complex(2.5, 0.3), complex(1.95, 0.0),
+                               complex(0.25, 0.0), complex(0.0, 1.0)])
+@pytest.mark.parametrize("dtype", ["fp64", "fp32", "ff"])
+def test_special_constants(c, dtype):
+    """|C| > 1.9 runs without deferred tests; C = -2, 1/4, i have exact orbits."""
+    win = (-2.1, 2.1, -0.9, 0.9)
+    W, H = 81, 41  # odd: the centre row is y = 0 exactly
+    for s in (SCHEDULES[1], SCHEDULES[3]):
+        f = Frame(c, win, W, H, 500, dtype)
+        _, views = batch([f], s)
+        np.testing.assert_array_equal(views[0], ref(f))
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32", "ff"])
+def test_cap_edge_cases(dtype):
+    for it in (0, 1, 2, 3, 5, 17):
+        for s in (SCHEDULES[0], SCHEDULES[3]):
+            f = Frame(C1, UNIT, 37, 29, it, dtype)
+            _, views = batch([f], s)
+            np.testing.assert_array_equal(views[0], ref(f))
+    assert not gpu(C1, UNIT, 40, 30, 0, dtype).any()
+    assert not gpu(C1, UNIT, 40, 30, 0, dtype, plain=True).any()
+
+
+# ------------------------------------------------------------------ batches
+def mixed_frames():
+    return [
+        Frame(C1, UNIT, 160, 120, 100, "fp64"),
+        Frame(complex(0.285, 0.01), (-1.3, 1.1, -0.7, 0.95), 97, 61, 250, "fp32"),
+        Frame(0j, (-2.0, 1.0, -1.0, 1.3), 64, 64, 150, "ff", "mandelbrot"),
+        Frame(complex(-2.0, 0.0), (-2.1, 2.1, -0.5, 0.5), 31, 9, 64, "fp32"),
+        Frame(complex(-0.123, 0.745), (-1.6, 1.6, -1.2, 1.2), 1, 1, 1000, "fp64"),
+        Frame(complex(0.3, 0.5), (-1.2, 1.2, -1.2, 1.2), 200, 3, 0, "ff"),
+        Frame(0j, (-0.75, -0.74, 0.1, 0.11), 90, 70, 2000, "fp64", "mandelbrot"),
+    ]
+
+
+@pytest.mark.parametrize("sched", [None, *range(len(SCHEDULES))])
+def test_mixed_batch_one_launch(sched):
+    frames = mixed_frames()
+    # gaps between frames stay untouched (sentinel -7): no stray or lost tile
+    offs, pos = [], 5
+    for f in frames:
+        offs.append(pos)
+        pos += f.pixels + 3
+    arena, views = batch(frames, None if sched is None else SCHEDULES[sched], offsets=offs)
+    covered = np.zeros(arena.size, dtype=bool)
+    for o, f, v in zip(offs, frames, views):
+        np.testing.assert_array_equal(v, ref(f))
+        covered[o:o + f.pixels] = True
+    assert (arena[~covered] == -7).all()
+
+
+def test_batch_equals_single_renders():
+    frames = [Frame(c, UNIT, 120, 90, 100, dt) for c in (C1, complex(0.3, 0.02), complex(-1.0, 0.25))
+              for dt in ("fp64", "fp32", "ff")]
+    _, views = batch(frames)
+    for f, v in zip(frames, views):
+        np.testing.assert_array_equal(v, gpu(f.c, f.window, f.width, f.height, f.max_iter, f.dtype))
+
+
+def test_row_ranges():
+    f = Frame(C1, UNIT, 70, 50, 100, "fp32")
+    full = ref(f)
+    _, views = batch([f], SCHEDULES[1], rows=[(13, 31)])
+    v = views[0]
+    np.testing.assert_array_equal(v[13:31], full[13:31])
+    assert (v[:13] == -7).all() and (v[31:] == -7).all()
+
+
+def test_plan_launch_and_graph_replay():
+    frames = wl.parameter_path(n=8, width=240, height=135)
+    plan = jr.Plan(frames, jr.Schedule(64, 16, 4, 16, 16, "cost"))
+    want = [oracle.render(f.c, f.window, f.width, f.height, f.max_iter, f.dtype) for f in frames]
+    plan.arena.fill_(-1)
+    plan.launch()
+    torch.cuda.synchronize()
+    for v, w in zip(plan.views, want):
+        np.testing.assert_array_equal(v.cpu().numpy(), w)
+    plan.capture()
+    for rep in range(4):
+        plan.arena.fill_(-1)          # eager work between the replays
+        torch.cuda.synchronize()
+        plan.replay()
+        torch.cuda.synchronize()
+        for v, w in zip(plan.views, want):
+            np.testing.assert_array_equal(v.cpu().numpy(), w)
+    plan.close()
+
+
+def test_streams_are_independent():
+    f1 = Frame(C1, UNIT, 256, 256, 300, "fp64")
+    f2 = Frame(complex(0.3, 0.5), UNIT, 256, 256, 300, "fp32")
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = []
+    for _ in range(3):
+        with torch.cuda.stream(s1):
+            a, va = jr.render_batch([f1], stream=s1)
+        with torch.cuda.stream(s2):
+            b, vb = jr.render_batch([f2], stream=s2)
+        outs.append((a, va, b, vb))
+    torch.cuda.synchronize()
+    for a, va, b, vb in outs:
+        np.testing.assert_array_equal(va[0].cpu().numpy(), ref(f1))
+        np.testing.assert_array_equal(vb[0].cpu().numpy(), ref(f2))
+
+
+# ------------------------------------------------------------ full sizes
+def _sample(W, H, n, seed):
+    rng = np.random.default_rng(seed)
+    ii = rng.integers(0, W, n).astype(np.int32)
+    jj = rng.integers(0, H, n).astype(np.int32)
+    # always include the corners and the centre
+    ii = np.concatenate([ii, [0, W - 1, 0, W - 1, W // 2]]).astype(np.int32)
+    jj = np.concatenate([jj, [0, 0, H - 1, H - 1, H // 2]]).astype(np.int32)
+    return ii, jj
+
+
+@pytest.mark.parametrize("seed,it,dtype", [(0, 100, "fp64"), (1, 1000, "fp64"),
+                                           (2, 100, "fp32"), (3, 1000, "fp32")])
+def test_single_4096_sampled(seed, it, dtype):
+    f = wl.single_4096(seed, it, dtype)
+    got = gpu(f.c, f.window, f.width, f.height, f.max_iter, f.dtype)
+    ii, jj = _sample(f.width, f.height, 20000, seed)
+    want = oracle.render_pixels(f.c, f.window, f.width, f.height, f.max_iter, ii, jj, f.dtype)
+    np.testing.assert_array_equal(got[jj, ii], want)
+    plain = gpu(f.c, f.window, f.width, f.height, f.max_iter, f.dtype, plain=True)
+    np.testing.assert_array_equal(plain, got)
+
+
+def test_parameter_path_full_sampled():
+    """The 256-frame 1920x1080 FP32 batch in the benchmark's launch setup."""
+    frames = wl.parameter_path()
+    plan = jr.Plan(frames, jr.default_schedule("fp32"))
+    plan.arena.fill_(-1)
+    plan.launch()
+    torch.cuda.synchronize()
+    arena = plan.arena.cpu().numpy()
+    assert (arena >= 0).all() and (arena <= 100).all()
+    for k in range(0, 256, 5):
+        f = frames[k]
+        v = arena[k * f.pixels:(k + 1) * f.pixels].reshape(f.height, f.width)
+        ii, jj = _sample(f.width, f.height, 1500, k)
+        want = oracle.render_pixels(f.c, f.window, f.width, f.height, f.max_iter, ii, jj, "fp32")
+        np.testing.assert_array_equal(v[jj, ii], want)
+    plan.close()
+
+
+def test_largest_frame():
+    """A frame of 2^31 - 1 - 2^16 pixels (the limit is < 2^31): counts 0 outside
+    the escape radius, and a band through the set checked against the oracle."""
+    W = 65535
+    H = (2 ** 31 - 1 - 2 ** 16) // W
+    win = (-2.0, 2.0, -1.5, 1.5)
+    out = torch.empty((H, W), dtype=torch.int32, device="cuda")
+    jr.render(complex(-0.8, 0.156), win, W, H, 20, "fp32", out=out)
+    torch.cuda.synchronize()
+    ii, jj = _sample(W, H, 5000, 11)
+    got = out[torch.from_numpy(jj).long().cuda(), torch.from_numpy(ii).long().cuda()].cpu().numpy()
+    want = oracle.render_pixels(complex(-0.8, 0.156), win, W, H, 20, ii, jj, "fp32")
+    np.testing.assert_array_equal(got, want)
+    del out
+    torch.cuda.empty_cache()
