@@ -86,10 +86,23 @@ EXPORTS = (
 
 
 def _load():
+    # torch ships its own HIP runtime (libamdhip64.so.7 under torch/lib).  Loading
+    # torch first makes libjulia.so bind to that same runtime (same SONAME), so
+    # torch's device pointers and streams are valid in the library's calls and
+    # the process holds one HIP runtime, not two.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError("libjulia.so is not built (%s); run python -m paper_1611_03079_amd.build"
                           % LIB_PATH)
     lib = ctypes.CDLL(LIB_PATH)
+    runtimes = set()
+    with open("/proc/self/maps") as maps:
+        for line in maps:
+            if "libamdhip64" in line:
+                runtimes.add(line.split()[-1])
+    if len(runtimes) > 1:
+        raise ImportError("two HIP runtimes are loaded (%s); import torch before any other "
+                          "HIP library" % ", ".join(sorted(runtimes)))
     i32, i64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
     P = ctypes.POINTER
     img = [jr_complex, jr_window, i32, i32, i32, i32, vp, vp]

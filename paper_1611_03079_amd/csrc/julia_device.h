@@ -26,9 +26,28 @@ struct alignas(16) DevFrame {
     int32_t row_begin, row_end;
     int32_t tiles_x;         // tiles per tile row of this frame
     int32_t tile_w, tile_h;
-    int32_t claim;           // tiles taken per atomic claim while in this frame
+    int32_t pad;
 };
 static_assert(sizeof(DevFrame) == 112, "DevFrame layout");
+
+// Work queues of the persistent kernel.  Same-address device-scope atomics
+// serialise (about 12 ns each on MI355X), so the tile counter is split into
+// kQueues counters on separate 4 KiB lines: granule u (a run of `granule`
+// consecutive tiles) belongs to queue u % kQueues.
+constexpr int kQueues = 64;
+constexpr int kQueueStride = 512;  // u64 elements between two counters (4 KiB)
+constexpr size_t kCounterBytes = (size_t)kQueues * kQueueStride * sizeof(unsigned long long);
+
+struct PersistentArgs {
+    const DevFrame* frames;
+    int32_t* out_base;
+    unsigned long long* ctr;
+    int64_t total_tiles;
+    int64_t granules;
+    int32_t nframes;
+    int32_t granule;   // tiles per granule
+    int32_t refill;
+};
 
 struct PlainArgs {
     int32_t* out;
@@ -36,10 +55,10 @@ struct PlainArgs {
     int32_t W, H, max_iter, mode;
 };
 
-hipError_t launch_persistent(int unroll, int dtmask, int blocks, const DevFrame* frames,
-                             int nframes, int64_t total_tiles, int32_t* out_base,
-                             unsigned long long* ctr, int refill, hipStream_t stream);
+// Zeroes the queue counters, then runs the persistent kernel (two kernels on
+// `stream`; both may be captured into a hipGraph).
+hipError_t launch_persistent(int unroll, int dtmask, int blocks, const PersistentArgs& args,
+                             hipStream_t stream);
 hipError_t launch_plain(int dtype, const PlainArgs& args, hipStream_t stream);
-hipError_t launch_zero_counters(unsigned long long* ctr, hipStream_t stream);
 
 }  // namespace jr

@@ -2,8 +2,8 @@
 //
 // Frame setup (pixel-centre mapping scalars in binary64), argument validation,
 // per-(device, stream) workspaces with a pinned staging ring for the frame
-// table, the self-resetting tile counter of the persistent kernel, prepared
-// plans and their hipGraph capture.  Compiled with -ffp-contract=off so that
+// table and the work-queue counters of the persistent kernel, prepared plans
+// and their hipGraph capture.  Compiled with -ffp-contract=off so that
 // the mapping scalars are the same rounded expressions on every build.
 
 #include <hip/hip_runtime_api.h>
@@ -167,8 +167,34 @@ bool absorbing(const jr_frame& f) {
 struct Table {
     std::vector<DevFrame> rows;
     int64_t total_tiles = 0;
+    double total_cost = 0.0;     // estimated, arbitrary units
+    double max_tile_cost = 0.0;  // estimated cost of the most expensive tile
     int dtmask = 0;
 };
+
+// Tiles per granule (one atomic claim): aim at ~16 granules per wave for the
+// most expensive tiles, so that claims stay rare on cheap work and a single
+// claim never holds a large share of a wave's work on expensive frames.
+int32_t granule_size(const Table& t, int blocks) {
+    const double waves = 4.0 * blocks;
+    const double target = t.total_cost / (waves * 16.0);
+    const double g = std::floor(target / std::max(t.max_tile_cost, 1.0));
+    return (int32_t)std::max(1.0, std::min(32.0, g));
+}
+
+jr::PersistentArgs make_args(const Table& t, const DevFrame* d_table, int32_t* out,
+                             unsigned long long* ctr, int32_t n, int blocks, int refill) {
+    jr::PersistentArgs a;
+    a.frames = d_table;
+    a.out_base = out;
+    a.ctr = ctr;
+    a.total_tiles = t.total_tiles;
+    a.nframes = n;
+    a.granule = granule_size(t, blocks);
+    a.granules = (t.total_tiles + a.granule - 1) / a.granule;
+    a.refill = refill;
+    return a;
+}
 
 void build_table(const jr_frame* frames, int32_t n, const jr_schedule& s, Table& t) {
     std::vector<int32_t> idx(n);
@@ -206,10 +232,9 @@ void build_table(const jr_frame* frames, int32_t n, const jr_schedule& s, Table&
         const int64_t tiles_y = (d.row_end - d.row_begin + d.tile_h - 1) / d.tile_h;
         d.tile_begin = t.total_tiles;
         t.total_tiles += (int64_t)d.tiles_x * tiles_y;
-        // Tiles per atomic claim: several cheap tiles at once, one expensive.
-        const double tile_cost = (double)d.tile_w * d.tile_h *
-                                 (4.0 + std::min<double>(f.max_iter, 64.0)) * dtype_cost(f.dtype);
-        d.claim = (int32_t)std::max(1.0, std::min(16.0, std::floor(262144.0 / tile_cost)));
+        const double tile_cost = frame_cost(f) / (double)((int64_t)d.tiles_x * tiles_y);
+        t.total_cost += frame_cost(f);
+        t.max_tile_cost = std::max(t.max_tile_cost, tile_cost);
         t.dtmask |= 1 << f.dtype;
     }
 }
@@ -275,8 +300,8 @@ int get_workspace(int dev, hipStream_t stream, Workspace** out) {
         return JR_OK;
     }
     Workspace* ws = new Workspace();
-    hipError_t e = hipMalloc((void**)&ws->d_ctr, 2 * sizeof(unsigned long long));
-    if (e == hipSuccess) e = hipMemset(ws->d_ctr, 0, 2 * sizeof(unsigned long long));
+    hipError_t e = hipMalloc((void**)&ws->d_ctr, jr::kCounterBytes);
+    if (e == hipSuccess) e = hipMemset(ws->d_ctr, 0, jr::kCounterBytes);
     for (int k = 0; k < kStages && e == hipSuccess; ++k)
         e = hipEventCreateWithFlags(&ws->ev[k], hipEventDisableTiming);
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -357,8 +382,9 @@ int enqueue_batch(const jr_frame* frames, int32_t n, int32_t* out_base, int64_t 
     HIP_TRY(hipEventRecord(ws->ev[k], stream), "hipEventRecord");
     ws->ev_used[k] = true;
     const int blocks = grid_blocks(info, s, t.total_tiles);
-    hipError_t e = jr::launch_persistent(s.unroll, t.dtmask, blocks, ws->d_table, n,
-                                         t.total_tiles, out_base, ws->d_ctr, s.refill, stream);
+    const jr::PersistentArgs args = make_args(t, ws->d_table, out_base, ws->d_ctr, n, blocks,
+                                              s.refill);
+    hipError_t e = jr::launch_persistent(s.unroll, t.dtmask, blocks, args, stream);
     if (e != hipSuccess) return hip_fail(e, "persistent kernel launch");
     return JR_OK;
 }
@@ -419,11 +445,10 @@ struct jr_plan {
     int dev = 0;
     DevFrame* d_table = nullptr;
     unsigned long long* d_ctr = nullptr;
-    int32_t n = 0;
     int64_t total_tiles = 0;
     int dtmask = 0;
-    int unroll = 1, refill = 1, blocks = 1;
-    int32_t* out = nullptr;
+    int unroll = 1, blocks = 1;
+    jr::PersistentArgs args;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -522,31 +547,28 @@ int jr_plan_create(const jr_frame* frames, int32_t n, int32_t* out_base, int64_t
     build_table(frames, n, s, t);
     jr_plan* p = new jr_plan();
     p->dev = dev;
-    p->n = n;
     p->total_tiles = t.total_tiles;
     p->dtmask = t.dtmask;
     p->unroll = s.unroll;
-    p->refill = s.refill;
     p->blocks = grid_blocks(info, s, t.total_tiles);
-    p->out = out_base;
     const size_t bytes = (size_t)n * sizeof(DevFrame);
     hipError_t e = hipMalloc((void**)&p->d_table, bytes);
     if (e == hipSuccess) e = hipMemcpy(p->d_table, t.rows.data(), bytes, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMalloc((void**)&p->d_ctr, 2 * sizeof(unsigned long long));
-    if (e == hipSuccess) e = hipMemset(p->d_ctr, 0, 2 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_ctr, jr::kCounterBytes);
+    if (e == hipSuccess) e = hipMemset(p->d_ctr, 0, jr::kCounterBytes);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         jr_plan_destroy(p);
         return hip_fail(e, "plan setup");
     }
+    p->args = make_args(t, p->d_table, out_base, p->d_ctr, n, p->blocks, s.refill);
     *plan = p;
     return JR_OK;
 }
 
 int jr_plan_launch(jr_plan* p, void* stream) {
     if (!p) return fail(JR_EINVAL, "plan is null");
-    hipError_t e = jr::launch_persistent(p->unroll, p->dtmask, p->blocks, p->d_table, p->n,
-                                         p->total_tiles, p->out, p->d_ctr, p->refill,
+    hipError_t e = jr::launch_persistent(p->unroll, p->dtmask, p->blocks, p->args,
                                          (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "plan launch");
     return JR_OK;
@@ -563,8 +585,7 @@ int jr_plan_capture(jr_plan* p, void* stream) {
     }
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t le = jr::launch_persistent(p->unroll, p->dtmask, p->blocks, p->d_table, p->n,
-                                              p->total_tiles, p->out, p->d_ctr, p->refill, s);
+        hipError_t le = jr::launch_persistent(p->unroll, p->dtmask, p->blocks, p->args, s);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(s, &g);
         if (e == hipSuccess && le != hipSuccess) e = le;

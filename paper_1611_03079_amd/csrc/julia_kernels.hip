@@ -15,8 +15,9 @@
 //                     comparator for the tuned kernel.
 //
 //   jr_persistent<K,M> persistent waves over a table of frames.  Each wave
-//                     claims tiles of pixels from one global atomic counter
-//                     (work stealing across frames of different cost), and
+//                     claims granules of tiles from atomic counters (64
+//                     queues; an idle wave steals from any queue that still
+//                     has work, across frames of different cost), and
 //                     inside a tile its 64 lanes take pixels one after the
 //                     other: a lane that finishes stores its count and takes
 //                     the tile's next pixel (lane refill), so divergent escape
@@ -347,64 +348,109 @@ __device__ __forceinline__ void run_frame_tile(const TileCtx& T, int defer, int 
         run_tile<A, 1>(T, refill);
 }
 
-// Grid: persistent workgroups of 256 threads (4 independent waves).  ctr[0] is
-// the global tile counter, ctr[1] counts waves that finished; the last wave
-// resets both so the next launch on the same workspace starts from zero.
-template <int K, int DTMASK>
-__global__ __launch_bounds__(256) void jr_persistent(const DevFrame* __restrict__ frames,
-                                                     int nframes, int64_t total_tiles,
-                                                     int32_t* __restrict__ out_base,
-                                                     unsigned long long* __restrict__ ctr,
-                                                     int refill) {
-    const int nwaves = gridDim.x * (blockDim.x / 64);
-    int f = 0;
-    int64_t cur = 0, end = 0;
-    for (;;) {
-        if (cur >= end) {
-            const int64_t g = frames[f].claim;
-            int64_t s = 0;
-            if (lane_id() == 0) s = (int64_t)atomicAdd(ctr, (unsigned long long)g);
-            s = uniform64(s);
-            if (s >= total_tiles) break;
-            cur = s;
-            end = min(s + g, total_tiles);
+__device__ __forceinline__ unsigned long long* queue_ctr(unsigned long long* ctr, int q) {
+    return ctr + (size_t)q * kQueueStride;
+}
+
+// Granules in queue q: granules q, q + kQueues, q + 2 kQueues, ...
+__device__ __forceinline__ int64_t queue_len(int64_t granules, int q) {
+    return granules > q ? (granules - q + kQueues - 1) / kQueues : 0;
+}
+
+// Largest frame index f with frames[f].tile_begin <= t.  Tiles of one granule
+// are consecutive and a queue's granules increase, so a short forward scan
+// from the previous frame usually ends it; otherwise binary search.
+__device__ __forceinline__ int find_frame(const DevFrame* __restrict__ frames, int nframes,
+                                          int64_t t, int f) {
+    if (frames[f].tile_begin <= t) {
+#pragma unroll 1
+        for (int s = 0; s < 4; ++s) {
+            if (f + 1 < nframes && frames[f + 1].tile_begin <= t)
+                f++;
+            else
+                return f;
         }
-        const int64_t t = cur++;
-        while (f + 1 < nframes && frames[f + 1].tile_begin <= t) f++;
-        const DevFrame& F = frames[f];
-        const int64_t local = t - F.tile_begin;
-        const int ty = (int)(local / F.tiles_x);
-        const int tx = (int)(local - (int64_t)ty * F.tiles_x);
-        TileCtx T;
-        T.out = out_base + F.out_offset;
-        T.cx = F.cx; T.cy = F.cy; T.hx = F.hx; T.hy = F.hy; T.cr = F.cr; T.ci = F.ci;
-        T.W = F.width; T.H = F.height; T.max_iter = F.max_iter; T.mode = F.mode;
-        T.col0 = tx * F.tile_w;
-        T.row0 = F.row_begin + ty * F.tile_h;
-        T.tw = min(F.tile_w, F.width - T.col0);
-        T.th = min(F.tile_h, F.row_end - T.row0);
-        const int dt = F.dtype;
-        if ((DTMASK & (1 << kFP32)) && dt == kFP32)
-            run_frame_tile<ArF32, K>(T, F.defer, refill);
-        else if ((DTMASK & (1 << kFP64)) && dt == kFP64)
-            run_frame_tile<ArF64, K>(T, F.defer, refill);
-        else if ((DTMASK & (1 << kFF)) && dt == kFF)
-            run_frame_tile<ArFF, K>(T, F.defer, refill);
     }
-    if (lane_id() == 0) {
-        unsigned long long prev = __hip_atomic_fetch_add(&ctr[1], 1ull, __ATOMIC_ACQ_REL,
-                                                         __HIP_MEMORY_SCOPE_AGENT);
-        if (prev == (unsigned long long)nwaves - 1) {
-            __hip_atomic_store(&ctr[0], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&ctr[1], 0ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    int lo = 0, hi = nframes - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (frames[mid].tile_begin <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int K, int DTMASK>
+__device__ __forceinline__ void run_global_tile(const PersistentArgs& a, int f, int64_t t) {
+    const DevFrame& F = a.frames[f];
+    const int64_t local = t - F.tile_begin;
+    const int ty = (int)(local / F.tiles_x);
+    const int tx = (int)(local - (int64_t)ty * F.tiles_x);
+    TileCtx T;
+    T.out = a.out_base + F.out_offset;
+    T.cx = F.cx; T.cy = F.cy; T.hx = F.hx; T.hy = F.hy; T.cr = F.cr; T.ci = F.ci;
+    T.W = F.width; T.H = F.height; T.max_iter = F.max_iter; T.mode = F.mode;
+    T.col0 = tx * F.tile_w;
+    T.row0 = F.row_begin + ty * F.tile_h;
+    T.tw = min(F.tile_w, F.width - T.col0);
+    T.th = min(F.tile_h, F.row_end - T.row0);
+    const int dt = F.dtype;
+    if ((DTMASK & (1 << kFP32)) && dt == kFP32)
+        run_frame_tile<ArF32, K>(T, F.defer, a.refill);
+    else if ((DTMASK & (1 << kFP64)) && dt == kFP64)
+        run_frame_tile<ArF64, K>(T, F.defer, a.refill);
+    else if ((DTMASK & (1 << kFF)) && dt == kFF)
+        run_frame_tile<ArFF, K>(T, F.defer, a.refill);
+}
+
+// Persistent workgroups of 256 threads: 4 independent waves.  Wave w starts on
+// queue w % kQueues and always holds one claim in flight (the atomic for the
+// next granule is issued before the current one is computed).  When its queue
+// is empty, the wave reads all kQueues counters at once (one per lane) and
+// moves to the next queue that still has granules; it leaves when none has.
+template <int K, int DTMASK>
+__global__ __launch_bounds__(256) void jr_persistent(PersistentArgs a) {
+    const int lane = lane_id();
+    const int wave = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    int q = wave % kQueues;
+    int64_t qlen = queue_len(a.granules, q);
+    unsigned long long raw = 0;
+    if (lane == 0) raw = atomicAdd(queue_ctr(a.ctr, q), 1ull);
+    int f = 0;
+    for (;;) {
+        const int64_t j = uniform64((int64_t)raw);
+        if (j >= qlen) {
+            bool has = false;
+            if (lane < kQueues) {
+                const unsigned long long c = __hip_atomic_load(
+                    queue_ctr(a.ctr, lane), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                has = (int64_t)c < queue_len(a.granules, lane);
+            }
+            const uint64_t m = __ballot(has);
+            if (m == 0) break;
+            const int s = (q + 1) & (kQueues - 1);
+            const uint64_t rot = s ? ((m >> s) | (m << (64 - s))) : m;
+            q = (s + __builtin_ctzll(rot)) & (kQueues - 1);
+            qlen = queue_len(a.granules, q);
+            if (lane == 0) raw = atomicAdd(queue_ctr(a.ctr, q), 1ull);
+            continue;
+        }
+        if (lane == 0) raw = atomicAdd(queue_ctr(a.ctr, q), 1ull);  // next claim, in flight
+        const int64_t t0 = (j * kQueues + q) * (int64_t)a.granule;
+        const int64_t t1 = min(t0 + (int64_t)a.granule, a.total_tiles);
+        for (int64_t t = t0; t < t1; ++t) {
+            f = find_frame(a.frames, a.nframes, t, f);
+            run_global_tile<K, DTMASK>(a, f, t);
         }
     }
 }
 
-// Sets the two counters of a workspace to zero (used when one is created or
-// after a failed launch; a plain kernel, so it may sit inside a hipGraph).
-__global__ void jr_zero_counters(unsigned long long* ctr) {
-    if (threadIdx.x < 2) ctr[threadIdx.x] = 0ull;
+// Zeroes the kQueues counters before a persistent launch (a kernel, not a
+// memset, so that it can sit inside a captured hipGraph).
+__global__ void jr_reset_queues(unsigned long long* ctr) {
+    if (threadIdx.x < kQueues) ctr[(size_t)threadIdx.x * kQueueStride] = 0ull;
 }
 
 }  // namespace jr
@@ -414,7 +460,7 @@ __global__ void jr_zero_counters(unsigned long long* ctr) {
 // ---------------------------------------------------------------------------
 namespace jr {
 
-using PersistentFn = void (*)(const DevFrame*, int, int64_t, int32_t*, unsigned long long*, int);
+using PersistentFn = void (*)(PersistentArgs);
 
 template <int K>
 static PersistentFn pick_mask(int dtmask) {
@@ -426,9 +472,8 @@ static PersistentFn pick_mask(int dtmask) {
     }
 }
 
-hipError_t launch_persistent(int unroll, int dtmask, int blocks, const DevFrame* frames,
-                             int nframes, int64_t total_tiles, int32_t* out_base,
-                             unsigned long long* ctr, int refill, hipStream_t stream) {
+hipError_t launch_persistent(int unroll, int dtmask, int blocks, const PersistentArgs& args,
+                             hipStream_t stream) {
     PersistentFn fn;
     switch (unroll) {
         case 1: fn = pick_mask<1>(dtmask); break;
@@ -437,8 +482,10 @@ hipError_t launch_persistent(int unroll, int dtmask, int blocks, const DevFrame*
         case 16: fn = pick_mask<16>(dtmask); break;
         default: return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), 0, stream, frames, nframes, total_tiles,
-                       out_base, ctr, refill);
+    hipLaunchKernelGGL(jr_reset_queues, dim3(1), dim3(kQueues), 0, stream, args.ctr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), 0, stream, args);
     return hipGetLastError();
 }
 
@@ -453,11 +500,6 @@ hipError_t launch_plain(int dtype, const PlainArgs& args, hipStream_t stream) {
         case kFF: hipLaunchKernelGGL(jr_plain<ArFF>, grid, dim3(256), 0, stream, args); break;
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_zero_counters(unsigned long long* ctr, hipStream_t stream) {
-    hipLaunchKernelGGL(jr_zero_counters, dim3(1), dim3(64), 0, stream, ctr);
     return hipGetLastError();
 }
 
