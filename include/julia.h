@@ -91,20 +91,25 @@ typedef struct {
 } jr_frame;
 
 /*
- * Schedule of the persistent kernel.  None of these fields changes a count:
- * they decide which lane computes which pixel and when, never the arithmetic.
- *   tile_w, tile_h  pixels per work tile claimed from the global tile
- *                   counter: 1 <= tile_w <= 4096, 1 <= tile_h, and
- *                   tile_w * tile_h <= 65536.
- *   unroll          iterations between two escape tests: 1, 4, 8 or 16.
- *                   With unroll > 1 a lane that escaped inside the block is
- *                   replayed from its saved state, so counts are unchanged;
- *                   frames where escape is not known to be absorbing
- *                   (|C| > 1.9 somewhere) always run with 1.
+ * Schedule of the tiled kernel.  None of these fields changes a count: they
+ * decide which lane computes which pixel and when, never the arithmetic.
+ *   tile_w, tile_h  pixels per work tile: 1 <= tile_w <= 64, 1 <= tile_h <= 64.
+ *   unroll          iterations per branch-free block: 1, 2, 4 or 8, or with
+ *                   defer = 1: 4, 8 or 16.
+ *   defer           0: every iterate is tested inside the block and the
+ *                   leading non-escaped iterates are counted; 1: only the
+ *                   block's last iterate is tested and lanes found escaped are
+ *                   replayed from the block start.  Both give the counts of a
+ *                   test on every iteration; frames where escape is not known
+ *                   to be absorbing (|C| > 1.9 somewhere) run with unroll 1.
  *   refill          idle lanes in a wave that trigger a refill round, 1..64:
- *                   finished lanes store their count and take the tile's next
- *                   pixels.
- *   waves_per_cu    resident waves per compute unit the grid is sized for
+ *                   finished lanes store their count and take the next pixels,
+ *                   from the next tile when the current one is used up.
+ *   persistent      1: waves_per_cu resident waves per compute unit take tiles
+ *                   from 64 atomic work queues, stealing from other queues when
+ *                   theirs is empty; 0: one wave per tile, placed by the
+ *                   hardware dispatcher.
+ *   waves_per_cu    persistent mode: resident waves per compute unit
  *                   (4..32, a multiple of 4).
  *   order           JR_ORDER_TABLE: frames in the order given;
  *                   JR_ORDER_COST: most expensive frames first (estimated
@@ -113,13 +118,15 @@ typedef struct {
 typedef struct {
     int32_t tile_w, tile_h;
     int32_t unroll;
+    int32_t defer;
     int32_t refill;
+    int32_t persistent;
     int32_t waves_per_cu;
     int32_t order;
 } jr_schedule;
 
 /*
- * Render one Julia image (Section 2) with the tuned persistent kernel.
+ * Render one Julia image (Section 2) with the tuned tiled kernel.
  * out: device, width*height int32, row-major.  The schedule is the library's
  * default for (dtype, max_iter) (see jr_set_default_schedule).
  */
@@ -143,7 +150,7 @@ int mandelbrot_render_plain(jr_window w, int32_t width, int32_t height,
 
 /*
  * Render n frames (any mix of sizes, caps, dtypes and modes) in ONE launch of
- * the persistent work-stealing kernel.  frames: host array of n >= 1
+ * the tiled kernel (persistent work-stealing waves by default).  frames: host array of n >= 1
  * descriptors, copied before return.  out_base: device arena of out_capacity
  * int32 elements holding every frame at its out_offset.  sched: NULL for the
  * default schedule of the batch's dominant dtype.  Frames must not overlap in

@@ -49,7 +49,8 @@ class jr_frame(ctypes.Structure):
 
 class jr_schedule(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
-                ("unroll", ctypes.c_int32), ("refill", ctypes.c_int32),
+                ("unroll", ctypes.c_int32), ("defer", ctypes.c_int32),
+                ("refill", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("waves_per_cu", ctypes.c_int32), ("order", ctypes.c_int32)]
 
 
@@ -58,22 +59,25 @@ assert ctypes.sizeof(jr_frame) == 88
 
 @dataclass(frozen=True)
 class Schedule:
-    """Schedule of the persistent kernel (see include/julia.h); never changes counts."""
+    """Schedule of the tiled kernel (see include/julia.h); never changes counts."""
     tile_w: int = 64
     tile_h: int = 16
     unroll: int = 4
+    defer: int = 0
     refill: int = 16
+    persistent: int = 1
     waves_per_cu: int = 16
     order: str = "cost"
 
     def to_c(self) -> jr_schedule:
-        return jr_schedule(self.tile_w, self.tile_h, self.unroll, self.refill,
-                           self.waves_per_cu, ORDERS[self.order])
+        return jr_schedule(self.tile_w, self.tile_h, self.unroll, self.defer, self.refill,
+                           self.persistent, self.waves_per_cu, ORDERS[self.order])
 
     @staticmethod
     def from_c(s: jr_schedule) -> "Schedule":
         inv = {v: k for k, v in ORDERS.items()}
-        return Schedule(s.tile_w, s.tile_h, s.unroll, s.refill, s.waves_per_cu, inv[s.order])
+        return Schedule(s.tile_w, s.tile_h, s.unroll, s.defer, s.refill, s.persistent,
+                        s.waves_per_cu, inv[s.order])
 
 
 EXPORTS = (

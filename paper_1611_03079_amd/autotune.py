@@ -1,0 +1,139 @@
+"""Autotuner for the tiled kernel's schedule.
+
+A schedule (tile shape, iteration block length and escape-test mode, refill
+threshold, persistent or one-wave-per-tile, resident waves, frame order)
+never changes a count: only which lane computes which pixel and when.  The
+tuner therefore times candidate schedules on a representative batch with HIP
+events around prepared launches (jr_plan_launch) and keeps the fastest.
+
+Search, in three stages from a base schedule:
+  1. the iteration block (unroll, defer),
+  2. tile shape x scheduling mode x refill threshold,
+  3. resident waves per compute unit (persistent mode only).
+
+Results are cached in a JSON file keyed by (device, dtype, cap bucket, pixel
+bucket); ``apply_cache`` installs the cached winners as the library defaults
+(jr_set_default_schedule), which julia_render and julia_render_batch use when
+no schedule is passed.
+"""
+import json
+import math
+import os
+from dataclasses import asdict, replace
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import paper_1611_03079_amd as jr
+
+BLOCKS = [(1, 0), (2, 0), (4, 0), (8, 0), (4, 1), (8, 1), (16, 1)]
+TILES = [(64, 1), (64, 4), (64, 16), (32, 8), (16, 16), (64, 64)]
+REFILLS = [8, 16, 32, 64]
+WAVES = [8, 16, 24, 32]
+
+DEFAULT_CACHE = os.environ.get(
+    "JR_AUTOTUNE_CACHE",
+    os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json"))
+
+
+def cap_bucket(max_iter: int) -> str:
+    return "cap<=128" if max_iter <= 128 else "cap<=1024" if max_iter <= 1024 else "cap>1024"
+
+
+def pixel_bucket(pixels: int) -> str:
+    return "px<1M" if pixels < (1 << 20) else "px<64M" if pixels < (64 << 20) else "px>=64M"
+
+
+def cache_key(device: str, dtype: str, max_iter: int, pixels: int) -> str:
+    return "|".join((device, dtype, cap_bucket(max_iter), pixel_bucket(pixels)))
+
+
+def time_plan(frames, schedule: jr.Schedule, reps: int = 3, warmup: int = 1) -> float:
+    """Median device time (ms) of one launch of `frames` under `schedule`."""
+    import torch
+    plan = jr.Plan(frames, schedule)
+    try:
+        for _ in range(warmup):
+            plan.launch()
+        times = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            plan.launch()
+            b.record()
+            b.synchronize()
+            times.append(a.elapsed_time(b))
+        times.sort()
+        return times[len(times) // 2]
+    finally:
+        plan.close()
+
+
+def _stage(frames, base: jr.Schedule, variants: List[dict], reps: int, log: list) -> jr.Schedule:
+    best, best_t = base, math.inf
+    seen = set()
+    for v in variants:
+        s = replace(base, **v)
+        if s in seen or jr.check_schedule(s) != jr.JR_OK:
+            continue
+        seen.add(s)
+        t = time_plan(frames, s, reps=reps)
+        log.append((asdict(s), t))
+        if t < best_t:
+            best, best_t = s, t
+    return best
+
+
+def tune(frames: Sequence, base: Optional[jr.Schedule] = None, reps: int = 3,
+         log: Optional[list] = None) -> Tuple[jr.Schedule, float, list]:
+    """Search schedules for `frames`; returns (best, its median ms, log)."""
+    log = [] if log is None else log
+    base = base or jr.Schedule()
+    s = _stage(frames, base, [dict(unroll=u, defer=d) for u, d in BLOCKS], reps, log)
+    s = _stage(frames, s, [dict(tile_w=tw, tile_h=th, persistent=p, refill=r)
+                           for tw, th in TILES for p in (1, 0) for r in REFILLS], reps, log)
+    if s.persistent:
+        s = _stage(frames, s, [dict(waves_per_cu=w) for w in WAVES], reps, log)
+    # re-check the block choice under the final tiling
+    s = _stage(frames, s, [dict(unroll=u, defer=d) for u, d in BLOCKS], reps, log)
+    best_t = min(t for d, t in log if jr.Schedule(**d) == s)
+    return s, best_t, log
+
+
+def device_name() -> str:
+    import torch
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return getattr(p, "gcnArchName", p.name).split(":")[0]
+
+
+def load_cache(path: str = DEFAULT_CACHE) -> Dict[str, dict]:
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def save_cache(cache: Dict[str, dict], path: str = DEFAULT_CACHE):
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def record(cache: Dict[str, dict], frames: Sequence, schedule: jr.Schedule, ms: float):
+    dtype = max(set(f.dtype for f in frames), key=lambda d: sum(f.pixels for f in frames if f.dtype == d))
+    cap = max(f.max_iter for f in frames)
+    px = sum(f.pixels for f in frames)
+    cache[cache_key(device_name(), dtype, cap, px)] = {"schedule": asdict(schedule), "ms": ms}
+
+
+def lookup(cache: Dict[str, dict], dtype: str, max_iter: int, pixels: int) -> Optional[jr.Schedule]:
+    e = cache.get(cache_key(device_name(), dtype, max_iter, pixels))
+    return jr.Schedule(**e["schedule"]) if e else None
+
+
+def apply_cache(cache: Dict[str, dict], max_iter: int = 100, pixels: int = 1 << 24):
+    """Install cached schedules for (dtype, max_iter, pixels) as library defaults."""
+    for dt in ("fp64", "fp32", "ff"):
+        s = lookup(cache, dt, max_iter, pixels)
+        if s is not None:
+            jr.set_default_schedule(dt, s)

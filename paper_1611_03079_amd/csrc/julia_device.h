@@ -22,7 +22,7 @@ struct alignas(16) DevFrame {
     int32_t max_iter;
     int32_t dtype;           // kFP64 / kFP32 / kFF
     int32_t mode;            // kModeJulia / kModeMandelbrot
-    int32_t defer;           // 1: escape absorbing over the whole frame
+    int32_t defer;           // 1: escape absorbing over the whole frame (|C| <= 1.9)
     int32_t row_begin, row_end;
     int32_t tiles_x;         // tiles per tile row of this frame
     int32_t tile_w, tile_h;
@@ -45,8 +45,9 @@ struct PersistentArgs {
     int64_t total_tiles;
     int64_t granules;
     int32_t nframes;
-    int32_t granule;   // tiles per granule
+    int32_t granule;     // tiles per granule
     int32_t refill;
+    int32_t persistent;  // 1: work queues; 0: one wave per tile
 };
 
 struct PlainArgs {
@@ -55,10 +56,10 @@ struct PlainArgs {
     int32_t W, H, max_iter, mode;
 };
 
-// Zeroes the queue counters, then runs the persistent kernel (two kernels on
-// `stream`; both may be captured into a hipGraph).
-hipError_t launch_persistent(int unroll, int dtmask, int blocks, const PersistentArgs& args,
-                             hipStream_t stream);
+// Runs the tiled kernel; in persistent mode a small kernel zeroes the queue
+// counters first (both may be captured into a hipGraph).
+hipError_t launch_tiled(int unroll, int defer, int dtmask, int blocks, const PersistentArgs& args,
+                        hipStream_t stream);
 hipError_t launch_plain(int dtype, const PlainArgs& args, hipStream_t stream);
 
 }  // namespace jr

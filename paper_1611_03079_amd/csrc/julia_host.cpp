@@ -93,10 +93,16 @@ int check_out(const void* p, const char* who) {
 }
 
 int check_schedule(const jr_schedule& s) {
-    if (s.tile_w < 1 || s.tile_w > 4096 || s.tile_h < 1 || (int64_t)s.tile_w * s.tile_h > 65536)
+    if (s.tile_w < 1 || s.tile_w > 64 || s.tile_h < 1 || s.tile_h > 64)
         return fail(JR_EINVAL, "schedule: tile %d x %d out of range", s.tile_w, s.tile_h);
-    if (s.unroll != 1 && s.unroll != 4 && s.unroll != 8 && s.unroll != 16)
-        return fail(JR_EINVAL, "schedule: unroll must be 1, 4, 8 or 16 (got %d)", s.unroll);
+    if (s.defer != 0 && s.defer != 1)
+        return fail(JR_EINVAL, "schedule: defer must be 0 or 1 (got %d)", s.defer);
+    if (!s.defer && s.unroll != 1 && s.unroll != 2 && s.unroll != 4 && s.unroll != 8)
+        return fail(JR_EINVAL, "schedule: unroll must be 1, 2, 4 or 8 (got %d)", s.unroll);
+    if (s.defer && s.unroll != 4 && s.unroll != 8 && s.unroll != 16)
+        return fail(JR_EINVAL, "schedule: with defer, unroll must be 4, 8 or 16 (got %d)", s.unroll);
+    if (s.persistent != 0 && s.persistent != 1)
+        return fail(JR_EINVAL, "schedule: persistent must be 0 or 1 (got %d)", s.persistent);
     if (s.refill < 1 || s.refill > 64)
         return fail(JR_EINVAL, "schedule: refill must be in 1..64 (got %d)", s.refill);
     if (s.waves_per_cu < 4 || s.waves_per_cu > 32 || (s.waves_per_cu % 4) != 0)
@@ -132,9 +138,10 @@ int check_frames(const jr_frame* frames, int32_t n, int64_t capacity) {
 std::mutex g_sched_mu;
 // Defaults per dtype; the autotuner can replace them (jr_set_default_schedule).
 jr_schedule g_default[3] = {
-    {64, 16, 8, 16, 16, JR_ORDER_COST},  // FP64
-    {64, 16, 4, 16, 16, JR_ORDER_COST},  // FP32
-    {64, 8, 4, 16, 16, JR_ORDER_COST},   // FF
+    // tile_w, tile_h, unroll, defer, refill, persistent, waves_per_cu, order
+    {64, 16, 4, 0, 16, 1, 16, JR_ORDER_COST},  // FP64
+    {64, 16, 4, 0, 16, 1, 16, JR_ORDER_COST},  // FP32
+    {64, 8, 4, 0, 16, 1, 16, JR_ORDER_COST},   // FF
 };
 
 jr_schedule default_schedule(int dtype) {
@@ -183,7 +190,7 @@ int32_t granule_size(const Table& t, int blocks) {
 }
 
 jr::PersistentArgs make_args(const Table& t, const DevFrame* d_table, int32_t* out,
-                             unsigned long long* ctr, int32_t n, int blocks, int refill) {
+                             unsigned long long* ctr, int32_t n, int blocks, const jr_schedule& s) {
     jr::PersistentArgs a;
     a.frames = d_table;
     a.out_base = out;
@@ -192,7 +199,8 @@ jr::PersistentArgs make_args(const Table& t, const DevFrame* d_table, int32_t* o
     a.nframes = n;
     a.granule = granule_size(t, blocks);
     a.granules = (t.total_tiles + a.granule - 1) / a.granule;
-    a.refill = refill;
+    a.refill = s.refill;
+    a.persistent = s.persistent;
     return a;
 }
 
@@ -223,11 +231,11 @@ void build_table(const jr_frame* frames, int32_t n, const jr_schedule& s, Table&
         d.max_iter = f.max_iter;
         d.dtype = f.dtype;
         d.mode = f.mode;
-        d.defer = (s.unroll > 1 && absorbing(f)) ? 1 : 0;
+        d.defer = absorbing(f) ? 1 : 0;
         d.row_begin = f.row_begin;
         d.row_end = f.row_end == 0 ? f.height : f.row_end;
         d.tile_w = std::min(s.tile_w, f.width);
-        d.tile_h = s.tile_h;
+        d.tile_h = std::min(s.tile_h, d.row_end - d.row_begin);
         d.tiles_x = (f.width + d.tile_w - 1) / d.tile_w;
         const int64_t tiles_y = (d.row_end - d.row_begin + d.tile_h - 1) / d.tile_h;
         d.tile_begin = t.total_tiles;
@@ -318,6 +326,7 @@ int get_workspace(int dev, hipStream_t stream, Workspace** out) {
 }
 
 int grid_blocks(const DeviceInfo& info, const jr_schedule& s, int64_t total_tiles) {
+    if (!s.persistent) return (int)std::min<int64_t>((total_tiles + 3) / 4, INT32_MAX);
     int64_t blocks = (int64_t)info.num_cus * (s.waves_per_cu / 4);
     // No more waves than tiles: extra waves would only claim and leave.
     const int64_t need = (total_tiles + 3) / 4;
@@ -382,9 +391,8 @@ int enqueue_batch(const jr_frame* frames, int32_t n, int32_t* out_base, int64_t 
     HIP_TRY(hipEventRecord(ws->ev[k], stream), "hipEventRecord");
     ws->ev_used[k] = true;
     const int blocks = grid_blocks(info, s, t.total_tiles);
-    const jr::PersistentArgs args = make_args(t, ws->d_table, out_base, ws->d_ctr, n, blocks,
-                                              s.refill);
-    hipError_t e = jr::launch_persistent(s.unroll, t.dtmask, blocks, args, stream);
+    const jr::PersistentArgs args = make_args(t, ws->d_table, out_base, ws->d_ctr, n, blocks, s);
+    hipError_t e = jr::launch_tiled(s.unroll, s.defer, t.dtmask, blocks, args, stream);
     if (e != hipSuccess) return hip_fail(e, "persistent kernel launch");
     return JR_OK;
 }
@@ -447,7 +455,7 @@ struct jr_plan {
     unsigned long long* d_ctr = nullptr;
     int64_t total_tiles = 0;
     int dtmask = 0;
-    int unroll = 1, blocks = 1;
+    int unroll = 1, defer = 0, blocks = 1;
     jr::PersistentArgs args;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -550,6 +558,7 @@ int jr_plan_create(const jr_frame* frames, int32_t n, int32_t* out_base, int64_t
     p->total_tiles = t.total_tiles;
     p->dtmask = t.dtmask;
     p->unroll = s.unroll;
+    p->defer = s.defer;
     p->blocks = grid_blocks(info, s, t.total_tiles);
     const size_t bytes = (size_t)n * sizeof(DevFrame);
     hipError_t e = hipMalloc((void**)&p->d_table, bytes);
@@ -561,15 +570,15 @@ int jr_plan_create(const jr_frame* frames, int32_t n, int32_t* out_base, int64_t
         jr_plan_destroy(p);
         return hip_fail(e, "plan setup");
     }
-    p->args = make_args(t, p->d_table, out_base, p->d_ctr, n, p->blocks, s.refill);
+    p->args = make_args(t, p->d_table, out_base, p->d_ctr, n, p->blocks, s);
     *plan = p;
     return JR_OK;
 }
 
 int jr_plan_launch(jr_plan* p, void* stream) {
     if (!p) return fail(JR_EINVAL, "plan is null");
-    hipError_t e = jr::launch_persistent(p->unroll, p->dtmask, p->blocks, p->args,
-                                         (hipStream_t)stream);
+    hipError_t e = jr::launch_tiled(p->unroll, p->defer, p->dtmask, p->blocks, p->args,
+                                    (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "plan launch");
     return JR_OK;
 }
@@ -585,7 +594,7 @@ int jr_plan_capture(jr_plan* p, void* stream) {
     }
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t le = jr::launch_persistent(p->unroll, p->dtmask, p->blocks, p->args, s);
+        hipError_t le = jr::launch_tiled(p->unroll, p->defer, p->dtmask, p->blocks, p->args, s);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(s, &g);
         if (e == hipSuccess && le != hipSuccess) e = le;

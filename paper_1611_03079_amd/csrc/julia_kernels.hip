@@ -14,19 +14,21 @@
 //                     GPU version assigns one thread to each point) and the
 //                     comparator for the tuned kernel.
 //
-//   jr_persistent<K,M> persistent waves over a table of frames.  Each wave
-//                     claims granules of tiles from atomic counters (64
+//   jr_tiled<K,D,M>   waves over a table of frames.  In persistent mode each
+//                     wave claims granules of tiles from atomic counters (64
 //                     queues; an idle wave steals from any queue that still
-//                     has work, across frames of different cost), and
-//                     inside a tile its 64 lanes take pixels one after the
-//                     other: a lane that finishes stores its count and takes
-//                     the tile's next pixel (lane refill), so divergent escape
-//                     counts do not leave lanes idle until the slowest pixel of
-//                     a fixed 64-pixel block ends.  With K > 1 the escape test
-//                     runs once every K iterations; a lane found escaped is
-//                     replayed from its saved state with a test on every
-//                     iteration, which gives the same count bit for bit
-//                     because escape is absorbing when |C| <= 1.9.
+//                     has work, across frames of different cost); otherwise
+//                     one wave per tile.  The 64 lanes of a wave take pixels
+//                     one after the other: a lane that finishes stores its
+//                     count and takes the next pixel (lane refill), from the
+//                     next tile when the current one runs out, so divergent
+//                     escape counts do not leave lanes idle until the slowest
+//                     pixel of a fixed block ends.  Iterations run in blocks
+//                     of K without branches; the escape test is counted on
+//                     every iterate, or (D = 1) run once per block with a
+//                     replay of the lanes found escaped.  Both give the counts
+//                     of a test on every iteration bit for bit, because escape
+//                     is absorbing when |C| <= 1.9 (other frames use K = 1).
 //
 // This translation unit is compiled with -ffp-contract=off: every a*b + c
 // below is a rounded product and a rounded sum unless fmaf() is written out.
@@ -46,8 +48,11 @@ namespace jr {
 struct ArF64 {
     struct Z { double x, y; };
     struct C { double r, i; };
-    __device__ static Z make(double x, double y) { return Z{x, y}; }
-    __device__ static C cmake(double r, double i) { return C{r, i}; }
+    using V = double;  // one coordinate
+    __device__ static V coord(double v) { return v; }
+    __device__ static V shfl(V v, int src) { return __shfl(v, src); }
+    __device__ static Z make(V x, V y) { return Z{x, y}; }
+    __device__ static C cmake(V r, V i) { return C{r, i}; }
     __device__ static bool inside(const Z& z) {
         double x2 = z.x * z.x;
         double y2 = z.y * z.y;
@@ -79,8 +84,11 @@ struct ArF64 {
 struct ArF32 {
     struct Z { float x, y; };
     struct C { float r, i; };
-    __device__ static Z make(double x, double y) { return Z{(float)x, (float)y}; }
-    __device__ static C cmake(double r, double i) { return C{(float)r, (float)i}; }
+    using V = float;
+    __device__ static V coord(double v) { return (float)v; }  // one rounding
+    __device__ static V shfl(V v, int src) { return __shfl(v, src); }
+    __device__ static Z make(V x, V y) { return Z{x, y}; }
+    __device__ static C cmake(V r, V i) { return C{r, i}; }
     __device__ static bool inside(const Z& z) {
         float yy = z.y * z.y;
         return __builtin_fmaf(z.x, z.x, yy) <= 4.0f;
@@ -148,8 +156,11 @@ struct ArFF {
         r.lo = (float)(v - (double)r.hi);
         return r;
     }
-    __device__ static Z make(double x, double y) { return Z{split(x), split(y)}; }
-    __device__ static C cmake(double r, double i) { return C{split(r), split(i)}; }
+    using V = D;
+    __device__ static V coord(double v) { return split(v); }
+    __device__ static V shfl(V v, int src) { return D{__shfl(v.hi, src), __shfl(v.lo, src)}; }
+    __device__ static Z make(V x, V y) { return Z{x, y}; }
+    __device__ static C cmake(V r, V i) { return C{r, i}; }
     __device__ static bool le4(D m) { return (m.hi < 4.0f) || (m.hi == 4.0f && m.lo <= 0.0f); }
     __device__ static bool inside(const Z& z) {
         return le4(add(mul(z.x, z.x), mul(z.y, z.y)));
@@ -204,11 +215,11 @@ __global__ __launch_bounds__(256) void jr_plain(PlainArgs p) {
         typename A::Z z;
         typename A::C c;
         if (p.mode == kModeMandelbrot) {
-            z = A::make(0.0, 0.0);
-            c = A::cmake(px, py);
+            z = A::make(A::coord(0.0), A::coord(0.0));
+            c = A::cmake(A::coord(px), A::coord(py));
         } else {
-            z = A::make(px, py);
-            c = A::cmake(p.cr, p.ci);
+            z = A::make(A::coord(px), A::coord(py));
+            c = A::cmake(A::coord(p.cr), A::coord(p.ci));
         }
         int n = 0;
         while (n < p.max_iter) {
@@ -220,7 +231,7 @@ __global__ __launch_bounds__(256) void jr_plain(PlainArgs p) {
 }
 
 // ---------------------------------------------------------------------------
-// Persistent kernel.
+// Tiled kernel: waves stream pixels from tiles with lane refill.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
@@ -235,119 +246,6 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-struct TileCtx {
-    int32_t* out;          // frame pixel (0, 0)
-    double cx, cy, hx, hy, cr, ci;
-    int W, H, max_iter, mode;
-    int col0, row0, tw, th;
-};
-
-// One tile of tw x th pixels, row-major inside the tile, processed by one
-// wave with lane refill.  Lane state: z (current iterate), zs (iterate at the
-// start of the running block), n (iterations done), and one of
-//   active   iterating a pixel,
-//   pending  escaped inside the last block, count found by replay,
-//   done     final count in cnt, store outstanding,
-//   idle     nothing.
-// Refill rounds run when at least `refill` lanes are not active or none is.
-template <class A, int K>
-__device__ void run_tile(const TileCtx& T, int refill) {
-    const int npix = T.tw * T.th;
-    const float rtw = 1.0f / (float)T.tw;
-    int next = 0;  // wave-uniform: first pixel of the tile not yet handed out
-    bool active = false, pending = false, done = false;
-    int n = 0, cnt = 0, off = 0;
-    typename A::Z z = A::make(0.0, 0.0);
-    typename A::Z zs = z;
-    typename A::C c = A::cmake(0.0, 0.0);
-
-    for (;;) {
-        const uint64_t busy = __ballot(active);
-        const int nidle = 64 - __popcll(busy);
-        if (nidle >= refill || busy == 0) {
-            if (K > 1 && __ballot(pending) != 0) {
-                if (pending) {
-                    // Replay the block from its saved start with a test on
-                    // every iteration.  The block-end test said |Z|^2 > 4 at
-                    // n + K, and escape is absorbing, so the first escaped
-                    // iterate lies in [n, n + K]; the cap may come first.
-                    z = zs;
-                    const int lim = min(K, T.max_iter - n);
-                    int j = 0;
-                    while (j < lim && A::check_step(z, c)) j++;
-                    cnt = n + j;
-                    done = true;
-                    pending = false;
-                }
-            }
-            if (done) {
-                T.out[off] = cnt;
-                done = false;
-            }
-            if (next < npix) {
-                const int k = next + lanes_below(~busy);
-                if (!active && k < npix) {
-                    int row = (int)((float)k * rtw);
-                    int col = k - row * T.tw;
-                    if (col < 0) { row -= 1; col += T.tw; }
-                    else if (col >= T.tw) { row += 1; col -= T.tw; }
-                    const int gi = T.col0 + col;
-                    const int gj = T.row0 + row;
-                    const double px = pixel_re(T.cx, T.hx, gi, T.W);
-                    const double py = pixel_im(T.cy, T.hy, gj, T.H);
-                    if (T.mode == kModeMandelbrot) {
-                        z = A::make(0.0, 0.0);
-                        c = A::cmake(px, py);
-                    } else {
-                        z = A::make(px, py);
-                        c = A::cmake(T.cr, T.ci);
-                    }
-                    n = 0;
-                    off = gj * T.W + gi;
-                    active = true;
-                }
-                next += nidle;
-            }
-            if (__ballot(active) == 0) break;
-        }
-        if (active) {
-            if (K == 1) {
-                const bool ok = A::check_step(z, c);
-                if (!ok || n >= T.max_iter) {
-                    cnt = n;
-                    done = true;
-                    active = false;
-                } else {
-                    n++;
-                }
-            } else {
-                zs = z;
-#pragma unroll
-                for (int u = 0; u < K; ++u) A::step(z, c);
-                if (!A::inside(z)) {
-                    pending = true;
-                    active = false;
-                } else {
-                    n += K;
-                    if (n >= T.max_iter) {  // no escape up to n >= cap: absorbing
-                        cnt = T.max_iter;
-                        done = true;
-                        active = false;
-                    }
-                }
-            }
-        }
-    }
-}
-
-template <class A, int K>
-__device__ __forceinline__ void run_frame_tile(const TileCtx& T, int defer, int refill) {
-    if (K > 1 && defer)
-        run_tile<A, K>(T, refill);
-    else
-        run_tile<A, 1>(T, refill);
-}
-
 __device__ __forceinline__ unsigned long long* queue_ctr(unsigned long long* ctr, int q) {
     return ctr + (size_t)q * kQueueStride;
 }
@@ -357,11 +255,75 @@ __device__ __forceinline__ int64_t queue_len(int64_t granules, int q) {
     return granules > q ? (granules - q + kQueues - 1) / kQueues : 0;
 }
 
-// Largest frame index f with frames[f].tile_begin <= t.  Tiles of one granule
-// are consecutive and a queue's granules increase, so a short forward scan
+// Hands out global tile indices to one wave.  Persistent mode: granules of
+// tiles from kQueues atomic counters; the wave starts on queue w % kQueues,
+// always holds the claim of its next granule in flight, and when its queue is
+// empty reads all counters at once (one per lane) and moves to the next queue
+// that still has granules.  Dispatch mode: the wave's own tile, once.
+struct Claimer {
+    unsigned long long raw;  // lane 0: result of the claim in flight
+    int64_t cur, end;        // remaining tiles of the current granule
+    int64_t qlen;
+    int q;
+    int wave;
+    bool started;
+};
+
+__device__ __forceinline__ void claimer_init(Claimer& cl, const PersistentArgs& a) {
+    // threadIdx.x / 64 is the same for the whole wave; readfirstlane tells the
+    // compiler so, which keeps the claimer and the tile state in SGPRs.
+    cl.wave = blockIdx.x * (blockDim.x / 64) +
+              (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    cl.cur = cl.end = 0;
+    cl.started = false;
+    cl.raw = 0;
+    cl.q = cl.wave % kQueues;
+    cl.qlen = queue_len(a.granules, cl.q);
+    if (a.persistent && lane_id() == 0) cl.raw = atomicAdd(queue_ctr(a.ctr, cl.q), 1ull);
+}
+
+__device__ __forceinline__ int64_t next_tile(Claimer& cl, const PersistentArgs& a) {
+    if (!a.persistent) {
+        if (cl.started) return -1;
+        cl.started = true;
+        return cl.wave < a.total_tiles ? (int64_t)cl.wave : -1;
+    }
+    if (cl.cur < cl.end) return cl.cur++;
+    for (;;) {
+        const int64_t j = uniform64((int64_t)cl.raw);
+        if (j < cl.qlen) {
+            if (lane_id() == 0) cl.raw = atomicAdd(queue_ctr(a.ctr, cl.q), 1ull);
+            const int64_t t0 = (j * kQueues + cl.q) * (int64_t)a.granule;
+            cl.cur = t0 + 1;
+            cl.end = min(t0 + (int64_t)a.granule, a.total_tiles);
+            return t0;
+        }
+        bool has = false;
+        if (lane_id() < kQueues) {
+            const unsigned long long c = __hip_atomic_load(
+                queue_ctr(a.ctr, lane_id()), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            has = (int64_t)c < queue_len(a.granules, lane_id());
+        }
+        const uint64_t m = __ballot(has);
+        if (m == 0) return -1;
+        const int s = (cl.q + 1) & (kQueues - 1);
+        const uint64_t rot = s ? ((m >> s) | (m << (64 - s))) : m;
+        cl.q = (s + __builtin_ctzll(rot)) & (kQueues - 1);
+        cl.qlen = queue_len(a.granules, cl.q);
+        if (lane_id() == 0) cl.raw = atomicAdd(queue_ctr(a.ctr, cl.q), 1ull);
+    }
+}
+
+// The frame table is read-only during a launch.  Reading it through the
+// constant address space lets the compiler use scalar loads (the table index
+// is wave-uniform), which it cannot prove safe through a generic pointer that
+// might alias the output.
+typedef const __attribute__((address_space(4))) DevFrame CFrame;
+__device__ __forceinline__ CFrame* cframes(const DevFrame* p) { return (CFrame*)p; }
+
+// Largest frame index f with frames[f].tile_begin <= t.  A short forward scan
 // from the previous frame usually ends it; otherwise binary search.
-__device__ __forceinline__ int find_frame(const DevFrame* __restrict__ frames, int nframes,
-                                          int64_t t, int f) {
+__device__ __forceinline__ int find_frame(CFrame* frames, int nframes, int64_t t, int f) {
     if (frames[f].tile_begin <= t) {
 #pragma unroll 1
         for (int s = 0; s < 4; ++s) {
@@ -382,68 +344,210 @@ __device__ __forceinline__ int find_frame(const DevFrame* __restrict__ frames, i
     return lo;
 }
 
-template <int K, int DTMASK>
-__device__ __forceinline__ void run_global_tile(const PersistentArgs& a, int f, int64_t t) {
-    const DevFrame& F = a.frames[f];
-    const int64_t local = t - F.tile_begin;
-    const int ty = (int)(local / F.tiles_x);
-    const int tx = (int)(local - (int64_t)ty * F.tiles_x);
-    TileCtx T;
-    T.out = a.out_base + F.out_offset;
-    T.cx = F.cx; T.cy = F.cy; T.hx = F.hx; T.hy = F.hy; T.cr = F.cr; T.ci = F.ci;
-    T.W = F.width; T.H = F.height; T.max_iter = F.max_iter; T.mode = F.mode;
-    T.col0 = tx * F.tile_w;
-    T.row0 = F.row_begin + ty * F.tile_h;
-    T.tw = min(F.tile_w, F.width - T.col0);
-    T.th = min(F.tile_h, F.row_end - T.row0);
-    const int dt = F.dtype;
-    if ((DTMASK & (1 << kFP32)) && dt == kFP32)
-        run_frame_tile<ArF32, K>(T, F.defer, a.refill);
-    else if ((DTMASK & (1 << kFP64)) && dt == kFP64)
-        run_frame_tile<ArF64, K>(T, F.defer, a.refill);
-    else if ((DTMASK & (1 << kFF)) && dt == kFF)
-        run_frame_tile<ArFF, K>(T, F.defer, a.refill);
+// The tile that lanes currently refill from (wave-uniform).  Kept small: it
+// lives in scalar registers for the whole stream.
+struct Src {
+    int64_t t;          // global tile index, -1: none left
+    int f;              // its frame
+    int variant;        // stream variant the tile needs (variant_of)
+    int32_t* out;       // count of the tile's pixel (0, 0)
+    int W, max_iter, mode;
+    int tw, npix, next;
+    uint32_t magic;     // k / tw == (k * magic) >> 18 for k < 4096, tw <= 64
+};
+
+// Which stream variant a frame needs: its dtype, and whether the blocked test
+// may be used (escape absorbing, |C| <= 1.9) or every iteration is tested.
+__device__ __forceinline__ int variant_of(int dtype, int absorbing) {
+    return dtype * 2 + (absorbing ? 1 : 0);
 }
 
-// Persistent workgroups of 256 threads: 4 independent waves.  Wave w starts on
-// queue w % kQueues and always holds one claim in flight (the atomic for the
-// next granule is issued before the current one is computed).  When its queue
-// is empty, the wave reads all kQueues counters at once (one per lane) and
-// moves to the next queue that still has granules; it leaves when none has.
-template <int K, int DTMASK>
-__global__ __launch_bounds__(256) void jr_persistent(PersistentArgs a) {
+// Makes tile t the refill source.  Lane L receives the binary64 coordinate of
+// the tile's column L (xd) and row L (yd), and every lane the frame's C.
+__device__ __forceinline__ void load_src(Src& s, const PersistentArgs& a, int64_t t,
+                                         double& xd, double& yd, double& cr, double& ci) {
+    s.t = t;
+    if (t < 0) return;
+    CFrame* frames = cframes(a.frames);
+    s.f = find_frame(frames, a.nframes, t, s.f);
+    CFrame& F = frames[s.f];
+    const uint32_t local = (uint32_t)(t - F.tile_begin);  // < 2^31 tiles per frame
+    const int ty = (int)(local / (uint32_t)F.tiles_x);
+    const int tx = (int)(local - (uint32_t)ty * (uint32_t)F.tiles_x);
+    const int col0 = tx * F.tile_w;
+    const int row0 = F.row_begin + ty * F.tile_h;
+    const int th = min(F.tile_h, F.row_end - row0);
+    s.variant = variant_of(F.dtype, F.defer);
+    s.W = F.width;
+    s.max_iter = F.max_iter;
+    s.mode = F.mode;
+    s.tw = min(F.tile_w, F.width - col0);
+    s.npix = s.tw * th;
+    s.next = 0;
+    s.magic = ((1u << 18) + (uint32_t)s.tw - 1u) / (uint32_t)s.tw;
+    s.out = a.out_base + F.out_offset + ((int64_t)row0 * F.width + col0);
     const int lane = lane_id();
-    const int wave = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-    int q = wave % kQueues;
-    int64_t qlen = queue_len(a.granules, q);
-    unsigned long long raw = 0;
-    if (lane == 0) raw = atomicAdd(queue_ctr(a.ctr, q), 1ull);
-    int f = 0;
+    xd = pixel_re(F.cx, F.hx, col0 + min(lane, s.tw - 1), F.width);
+    yd = pixel_im(F.cy, F.hy, row0 + min(lane, th - 1), F.height);
+    cr = F.cr;
+    ci = F.ci;
+}
+
+// Streams pixels through one wave while the tiles handed out need this
+// variant (A, absorbing or not).  Lane state: z (iterate), zs (iterate at the
+// start of a deferred block), n (iterations done), mi (cap of the pixel's
+// frame), outp (where its count goes), and one of
+//   active   iterating,
+//   pending  escaped inside a deferred block; count found by replay,
+//   done     final count in cnt, store outstanding,
+//   idle     nothing.
+// Blocks of K iterations run without branches:
+//   DEFER = 0: every iterate is tested and the leading non-escaped iterates
+//     are counted (lead += |Z|^2 <= 4).  Escape being absorbing, the first
+//     escaped iterate is n + lead.  With K = 1 this is the exact test on every
+//     iteration and needs no absorbing property.
+//   DEFER = 1: the K steps run untested and only the last iterate is tested;
+//     lanes found escaped replay the block from zs with the counted test.
+// A refill round runs when at least `refill` lanes are not active (or none
+// is): pending lanes are resolved, finished lanes store, idle lanes take the
+// next pixels of the tile, and of the following tiles when it runs out.
+// Returns when the next tile needs another variant (left in s) or none is left.
+template <class A, int K, int DEFER>
+__device__ void run_stream(Src& s, Claimer& cl, const PersistentArgs& a, double xd, double yd,
+                           double crd, double cid) {
+    using V = typename A::V;
+    const int my_variant = s.variant;
+    const V zero = A::coord(0.0);
+    V xcol = A::coord(xd), yrow = A::coord(yd);
+    V cre = A::coord(crd), cim = A::coord(cid);
+    bool src_ok = true;
+    bool active = false, pending = false, done = false;
+    int n = 0, cnt = 0, mi = 0;
+    int32_t* outp = s.out;
+    typename A::Z z = A::make(zero, zero);
+    typename A::Z zs = z;
+    typename A::C c = A::cmake(zero, zero);
+
     for (;;) {
-        const int64_t j = uniform64((int64_t)raw);
-        if (j >= qlen) {
-            bool has = false;
-            if (lane < kQueues) {
-                const unsigned long long c = __hip_atomic_load(
-                    queue_ctr(a.ctr, lane), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                has = (int64_t)c < queue_len(a.granules, lane);
+        uint64_t busy = __ballot(active);
+        if (64 - __popcll(busy) >= a.refill || busy == 0) {
+            if (DEFER && __ballot(pending) != 0) {
+                if (pending) {
+                    z = zs;
+                    int lead = 0;
+#pragma unroll
+                    for (int u = 0; u < K; ++u) lead += A::check_step(z, c) ? 1 : 0;
+                    cnt = min(n + lead, mi);
+                    done = true;
+                    pending = false;
+                }
             }
-            const uint64_t m = __ballot(has);
-            if (m == 0) break;
-            const int s = (q + 1) & (kQueues - 1);
-            const uint64_t rot = s ? ((m >> s) | (m << (64 - s))) : m;
-            q = (s + __builtin_ctzll(rot)) & (kQueues - 1);
-            qlen = queue_len(a.granules, q);
-            if (lane == 0) raw = atomicAdd(queue_ctr(a.ctr, q), 1ull);
-            continue;
+            if (done) {
+                *outp = cnt;
+                done = false;
+            }
+            uint64_t idle = ~busy;
+            while (idle != 0 && src_ok) {
+                const int k = s.next + lanes_below(idle);
+                const int kk = min(k, s.npix - 1);
+                const int row = (int)(((uint32_t)kk * s.magic) >> 18);
+                const int col = kk - row * s.tw;
+                const V x0 = A::shfl(xcol, col);
+                const V y0 = A::shfl(yrow, row);
+                if (!active && k < s.npix) {
+                    if (s.mode == kModeMandelbrot) {
+                        z = A::make(zero, zero);
+                        c = A::cmake(x0, y0);
+                    } else {
+                        z = A::make(x0, y0);
+                        c = A::cmake(cre, cim);
+                    }
+                    n = 0;
+                    mi = s.max_iter;
+                    outp = s.out + (row * s.W + col);
+                    active = true;
+                }
+                s.next += __popcll(idle);
+                if (s.next >= s.npix) {
+                    load_src(s, a, next_tile(cl, a), xd, yd, crd, cid);
+                    if (s.t < 0 || s.variant != my_variant) {
+                        src_ok = false;
+                    } else {
+                        xcol = A::coord(xd);
+                        yrow = A::coord(yd);
+                        cre = A::coord(crd);
+                        cim = A::coord(cid);
+                    }
+                }
+                idle = ~__ballot(active);
+            }
+            busy = __ballot(active);
+            if (busy == 0) return;
         }
-        if (lane == 0) raw = atomicAdd(queue_ctr(a.ctr, q), 1ull);  // next claim, in flight
-        const int64_t t0 = (j * kQueues + q) * (int64_t)a.granule;
-        const int64_t t1 = min(t0 + (int64_t)a.granule, a.total_tiles);
-        for (int64_t t = t0; t < t1; ++t) {
-            f = find_frame(a.frames, a.nframes, t, f);
-            run_global_tile<K, DTMASK>(a, f, t);
+        if (active) {
+            if (DEFER) {
+                zs = z;
+#pragma unroll
+                for (int u = 0; u < K; ++u) A::step(z, c);
+                if (!A::inside(z)) {
+                    pending = true;
+                    active = false;
+                } else {
+                    n += K;
+                    if (n >= mi) {  // no escape up to n >= cap (absorbing)
+                        cnt = mi;
+                        done = true;
+                        active = false;
+                    }
+                }
+            } else {
+                int lead = 0;
+#pragma unroll
+                for (int u = 0; u < K; ++u) lead += A::check_step(z, c) ? 1 : 0;
+                if (lead < K) {
+                    cnt = min(n + lead, mi);
+                    done = true;
+                    active = false;
+                } else {
+                    n += K;
+                    if (n >= mi) {
+                        cnt = mi;
+                        done = true;
+                        active = false;
+                    }
+                }
+            }
         }
+    }
+}
+
+// Persistent (or one-wave-per-tile) kernel over a table of frames: 256-thread
+// workgroups of 4 independent waves.  Each wave takes tiles from its Claimer
+// and hands them to the stream of the variant they need.
+template <int K, int DEFER, int DTMASK>
+__global__ __launch_bounds__(256) void jr_tiled(PersistentArgs a) {
+    Claimer cl;
+    claimer_init(cl, a);
+    Src s;
+    s.f = 0;
+    double xd, yd, cr, ci;
+    load_src(s, a, next_tile(cl, a), xd, yd, cr, ci);
+    while (s.t >= 0) {
+        const int v = s.variant;
+        if ((DTMASK & (1 << kFP32)) && v == variant_of(kFP32, 1))
+            run_stream<ArF32, K, DEFER>(s, cl, a, xd, yd, cr, ci);
+        else if ((DTMASK & (1 << kFP32)) && v == variant_of(kFP32, 0))
+            run_stream<ArF32, 1, 0>(s, cl, a, xd, yd, cr, ci);
+        else if ((DTMASK & (1 << kFP64)) && v == variant_of(kFP64, 1))
+            run_stream<ArF64, K, DEFER>(s, cl, a, xd, yd, cr, ci);
+        else if ((DTMASK & (1 << kFP64)) && v == variant_of(kFP64, 0))
+            run_stream<ArF64, 1, 0>(s, cl, a, xd, yd, cr, ci);
+        else if ((DTMASK & (1 << kFF)) && v == variant_of(kFF, 1))
+            run_stream<ArFF, K, DEFER>(s, cl, a, xd, yd, cr, ci);
+        else if ((DTMASK & (1 << kFF)) && v == variant_of(kFF, 0))
+            run_stream<ArFF, 1, 0>(s, cl, a, xd, yd, cr, ci);
+        else
+            load_src(s, a, next_tile(cl, a), xd, yd, cr, ci);  // not reached
     }
 }
 
@@ -456,35 +560,49 @@ __global__ void jr_reset_queues(unsigned long long* ctr) {
 }  // namespace jr
 
 // ---------------------------------------------------------------------------
-// Launch helpers used by the host runtime (julia_host.hip).
+// Launch helpers used by the host runtime (julia_host.cpp).
 // ---------------------------------------------------------------------------
 namespace jr {
 
-using PersistentFn = void (*)(PersistentArgs);
+using TiledFn = void (*)(PersistentArgs);
 
-template <int K>
-static PersistentFn pick_mask(int dtmask) {
+template <int K, int DEFER>
+static TiledFn pick_mask(int dtmask) {
     switch (dtmask) {
-        case 1 << kFP64: return jr_persistent<K, 1 << kFP64>;
-        case 1 << kFP32: return jr_persistent<K, 1 << kFP32>;
-        case 1 << kFF: return jr_persistent<K, 1 << kFF>;
-        default: return jr_persistent<K, 7>;
+        case 1 << kFP64: return jr_tiled<K, DEFER, 1 << kFP64>;
+        case 1 << kFP32: return jr_tiled<K, DEFER, 1 << kFP32>;
+        case 1 << kFF: return jr_tiled<K, DEFER, 1 << kFF>;
+        default: return jr_tiled<K, DEFER, 7>;
     }
 }
 
-hipError_t launch_persistent(int unroll, int dtmask, int blocks, const PersistentArgs& args,
-                             hipStream_t stream) {
-    PersistentFn fn;
-    switch (unroll) {
-        case 1: fn = pick_mask<1>(dtmask); break;
-        case 4: fn = pick_mask<4>(dtmask); break;
-        case 8: fn = pick_mask<8>(dtmask); break;
-        case 16: fn = pick_mask<16>(dtmask); break;
-        default: return hipErrorInvalidValue;
+static TiledFn pick(int unroll, int defer, int dtmask) {
+    if (defer) {
+        switch (unroll) {
+            case 4: return pick_mask<4, 1>(dtmask);
+            case 8: return pick_mask<8, 1>(dtmask);
+            case 16: return pick_mask<16, 1>(dtmask);
+            default: return nullptr;
+        }
     }
-    hipLaunchKernelGGL(jr_reset_queues, dim3(1), dim3(kQueues), 0, stream, args.ctr);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    switch (unroll) {
+        case 1: return pick_mask<1, 0>(dtmask);
+        case 2: return pick_mask<2, 0>(dtmask);
+        case 4: return pick_mask<4, 0>(dtmask);
+        case 8: return pick_mask<8, 0>(dtmask);
+        default: return nullptr;
+    }
+}
+
+hipError_t launch_tiled(int unroll, int defer, int dtmask, int blocks, const PersistentArgs& args,
+                        hipStream_t stream) {
+    TiledFn fn = pick(unroll, defer, dtmask);
+    if (!fn) return hipErrorInvalidValue;
+    if (args.persistent) {
+        hipLaunchKernelGGL(jr_reset_queues, dim3(1), dim3(kQueues), 0, stream, args.ctr);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), 0, stream, args);
     return hipGetLastError();
 }

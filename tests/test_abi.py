@@ -102,13 +102,15 @@ def test_check_frames():
 
 
 @pytest.mark.parametrize("field,value", [
-    ("tile_w", 0), ("tile_w", 5000), ("tile_h", 0), ("tile_h", 100000), ("unroll", 2),
-    ("unroll", 32), ("refill", 0), ("refill", 65), ("waves_per_cu", 2),
-    ("waves_per_cu", 6), ("waves_per_cu", 36),
+    ("tile_w", 0), ("tile_w", 65), ("tile_h", 0), ("tile_h", 65), ("unroll", 3),
+    ("unroll", 16), ("unroll", 32), ("defer", 2), ("refill", 0), ("refill", 65),
+    ("persistent", 2), ("waves_per_cu", 2), ("waves_per_cu", 6), ("waves_per_cu", 36),
 ])
 def test_check_schedule_rejects(field, value):
     s = jr.Schedule()
     assert jr.check_schedule(s) == jr.JR_OK
+    assert jr.check_schedule(jr.Schedule(unroll=16, defer=1)) == jr.JR_OK
+    assert jr.check_schedule(jr.Schedule(unroll=2, defer=1)) == jr.JR_EINVAL
     bad = jr.Schedule(**{**s.__dict__, field: value})
     assert jr.check_schedule(bad) == jr.JR_EINVAL
 
@@ -118,7 +120,7 @@ def test_default_schedules_are_valid_and_settable():
         s = jr.default_schedule(dt)
         assert jr.check_schedule(s) == jr.JR_OK
     old = jr.default_schedule("fp32")
-    new = jr.Schedule(32, 8, 8, 8, 24, "table")
+    new = jr.Schedule(32, 8, 8, 1, 8, 1, 24, "table")
     jr.set_default_schedule("fp32", new)
     assert jr.default_schedule("fp32") == new
     jr.set_default_schedule("fp32", old)

@@ -20,13 +20,16 @@ import paper_1611_03079_amd as jr  # noqa: E402
 UNIT = (-1.5, 1.5, -1.5, 1.5)
 C1 = complex(-0.8, 0.156)
 
+# tile_w, tile_h, unroll, defer, refill, persistent, waves_per_cu, order
 SCHEDULES = [
-    jr.Schedule(64, 16, 1, 16, 16, "cost"),
-    jr.Schedule(64, 16, 4, 16, 16, "cost"),
-    jr.Schedule(64, 8, 8, 1, 8, "table"),
-    jr.Schedule(32, 4, 16, 64, 32, "cost"),
-    jr.Schedule(13, 7, 4, 5, 4, "table"),   # ragged tiles, few waves
-    jr.Schedule(8, 8, 8, 32, 16, "cost"),
+    jr.Schedule(64, 16, 1, 0, 16, 1, 16, "cost"),
+    jr.Schedule(64, 16, 4, 0, 16, 1, 16, "cost"),
+    jr.Schedule(64, 8, 8, 1, 1, 1, 8, "table"),
+    jr.Schedule(32, 4, 16, 1, 64, 1, 32, "cost"),
+    jr.Schedule(13, 7, 4, 1, 5, 1, 4, "table"),   # ragged tiles, few waves
+    jr.Schedule(8, 8, 8, 0, 32, 0, 16, "cost"),   # one wave per tile
+    jr.Schedule(64, 64, 2, 0, 48, 0, 16, "table"),
+    jr.Schedule(1, 1, 1, 0, 1, 1, 4, "cost"),     # one-pixel tiles
 ]
 
 
@@ -97,7 +100,7 @@ def test_special_constants(c, dtype):
     """|C| > 1.9 runs without deferred tests; C = -2, 1/4, i have exact orbits."""
     win = (-2.1, 2.1, -0.9, 0.9)
     W, H = 81, 41  # odd: the centre row is y = 0 exactly
-    for s in (SCHEDULES[1], SCHEDULES[3]):
+    for s in (SCHEDULES[1], SCHEDULES[3], SCHEDULES[5]):
         f = Frame(c, win, W, H, 500, dtype)
         _, views = batch([f], s)
         np.testing.assert_array_equal(views[0], ref(f))
@@ -106,7 +109,7 @@ def test_special_constants(c, dtype):
 @pytest.mark.parametrize("dtype", ["fp64", "fp32", "ff"])
 def test_cap_edge_cases(dtype):
     for it in (0, 1, 2, 3, 5, 17):
-        for s in (SCHEDULES[0], SCHEDULES[3]):
+        for s in (SCHEDULES[0], SCHEDULES[3], SCHEDULES[6]):
             f = Frame(C1, UNIT, 37, 29, it, dtype)
             _, views = batch([f], s)
             np.testing.assert_array_equal(views[0], ref(f))
@@ -162,7 +165,7 @@ def test_row_ranges():
 
 def test_plan_launch_and_graph_replay():
     frames = wl.parameter_path(n=8, width=240, height=135)
-    plan = jr.Plan(frames, jr.Schedule(64, 16, 4, 16, 16, "cost"))
+    plan = jr.Plan(frames, jr.Schedule(64, 16, 4, 0, 16, 1, 16, "cost"))
     want = [oracle.render(f.c, f.window, f.width, f.height, f.max_iter, f.dtype) for f in frames]
     plan.arena.fill_(-1)
     plan.launch()
