@@ -411,10 +411,11 @@ __device__ __forceinline__ void load_src(Src& s, const PersistentArgs& a, int64_
 // A refill round runs when at least `refill` lanes are not active (or none
 // is): pending lanes are resolved, finished lanes store, idle lanes take the
 // next pixels of the tile, and of the following tiles when it runs out.
-// Returns when the next tile needs another variant (left in s) or none is left.
+// Returns when the next tile needs another variant (left in s, its coordinate
+// tables in xd, yd and its constant in crd, cid) or none is left.
 template <class A, int K, int DEFER>
-__device__ void run_stream(Src& s, Claimer& cl, const PersistentArgs& a, double xd, double yd,
-                           double crd, double cid) {
+__device__ void run_stream(Src& s, Claimer& cl, const PersistentArgs& a, double& xd, double& yd,
+                           double& crd, double& cid) {
     using V = typename A::V;
     const int my_variant = s.variant;
     const V zero = A::coord(0.0);
