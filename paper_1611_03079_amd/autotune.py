@@ -137,3 +137,42 @@ def apply_cache(cache: Dict[str, dict], max_iter: int = 100, pixels: int = 1 << 
         s = lookup(cache, dt, max_iter, pixels)
         if s is not None:
             jr.set_default_schedule(dt, s)
+
+
+# ------------------------------------------------------------------ command line
+def standard_workloads():
+    """Representative batches of the workloads the library is tuned for."""
+    import workloads as wl
+    return {
+        "parameter_path_fp32": wl.parameter_path(),
+        "single_4096_fp32": [wl.single_4096(s, it, "fp32") for it in (100, 1000) for s in range(2)],
+        "single_4096_fp64": [wl.single_4096(s, it, "fp64") for it in (100, 1000) for s in range(2)],
+        "single_512_fp64": [wl.single_512("fp64")],
+        "uneven_fp32_ff": wl.uneven_batch(0, n=16),
+        "cardioid_path_fp32": wl.cardioid_path(64),
+    }
+
+
+def main(argv=None):
+    import argparse
+    import torch
+    p = argparse.ArgumentParser(description="tune schedules and write the cache")
+    p.add_argument("--out", default=DEFAULT_CACHE)
+    p.add_argument("--only", nargs="*")
+    p.add_argument("--reps", type=int, default=3)
+    args = p.parse_args(argv)
+    torch.cuda.set_device(0)
+    cache = load_cache(args.out)
+    for name, frames in standard_workloads().items():
+        if args.only and name not in args.only:
+            continue
+        best, ms, log = tune(frames, reps=args.reps)
+        record(cache, frames, best, ms)
+        cache.setdefault("_workloads", {})[name] = {"schedule": asdict(best), "ms": ms,
+                                                    "candidates": len(log)}
+        print("%-22s %9.4f ms  %s" % (name, ms, best), flush=True)
+        save_cache(cache, args.out)
+
+
+if __name__ == "__main__":
+    main()

@@ -396,21 +396,23 @@ __device__ __forceinline__ void load_src(Src& s, const PersistentArgs& a, int64_
 // Streams pixels through one wave while the tiles handed out need this
 // variant (A, absorbing or not).  Lane state: z (iterate), zs (iterate at the
 // start of a deferred block), n (iterations done), mi (cap of the pixel's
-// frame), outp (where its count goes), and one of
-//   active   iterating,
-//   pending  escaped inside a deferred block; count found by replay,
-//   done     final count in cnt, store outstanding,
-//   idle     nothing.
-// Blocks of K iterations run without branches:
+// frame), outp (where its count goes), and three flags:
+//   it  the lane iterates an unfinished pixel,
+//   pe  (DEFER) it escaped inside the last block; the count needs a replay,
+//   fi  its final count is in cnt and not yet stored.
+// Blocks of K iterations run on every lane (a lane that is not iterating
+// computes values nobody reads), and the bookkeeping after a block is
+// selects, so a block costs vector instructions and few scalar ones.  A
+// counted block ends early once every iterating lane has escaped.
 //   DEFER = 0: every iterate is tested and the leading non-escaped iterates
 //     are counted (lead += |Z|^2 <= 4).  Escape being absorbing, the first
 //     escaped iterate is n + lead.  With K = 1 this is the exact test on every
 //     iteration and needs no absorbing property.
 //   DEFER = 1: the K steps run untested and only the last iterate is tested;
 //     lanes found escaped replay the block from zs with the counted test.
-// A refill round runs when at least `refill` lanes are not active (or none
-// is): pending lanes are resolved, finished lanes store, idle lanes take the
-// next pixels of the tile, and of the following tiles when it runs out.
+// A refill round runs when at least `refill` lanes are not iterating (or no
+// lane is): replays are resolved, finished lanes store, and free lanes take
+// the next pixels of the tile, and of the following tiles when it runs out.
 // Returns when the next tile needs another variant (left in s, its coordinate
 // tables in xd, yd and its constant in crd, cid) or none is left.
 template <class A, int K, int DEFER>
@@ -422,32 +424,33 @@ __device__ void run_stream(Src& s, Claimer& cl, const PersistentArgs& a, double&
     V xcol = A::coord(xd), yrow = A::coord(yd);
     V cre = A::coord(crd), cim = A::coord(cid);
     bool src_ok = true;
-    bool active = false, pending = false, done = false;
+    bool it = false, pe = false, fi = false;
     int n = 0, cnt = 0, mi = 0;
     int32_t* outp = s.out;
     typename A::Z z = A::make(zero, zero);
     typename A::Z zs = z;
     typename A::C c = A::cmake(zero, zero);
+    uint64_t running = 0;  // wave-uniform: ballot(it)
 
     for (;;) {
-        uint64_t busy = __ballot(active);
-        if (64 - __popcll(busy) >= a.refill || busy == 0) {
-            if (DEFER && __ballot(pending) != 0) {
-                if (pending) {
-                    z = zs;
-                    int lead = 0;
+        if (64 - __popcll(running) >= a.refill || running == 0) {
+            if (DEFER && __ballot(pe) != 0) {
+                // replay the last block from its start, on every lane
+                typename A::Z zr = zs;
+                int lead = 0;
 #pragma unroll
-                    for (int u = 0; u < K; ++u) lead += A::check_step(z, c) ? 1 : 0;
+                for (int u = 0; u < K; ++u) lead += A::check_step(zr, c) ? 1 : 0;
+                if (pe) {
                     cnt = min(n + lead, mi);
-                    done = true;
-                    pending = false;
+                    fi = true;
+                    pe = false;
                 }
             }
-            if (done) {
+            if (fi) {
                 *outp = cnt;
-                done = false;
+                fi = false;
             }
-            uint64_t idle = ~busy;
+            uint64_t idle = ~running;
             while (idle != 0 && src_ok) {
                 const int k = s.next + lanes_below(idle);
                 const int kk = min(k, s.npix - 1);
@@ -455,7 +458,7 @@ __device__ void run_stream(Src& s, Claimer& cl, const PersistentArgs& a, double&
                 const int col = kk - row * s.tw;
                 const V x0 = A::shfl(xcol, col);
                 const V y0 = A::shfl(yrow, row);
-                if (!active && k < s.npix) {
+                if (!it && k < s.npix) {
                     if (s.mode == kModeMandelbrot) {
                         z = A::make(zero, zero);
                         c = A::cmake(x0, y0);
@@ -466,7 +469,7 @@ __device__ void run_stream(Src& s, Claimer& cl, const PersistentArgs& a, double&
                     n = 0;
                     mi = s.max_iter;
                     outp = s.out + (row * s.W + col);
-                    active = true;
+                    it = true;
                 }
                 s.next += __popcll(idle);
                 if (s.next >= s.npix) {
@@ -480,45 +483,41 @@ __device__ void run_stream(Src& s, Claimer& cl, const PersistentArgs& a, double&
                         cim = A::coord(cid);
                     }
                 }
-                idle = ~__ballot(active);
+                idle = ~__ballot(it);
             }
-            busy = __ballot(active);
-            if (busy == 0) return;
+            running = __ballot(it);
+            if (running == 0) return;
         }
-        if (active) {
-            if (DEFER) {
-                zs = z;
+        if (DEFER) {
+            zs = pe ? zs : z;  // a lane waiting for its replay keeps its block start
 #pragma unroll
-                for (int u = 0; u < K; ++u) A::step(z, c);
-                if (!A::inside(z)) {
-                    pending = true;
-                    active = false;
-                } else {
-                    n += K;
-                    if (n >= mi) {  // no escape up to n >= cap (absorbing)
-                        cnt = mi;
-                        done = true;
-                        active = false;
-                    }
-                }
-            } else {
-                int lead = 0;
+            for (int u = 0; u < K; ++u) A::step(z, c);
+            const bool esc = !A::inside(z);
+            const bool capped = n + K >= mi;  // no escape up to n + K >= cap: absorbing
+            cnt = (it && !esc && capped) ? mi : cnt;
+            fi = fi || (it && !esc && capped);
+            pe = pe || (it && esc);
+            it = it && !esc && !capped;
+            n += K;
+            n -= (pe && !it) ? K : 0;  // a lane to replay keeps n at the block start
+        } else {
+            int lead = 0;
 #pragma unroll
-                for (int u = 0; u < K; ++u) lead += A::check_step(z, c) ? 1 : 0;
-                if (lead < K) {
-                    cnt = min(n + lead, mi);
-                    done = true;
-                    active = false;
-                } else {
-                    n += K;
-                    if (n >= mi) {
-                        cnt = mi;
-                        done = true;
-                        active = false;
-                    }
-                }
+            for (int u = 0; u < K; ++u) {
+                const bool ok = A::check_step(z, c);
+                lead += ok ? 1 : 0;
+                // every iterating lane has escaped: the block can end here
+                // (each lane's lead is already final)
+                if (u + 1 < K && __ballot(ok && it) == 0) break;
             }
+            const bool stop = (lead < K) || (n + K >= mi);
+            const int final_cnt = min(n + lead, mi);
+            cnt = (it && stop) ? final_cnt : cnt;
+            fi = fi || (it && stop);
+            it = it && !stop;
+            n += K;
         }
+        running = __ballot(it);
     }
 }
 

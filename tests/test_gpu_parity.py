@@ -146,6 +146,24 @@ def test_mixed_batch_one_launch(sched):
     assert (arena[~covered] == -7).all()
 
 
+@pytest.mark.parametrize("sched", [jr.Schedule(4, 4, 4, 0, 16, 1, 4, "table"),
+                                   jr.Schedule(8, 2, 8, 1, 8, 1, 4, "table"),
+                                   jr.Schedule(3, 5, 2, 0, 64, 0, 16, "table")])
+def test_variant_switches_inside_a_wave(sched):
+    """Frames alternate dtype, mode and absorbing/non-absorbing C in table order
+    with small tiles, so a wave's stream changes variant many times."""
+    cs = [complex(-0.8, 0.156), complex(2.2, 0.1), complex(0.3, -0.5), complex(-1.95, 0.05)]
+    frames = []
+    for k in range(36):
+        dt = ("fp64", "fp32", "ff")[k % 3]
+        mode = "mandelbrot" if k % 5 == 4 else "julia"
+        win = (-2.1, 1.0, -1.2, 1.1) if mode == "mandelbrot" else (-1.7, 1.6, -1.3, 1.2)
+        frames.append(Frame(cs[k % 4], win, 23 + k, 17 + (k % 7), 40 + 13 * k, dt, mode))
+    _, views = batch(frames, sched)
+    for f, v in zip(frames, views):
+        np.testing.assert_array_equal(v, ref(f))
+
+
 def test_batch_equals_single_renders():
     frames = [Frame(c, UNIT, 120, 90, 100, dt) for c in (C1, complex(0.3, 0.02), complex(-1.0, 0.25))
               for dt in ("fp64", "fp32", "ff")]
