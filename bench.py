@@ -1,21 +1,25 @@
 """Benchmark of the escape-time hot path on one MI355X.
 
-Workload (a step): the single-image 4096x4096 configuration -- window
-[-1.6, 1.6]^2, C = 0.7885 exp(i theta) with theta from seeds 0..3, caps 100
-and 1000 -- rendered in FP32 with the tuned persistent kernel, one launch per
-image (8 images per step).  Inputs are synthetic and live in HBM before the
-timed region; nothing leaves the device inside it.
+Workload (one step): the batched parameter path -- 256 frames of 1920x1080,
+C_k = 0.7885 exp(2 pi i k / 256), window Re[-1.78, 1.78] x Im[-1, 1], cap 100,
+FP32 -- rendered in ONE launch of the tiled kernel with the autotuned schedule,
+replayed from a captured hipGraph.  This is the batched form the throughput
+target is quoted on.  Inputs are synthetic and resident in HBM before the timed
+region; nothing leaves the device inside it.
 
 Metric: useful pixel-iterations per second (sum of the output counts over the
-step / step time), in Gpixel-iter/s.  One pixel-iteration is 8 flops
-(x^2, y^2, x^2+y^2, x^2-y^2, +Re C, 2x, (2x)y, +Im C).
+step / step time), in Gpixel-iter/s.  A pixel-iteration is 8 flops (x^2, y^2,
+x^2+y^2, x^2-y^2, +Re C, 2x, (2x)y, +Im C); 4 bytes are written per pixel and
+nothing is read.
 
-The JSON line also carries the roofline of the dominant kernel (useful FLOP/s
-of the persistent kernel from HIP events around each launch, against the
-vector FP32 peak), the single-threaded CPU oracle on a bounded sample of the
-same workload, and further legs in "extra": FP64, the plain one-thread-per-
-pixel kernel on the same images, the 256-frame 1920x1080 parameter path in
-one persistent launch, and the 512x512 FP64 image's latency.
+The JSON line also carries the roofline of the kernel (HIP events around each
+launch on the stream it runs on), the single-threaded CPU oracle on a bounded
+sample of the same workload, and further legs in "extra": the plain
+one-thread-per-pixel kernel on the same frames, the persistent-queue mode, the
+single 4096x4096 images in FP32 and FP64, the 512x512 FP64 image's latency,
+an uneven batch (FP32 + float-float, one launch), the serving loop's p50/p99
+latency under Poisson arrivals, and the FP32 / float-float pixel fractions that
+differ from FP64.
 """
 import argparse
 import json
@@ -26,10 +30,18 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (256 CU x 2.4 GHz x 256 flop/clk)
-PEAK_FP64_TFLOPS = 78.6    # MI355X vector FP64 (256 CU x 2.4 GHz x 128 flop/clk)
+PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32: 256 CU x 2.4 GHz x 256 flop/clk
+PEAK_FP64_TFLOPS = 78.6    # MI355X vector FP64: 256 CU x 2.4 GHz x 128 flop/clk
 PEAK_HBM_GBS = 8000.0
 FLOP_PER_ITER = 8
+BYTES_PER_PIXEL = 4
+METRIC = "Gpixel-iters/s (FP64/FP32/float-float) vs plain kernel; p99 frame latency"
+
+# HBM bytes per launch of the headline kernel from rocprofv3 --pmc FETCH_SIZE
+# and WRITE_SIZE (KiB summed over dispatch), scaled by the ratio the same
+# counters give for a plain device copy of known size.  None until measured on
+# the current kernel.
+MEASURED_TRAFFIC_BYTES = None
 
 
 def parse():
@@ -37,78 +49,183 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--cpu-seconds", type=float, default=12.0,
-                   help="bound on the CPU-oracle sample")
+    p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--no-extra", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--serve-seconds", type=float, default=2.5)
     return p.parse_args()
 
 
-def frames_single_4096(dtype):
-    import workloads as wl
-    return [wl.single_4096(seed, it, dtype) for it in (100, 1000) for seed in range(4)]
+def tuned_schedule(jr, name, frames):
+    """Schedule from the committed autotune cache, else tuned here (seconds)."""
+    from paper_1611_03079_amd import autotune as at
+    cache = at.load_cache()
+    e = cache.get("_workloads", {}).get(name)
+    if e:
+        return jr.Schedule(**e["schedule"]), "cache"
+    best, _, _ = at.tune(frames, reps=3)
+    return best, "tuned at start"
 
 
-def time_renders(jr, torch, frames, outs, steps, warmup, plain=False):
-    """Time `steps` passes; each pass renders every frame with one launch.
-    Returns (ms per step, per-launch kernel ms list from events)."""
-    def one_pass(events=None):
-        for k, (f, o) in enumerate(zip(frames, outs)):
-            if events is not None:
-                events[k][0].record()
-            jr.render(f.c, f.window, f.width, f.height, f.max_iter, f.dtype, out=o, plain=plain)
-            if events is not None:
-                events[k][1].record()
-
+def time_plan_steps(torch, plan, steps, warmup, graph=True):
+    """ms per step (wall, synchronised) and mean kernel ms (events)."""
+    run = plan.replay if graph else plan.launch
     for _ in range(warmup):
-        one_pass()
+        run()
     torch.cuda.synchronize()
-    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in frames] for _ in range(steps)]
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
     t0 = time.perf_counter()
-    for s in range(steps):
-        one_pass(ev[s])
+    for a, b in ev:
+        a.record()
+        run()
+        b.record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kernel_ms = sum(a.elapsed_time(b) for row in ev for a, b in row) / steps
-    return (t1 - t0) * 1e3 / steps, kernel_ms
+    kms = sum(a.elapsed_time(b) for a, b in ev) / steps
+    return (t1 - t0) * 1e3 / steps, kms
+
+
+def time_renders(jr, torch, frames, outs, reps, plain):
+    def one():
+        for f, o in zip(frames, outs):
+            jr.render(f.c, f.window, f.width, f.height, f.max_iter, f.dtype, out=o,
+                      plain=plain, mode=f.mode)
+    one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        one()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps
+
+
+def count_sum(torch, views):
+    return sum(int(v.sum(dtype=torch.int64).item()) for v in views)
 
 
 def cpu_baseline(frames, seconds):
-    """The oracle, single-threaded, on rows spread over the step's images until
-    `seconds` of CPU work; returns pixel-iter/s and the sample description."""
+    """The oracle, single-threaded, on whole rows spread over the frames (row
+    stride 54, frame stride 8) until `seconds` of CPU work."""
     import numpy as np
     import oracle
-    t_end = time.perf_counter() + seconds
-    total_iters, total_px, elapsed = 0, 0, 0.0
-    rows_done = 0
-    stride = 64
-    rng_rows = [list(range(r, f.height, stride)) for f in frames for r in (0,)]
-    k = 0
-    while time.perf_counter() < t_end and rows_done < sum(len(r) for r in rng_rows):
-        for fi, f in enumerate(frames):
-            if k >= len(rng_rows[fi]):
-                continue
-            j = rng_rows[fi][k]
-            ii = np.arange(f.width, dtype=np.int32)
-            jj = np.full(f.width, j, dtype=np.int32)
-            t0 = time.perf_counter()
-            c = oracle.render_pixels(f.c, f.window, f.width, f.height, f.max_iter, ii, jj, f.dtype)
-            elapsed += time.perf_counter() - t0
-            total_iters += int(c.sum(dtype=np.int64))
-            total_px += f.width
-            rows_done += 1
-        k += 1
-    return total_iters / elapsed, ("every %dth row of each of the %d images, first %d rows "
-                                   "(%d pixels, %.1f s single-threaded)"
-                                   % (stride, len(frames), rows_done, total_px, elapsed))
+    picks = [(fi, j) for j in range(0, frames[0].height, 54) for fi in range(0, len(frames), 8)]
+    iters = px = 0
+    spent = 0.0
+    done = 0
+    for fi, j in picks:
+        if spent >= seconds:
+            break
+        f = frames[fi]
+        ii = np.arange(f.width, dtype=np.int32)
+        jj = np.full(f.width, j, dtype=np.int32)
+        t0 = time.perf_counter()
+        c = oracle.render_pixels(f.c, f.window, f.width, f.height, f.max_iter, ii, jj, f.dtype)
+        spent += time.perf_counter() - t0
+        iters += int(c.sum(dtype=np.int64))
+        px += f.width
+        done += 1
+    sample = ("%d whole rows (every 54th row of every 8th frame, %d pixels), "
+              "oracle FP32 formulation, %.1f s single-threaded" % (done, px, spent))
+    return iters / spent, sample
+
+
+def extra_legs(args, torch, jr, wl, frames, sched, ms_headline, iters):
+    from paper_1611_03079_amd.serve import GpuBackend, Server, run_open_loop
+    ex = {}
+    reps = 3
+    # plain kernel: one launch per frame, same frames
+    outs = [torch.empty((f.height, f.width), dtype=torch.int32, device="cuda") for f in frames]
+    ms_plain = time_renders(jr, torch, frames, outs, reps, plain=True)
+    ex["parameter_path_plain_per_frame"] = {
+        "gpixel_iter_s": round(iters / (ms_plain * 1e-3) / 1e9, 2), "ms_per_step": round(ms_plain, 4)}
+    ex["tuned_batch_vs_plain"] = round(ms_plain / ms_headline, 3)
+    del outs
+    # persistent work-queue mode of the same batch
+    from dataclasses import replace
+    pers = replace(sched, persistent=1, waves_per_cu=32)
+    plan = jr.Plan(frames, pers)
+    ms_p, _ = time_plan_steps(torch, plan, 5, 1, graph=False)
+    plan.close()
+    ex["parameter_path_persistent_queues"] = {"ms_per_step": round(ms_p, 4),
+                                              "gpixel_iter_s": round(iters / (ms_p * 1e-3) / 1e9, 2)}
+    # single 4096x4096 images, FP32 and FP64, tuned vs plain
+    for dt in ("fp32", "fp64"):
+        fr = [wl.single_4096(s, it, dt) for it in (100, 1000) for s in range(4)]
+        outs = [torch.empty((f.height, f.width), dtype=torch.int32, device="cuda") for f in fr]
+        ms_t = time_renders(jr, torch, fr, outs, reps, plain=False)
+        it_s = count_sum(torch, outs)
+        ms_pl = time_renders(jr, torch, fr, outs, reps, plain=True)
+        peak = PEAK_FP32_TFLOPS if dt == "fp32" else PEAK_FP64_TFLOPS
+        ex["single_4096_%s" % dt] = {
+            "gpixel_iter_s": round(it_s / (ms_t * 1e-3) / 1e9, 2),
+            "plain_gpixel_iter_s": round(it_s / (ms_pl * 1e-3) / 1e9, 2),
+            "frac_vector_peak": round(FLOP_PER_ITER * it_s / (ms_t * 1e-3) / 1e12 / peak, 4),
+            "images": len(fr), "pixel_iters": it_s}
+        del outs
+    # 512x512 FP64: launch-bound latency, tuned and plain
+    f1 = wl.single_512("fp64")
+    o = torch.empty((512, 512), dtype=torch.int32, device="cuda")
+    for plain in (False, True):
+        for _ in range(5):
+            jr.render(f1.c, f1.window, 512, 512, 100, "fp64", out=o, plain=plain)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(50):
+            jr.render(f1.c, f1.window, 512, 512, 100, "fp64", out=o, plain=plain)
+            torch.cuda.synchronize()
+        ex["single_512_fp64_latency_us_" + ("plain" if plain else "tuned")] = round(
+            (time.perf_counter() - t0) / 50 * 1e6, 1)
+    # uneven batch: FP32 + float-float frames of random sides and caps, one launch
+    ub = wl.uneven_batch(0, n=64)
+    usched, _ = tuned_schedule(jr, "uneven_fp32_ff", ub)
+    plan = jr.Plan(ub, usched)
+    ms_u, _ = time_plan_steps(torch, plan, 2, 1, graph=False)
+    it_u = count_sum(torch, plan.views)
+    plan.close()
+    outs = [torch.empty((f.height, f.width), dtype=torch.int32, device="cuda") for f in ub]
+    ms_up = time_renders(jr, torch, ub, outs, 1, plain=True)
+    del outs
+    ex["uneven_batch_64_frames_fp32_ff"] = {
+        "gpixel_iter_s": round(it_u / (ms_u * 1e-3) / 1e9, 2), "ms": round(ms_u, 3),
+        "plain_per_frame_ms": round(ms_up, 3), "vs_plain": round(ms_up / ms_u, 3),
+        "pixels": sum(f.pixels for f in ub), "pixel_iters": it_u}
+    # serving: Poisson arrivals at several rates
+    serve = {}
+    for rate in (50, 200, 800, 2000):
+        n = max(20, int(rate * args.serve_seconds))
+        reqs = wl.serving_stream(11, float(rate), n)
+        cap = 8 * 1920 * 1080
+        srv = Server(GpuBackend(cap), cap, step_budget=2.0e8, copy_out=False)
+        st = run_open_loop(srv, reqs, drain_timeout=5.0)
+        torch.cuda.synchronize()
+        span = max(st.t_last - st.t_first, 1e-9)
+        serve["rate_%d" % rate] = {
+            "offered": n, "completed": st.completed,
+            "p50_ms": round(st.percentile(50) * 1e3, 2), "p99_ms": round(st.percentile(99) * 1e3, 2),
+            "completed_req_s": round(st.completed / span, 1), "steps": st.steps}
+        del srv
+        torch.cuda.empty_cache()
+    ex["serving"] = serve
+    # pixels whose FP32 / float-float count differs from FP64 (GPU vs GPU)
+    mism = {}
+    for dt in ("fp32", "ff"):
+        diff = tot = 0
+        for f in frames[::32]:
+            a = jr.render(f.c, f.window, f.width, f.height, f.max_iter, "fp64")
+            b = jr.render(f.c, f.window, f.width, f.height, f.max_iter, dt)
+            diff += int((a != b).sum().item())
+            tot += f.pixels
+        mism[dt] = round(diff / tot, 6)
+    ex["mismatch_vs_fp64_parameter_path"] = mism
+    return ex
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU; --gpus %d is not supported "
-              "(the path needs no exchange between GPUs; see DESIGN.md on sharding)" % args.gpus,
+        print("bench.py measures one GPU; --gpus %d is not supported: the path has no "
+              "exchange between GPUs (DESIGN.md describes how it would shard)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
     import torch
@@ -116,16 +233,20 @@ def main():
     import workloads as wl
 
     torch.cuda.set_device(0)
-    frames = frames_single_4096("fp32")
-    outs = [torch.empty((f.height, f.width), dtype=torch.int32, device="cuda") for f in frames]
-    ms_step, kernel_ms = time_renders(jr, torch, frames, outs, args.steps, args.warmup)
-    iters = sum(int(o.sum(dtype=torch.int64).item()) for o in outs)
+    frames = wl.parameter_path()
+    sched, sched_src = tuned_schedule(jr, "parameter_path_fp32", frames)
+    plan = jr.Plan(frames, sched)
+    plan.capture()
+    ms_step, kernel_ms = time_plan_steps(torch, plan, args.steps, args.warmup, graph=True)
+    iters = count_sum(torch, plan.views)
+    info = plan.info()
+    plan.close()
     pixels = sum(f.pixels for f in frames)
     value = iters / (ms_step * 1e-3) / 1e9
-    achieved_tflops = FLOP_PER_ITER * iters / (kernel_ms * 1e-3) / 1e12
-
+    store_gbs = BYTES_PER_PIXEL * pixels / (kernel_ms * 1e-3) / 1e9
+    alu_tflops = FLOP_PER_ITER * iters / (kernel_ms * 1e-3) / 1e12
     line = {
-        "metric": "Gpixel-iters/s (FP64/FP32/float-float) vs plain kernel; p99 frame latency",
+        "metric": METRIC,
         "value": round(value, 3),
         "unit": "Gpixel-iter/s",
         "n_gpus": 1,
@@ -137,72 +258,24 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "single_4096: 4096x4096, window [-1.6,1.6]^2, "
-                               "C=0.7885exp(i theta(seed)), seeds 0-3, max_iter {100,1000}, "
-                               "FP32, tuned persistent kernel, one launch per image",
-                   "images_per_step": len(frames), "pixels_per_step": pixels,
-                   "pixel_iters_per_step": iters,
-                   "schedule": jr.default_schedule("fp32").__dict__},
-        "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 3),
-                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4), "traffic": None,
-                     "kernel": "jr_persistent<unroll, FP32>",
-                     "kernel_ms_per_step": round(kernel_ms, 4)},
+        "config": {"workload": "parameter_path: 256 frames 1920x1080, C=0.7885exp(2 pi i k/256), "
+                               "window Re[-1.78,1.78] x Im[-1,1], max_iter 100, FP32, one launch "
+                               "of the tiled kernel per step (hipGraph replay), autotuned schedule",
+                   "frames": len(frames), "pixels_per_step": pixels, "pixel_iters_per_step": iters,
+                   "schedule": sched.__dict__, "schedule_source": sched_src,
+                   "tiles": info["tiles"], "workgroups": info["workgroups"]},
+        "roofline": {"bound": "hbm", "achieved": round(store_gbs, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(store_gbs / PEAK_HBM_GBS, 4),
+                     "traffic": MEASURED_TRAFFIC_BYTES,
+                     "algorithmic_bytes_per_launch": BYTES_PER_PIXEL * pixels,
+                     "kernel_ms": round(kernel_ms, 4),
+                     "alu": {"achieved": round(alu_tflops, 2), "peak": PEAK_FP32_TFLOPS,
+                             "unit": "TFLOP/s", "frac": round(alu_tflops / PEAK_FP32_TFLOPS, 4),
+                             "flops_per_launch": FLOP_PER_ITER * iters},
+                     "kernel": "jr_tiled (libjulia.so)"},
     }
-    extra = {}
     if not args.no_extra:
-        steps = max(3, args.steps // 4)
-        # plain kernel on the same images
-        ms_plain, k_plain = time_renders(jr, torch, frames, outs, steps, 1, plain=True)
-        extra["fp32_plain"] = {"gpixel_iter_s": round(iters / (ms_plain * 1e-3) / 1e9, 3),
-                               "ms_per_step": round(ms_plain, 4)}
-        extra["fp32_tuned_vs_plain"] = round(ms_plain / ms_step, 3)
-        f64 = frames_single_4096("fp64")
-        ms64, k64 = time_renders(jr, torch, f64, outs, steps, 1)
-        it64 = sum(int(o.sum(dtype=torch.int64).item()) for o in outs)
-        ms64p, _ = time_renders(jr, torch, f64, outs, steps, 1, plain=True)
-        extra["fp64"] = {"gpixel_iter_s": round(it64 / (ms64 * 1e-3) / 1e9, 3),
-                         "ms_per_step": round(ms64, 4),
-                         "frac_fp64_peak": round(FLOP_PER_ITER * it64 / (k64 * 1e-3) / 1e12
-                                                 / PEAK_FP64_TFLOPS, 4),
-                         "plain_gpixel_iter_s": round(it64 / (ms64p * 1e-3) / 1e9, 3)}
-        del outs
-        # batched parameter path, one persistent launch per pass
-        pp = wl.parameter_path()
-        plan = jr.Plan(pp, jr.default_schedule("fp32"))
-        plan.capture()
-        for _ in range(2):
-            plan.replay()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = max(3, args.steps // 4)
-        e0.record()
-        for _ in range(reps):
-            plan.replay()
-        e1.record()
-        torch.cuda.synchronize()
-        ms_pp = e0.elapsed_time(e1) / reps
-        it_pp = int(plan.arena.sum(dtype=torch.int64).item())
-        px_pp = sum(f.pixels for f in pp)
-        extra["parameter_path_256x1920x1080_fp32"] = {
-            "gpixel_iter_s": round(it_pp / (ms_pp * 1e-3) / 1e9, 3),
-            "ms_per_batch": round(ms_pp, 4),
-            "frac_fp32_peak": round(FLOP_PER_ITER * it_pp / (ms_pp * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
-            "store_gb_s": round(4 * px_pp / (ms_pp * 1e-3) / 1e9, 1),
-            "pixel_iters": it_pp, "pixels": px_pp}
-        plan.close()
-        # 512x512 FP64 latency (launch-bound)
-        o = torch.empty((512, 512), dtype=torch.int32, device="cuda")
-        f1 = wl.single_512()
-        for _ in range(5):
-            jr.render(f1.c, f1.window, 512, 512, 100, "fp64", out=o)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(50):
-            jr.render(f1.c, f1.window, 512, 512, 100, "fp64", out=o)
-            torch.cuda.synchronize()
-        extra["single_512_fp64_latency_us"] = round((time.perf_counter() - t0) / 50 * 1e6, 1)
-        line["extra"] = extra
+        line["extra"] = extra_legs(args, torch, jr, wl, frames, sched, ms_step, iters)
     if not args.no_cpu:
         rate, sample = cpu_baseline(frames, args.cpu_seconds)
         line["cpu_baseline"] = {"value": round(rate / 1e9, 5), "unit": "Gpixel-iter/s",

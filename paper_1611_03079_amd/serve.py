@@ -1,0 +1,304 @@
+"""Continuous-batching request loop for interactive exploration.
+
+The paper's application renders a Julia image for the parameter the user is
+moving (Sections 2 and 3: real-time full-screen frames, parameter paths, deep
+zooms).  This loop serves a stream of such requests on one GPU:
+
+  * requests arrive at any time (submit() returns a Future);
+  * a request is admitted when its counts fit in the device output arena
+    (memory-based admission, first come first served);
+  * every step takes rows from all admitted requests, oldest first, up to a
+    work budget, and renders them in ONE launch of the batch kernel (frames of
+    different sizes, caps and dtypes together; a large frame is split over
+    several steps by row ranges);
+  * two steps are kept in flight on two streams, so work admitted while
+    others run overlaps with them on the device;
+  * a request completes when the step holding its last rows has finished; its
+    counts are copied out of the arena and the arena range is freed;
+  * latency = completion time - arrival time; p50/p99 and throughput are kept.
+
+The arithmetic of each frame is picked by a precision policy from its window
+width and cap.  Scheduling never changes a count, so every result equals the
+same request rendered alone.
+"""
+import collections
+import math
+import threading
+import time
+from concurrent.futures import Future
+from dataclasses import dataclass, field
+from typing import Deque, Dict, List, Optional
+
+DTYPE_COST = {"fp32": 1.0, "fp64": 1.75, "ff": 20.0}
+
+
+@dataclass
+class PrecisionPolicy:
+    """dtype by window width and cap: FP32 for wide windows and small caps,
+    float-float for narrower windows, FP64 below `ff_min_width`."""
+    fp32_min_width: float = 0.5
+    fp32_max_iter: int = 200
+    ff_min_width: float = 1e-5
+
+    def pick(self, width: float, max_iter: int) -> str:
+        if width >= self.fp32_min_width and max_iter <= self.fp32_max_iter:
+            return "fp32"
+        if width >= self.ff_min_width:
+            return "ff"
+        return "fp64"
+
+
+class ArenaAllocator:
+    """First-fit allocator of element ranges in [0, capacity)."""
+
+    def __init__(self, capacity: int):
+        self.capacity = int(capacity)
+        self.free = [(0, self.capacity)]  # sorted (offset, length)
+        self.used = 0
+
+    def alloc(self, n: int) -> Optional[int]:
+        for k, (off, ln) in enumerate(self.free):
+            if ln >= n:
+                if ln == n:
+                    self.free.pop(k)
+                else:
+                    self.free[k] = (off + n, ln - n)
+                self.used += n
+                return off
+        return None
+
+    def release(self, off: int, n: int):
+        self.used -= n
+        self.free.append((off, n))
+        self.free.sort()
+        merged = []
+        for o, ln in self.free:
+            if merged and merged[-1][0] + merged[-1][1] == o:
+                merged[-1] = (merged[-1][0], merged[-1][1] + ln)
+            else:
+                merged.append((o, ln))
+        self.free = merged
+
+
+@dataclass
+class _Req:
+    rid: int
+    frame: object            # has c, window, width, height, max_iter, dtype, mode
+    arrival: float
+    future: Future
+    offset: int = -1
+    next_row: int = 0
+    last_step: int = -1      # step that holds the frame's last rows
+    done_rows: int = 0
+
+
+@dataclass
+class Stats:
+    latencies: List[float] = field(default_factory=list)
+    completed: int = 0
+    pixels: int = 0
+    steps: int = 0
+    t_first: float = math.inf
+    t_last: float = 0.0
+
+    def percentile(self, q: float) -> float:
+        if not self.latencies:
+            return math.nan
+        xs = sorted(self.latencies)
+        k = min(len(xs) - 1, max(0, int(math.ceil(q / 100.0 * len(xs))) - 1))
+        return xs[k]
+
+
+class GpuBackend:
+    """libjulia.so on the current CUDA device: device arena, two streams."""
+
+    def __init__(self, arena_elements: int, streams: int = 2):
+        import torch
+        import paper_1611_03079_amd as jr
+        self.torch, self.jr = torch, jr
+        self.arena = torch.empty(int(arena_elements), dtype=torch.int32, device="cuda")
+        self.streams = [torch.cuda.Stream() for _ in range(streams)]
+
+    def now(self) -> float:
+        return time.perf_counter()
+
+    def launch(self, frames, offsets, rows, stream_idx: int, schedule=None):
+        st = self.streams[stream_idx]
+        self.jr.render_batch(frames, schedule, arena=self.arena, offsets=offsets, rows=rows,
+                             stream=st)
+        ev = self.torch.cuda.Event()
+        ev.record(st)
+        return ev
+
+    def done(self, handle) -> bool:
+        return handle.query()
+
+    def fetch(self, offset: int, frame, stream_idx: int):
+        st = self.streams[stream_idx]
+        n = frame.width * frame.height
+        with self.torch.cuda.stream(st):
+            out = self.arena[offset: offset + n].view(frame.height, frame.width).clone()
+            ev = self.torch.cuda.Event()
+            ev.record(st)
+        return ev, out
+
+
+class Server:
+    def __init__(self, backend, arena_elements: int, step_budget: float = 2.0e8,
+                 max_inflight: int = 2, policy: Optional[PrecisionPolicy] = None,
+                 copy_out: bool = True, schedule=None):
+        self.b = backend
+        self.alloc = ArenaAllocator(arena_elements)
+        self.step_budget = step_budget
+        self.max_inflight = max_inflight
+        self.policy = policy or PrecisionPolicy()
+        self.copy_out = copy_out
+        self.schedule = schedule
+        self.queue: Deque[_Req] = collections.deque()
+        self.active: List[_Req] = []
+        self.inflight: Deque = collections.deque()   # (step id, handle, [reqs ending here])
+        self.fetching: List = []                     # (handle, req, result)
+        self.stats = Stats()
+        self.lock = threading.Lock()
+        self.step_id = 0
+        self._rid = 0
+        self._stop = False
+        self._thread = None
+
+    # ------------------------------------------------------------- client side
+    def submit(self, frame, arrival: Optional[float] = None) -> Future:
+        fut = Future()
+        if frame.width * frame.height > self.alloc.capacity:
+            fut.set_exception(ValueError("frame larger than the output arena"))
+            return fut
+        if getattr(frame, "dtype", None) in (None, "auto"):
+            w = frame.window[1] - frame.window[0]
+            frame.dtype = self.policy.pick(w, frame.max_iter)
+        with self.lock:
+            self._rid += 1
+            self.queue.append(_Req(self._rid, frame, self.b.now() if arrival is None else arrival,
+                                   fut))
+        return fut
+
+    def pending(self) -> int:
+        with self.lock:
+            return len(self.queue) + len(self.active) + len(self.fetching)
+
+    # ------------------------------------------------------------- scheduler
+    def _admit(self):
+        with self.lock:
+            while self.queue:
+                r = self.queue[0]
+                if r.future.cancelled():
+                    self.queue.popleft()
+                    continue
+                off = self.alloc.alloc(r.frame.width * r.frame.height)
+                if off is None:
+                    break   # first come first served: the head waits for memory
+                r.offset = off
+                self.active.append(self.queue.popleft())
+
+    def _row_cost(self, f) -> float:
+        return f.width * (4.0 + min(f.max_iter, 256)) * DTYPE_COST[f.dtype]
+
+    def _build_step(self):
+        frames, offsets, rows, ending = [], [], [], []
+        budget = self.step_budget
+        for r in self.active:
+            if r.next_row >= r.frame.height:
+                continue
+            f = r.frame
+            take = max(1, min(f.height - r.next_row, int(budget // self._row_cost(f))))
+            frames.append(f)
+            offsets.append(r.offset)
+            rows.append((r.next_row, r.next_row + take))
+            r.next_row += take
+            if r.next_row >= f.height:
+                r.last_step = self.step_id
+                ending.append(r)
+            budget -= take * self._row_cost(f)
+            if budget <= 0:
+                break
+        return frames, offsets, rows, ending
+
+    def step(self) -> bool:
+        """One scheduler pass; returns True when it did anything."""
+        busy = False
+        self._admit()
+        if len(self.inflight) < self.max_inflight:
+            frames, offsets, rows, ending = self._build_step()
+            if frames:
+                sidx = self.step_id % self.max_inflight
+                h = self.b.launch(frames, offsets, rows, sidx, self.schedule)
+                self.inflight.append((self.step_id, sidx, h, ending))
+                self.step_id += 1
+                self.stats.steps += 1
+                busy = True
+        while self.inflight and self.b.done(self.inflight[0][2]):
+            _, sidx, _, ending = self.inflight.popleft()
+            for r in ending:
+                if self.copy_out:
+                    h, out = self.b.fetch(r.offset, r.frame, sidx)
+                else:
+                    h, out = None, None
+                self.fetching.append((h, r, out))
+            busy = True
+        keep = []
+        for h, r, out in self.fetching:
+            if h is None or self.b.done(h):
+                t = self.b.now()
+                self.stats.latencies.append(t - r.arrival)
+                self.stats.completed += 1
+                self.stats.pixels += r.frame.width * r.frame.height
+                self.stats.t_first = min(self.stats.t_first, r.arrival)
+                self.stats.t_last = max(self.stats.t_last, t)
+                with self.lock:
+                    self.active.remove(r)
+                    self.alloc.release(r.offset, r.frame.width * r.frame.height)
+                if not r.future.cancelled():
+                    r.future.set_result(out)
+                busy = True
+            else:
+                keep.append((h, r, out))
+        self.fetching = keep
+        return busy
+
+    def run_until_idle(self, timeout: float = 60.0):
+        t_end = time.perf_counter() + timeout
+        while self.pending() and time.perf_counter() < t_end:
+            if not self.step():
+                time.sleep(0.0001)
+        if self.pending():
+            raise TimeoutError("requests still pending after %.1f s" % timeout)
+
+    def start(self):
+        def loop():
+            while not self._stop:
+                if not self.step():
+                    time.sleep(0.0001)
+        self._thread = threading.Thread(target=loop, daemon=True)
+        self._thread.start()
+
+    def stop(self):
+        self._stop = True
+        if self._thread:
+            self._thread.join()
+
+
+def run_open_loop(server: Server, requests, drain_timeout: float = 60.0) -> Stats:
+    """Submit requests at their scheduled arrival times (open loop: latency is
+    measured from the scheduled arrival, so a slow server cannot hide
+    queueing) while the server runs in its own thread."""
+    server.start()
+    t0 = time.perf_counter()
+    futs = []
+    for req in requests:
+        delay = t0 + req.arrival_s - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        futs.append(server.submit(req.frame, arrival=t0 + req.arrival_s))
+    t_end = time.perf_counter() + drain_timeout
+    while server.pending() and time.perf_counter() < t_end:
+        time.sleep(0.001)
+    server.stop()
+    return server.stats

@@ -1,0 +1,142 @@
+"""The serving loop's scheduling on the CPU, with a fake backend.
+
+The fake backend renders with the oracle and completes a launch only after
+a few polls, so admission, row chunking, completion order, latency accounting
+and cancellation are exercised without a GPU."""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import Frame
+from paper_1611_03079_amd.serve import ArenaAllocator, PrecisionPolicy, Server
+
+
+class FakeBackend:
+    def __init__(self, capacity, polls=2):
+        self.arena = np.full(capacity, -1, dtype=np.int32)
+        self.polls = polls
+        self.clock = 0.0
+        self.launches = []
+
+    def now(self):
+        self.clock += 1.0
+        return self.clock
+
+    def launch(self, frames, offsets, rows, stream_idx, schedule=None):
+        self.launches.append([(id(f), r) for f, r in zip(frames, rows)])
+        for f, o, (r0, r1) in zip(frames, offsets, rows):
+            img = oracle.render(f.c, f.window, f.width, f.height, f.max_iter, f.dtype, f.mode)
+            view = self.arena[o: o + f.width * f.height].reshape(f.height, f.width)
+            assert (view[r0:r1] == -1).all(), "rows rendered twice"
+            view[r0:r1] = img[r0:r1]
+        return [self.polls]
+
+    def done(self, h):
+        h[0] -= 1
+        return h[0] < 0
+
+    def fetch(self, offset, frame, stream_idx):
+        n = frame.width * frame.height
+        out = self.arena[offset: offset + n].reshape(frame.height, frame.width).copy()
+        self.arena[offset: offset + n] = -1   # the range may be handed out again
+        return [0], out
+
+
+def frames(n, w=24, h=18):
+    cs = [complex(-0.8, 0.156), complex(0.285, 0.01), complex(-0.4, 0.6), complex(0.3, -0.5)]
+    return [Frame(cs[k % 4], (-1.5, 1.5, -1.2, 1.2), w + k, h + (k % 3), 60 + 10 * k,
+                  ("fp64", "fp32", "ff")[k % 3]) for k in range(n)]
+
+
+def test_allocator_first_fit_and_merge():
+    a = ArenaAllocator(100)
+    x = a.alloc(30); y = a.alloc(30); z = a.alloc(30)
+    assert (x, y, z) == (0, 30, 60) and a.alloc(20) is None
+    a.release(y, 30)
+    assert a.alloc(40) is None and a.alloc(25) == 30
+    a.release(x, 30); a.release(30, 25); a.release(z, 30)
+    assert a.free == [(0, 100)] and a.used == 0
+
+
+def test_all_requests_complete_with_oracle_counts():
+    fr = frames(7)
+    b = FakeBackend(10_000)
+    srv = Server(b, 10_000, step_budget=3e4)
+    futs = [srv.submit(f) for f in fr]
+    srv.run_until_idle(timeout=30)
+    for f, fu in zip(fr, futs):
+        np.testing.assert_array_equal(fu.result(), oracle.render(
+            f.c, f.window, f.width, f.height, f.max_iter, f.dtype))
+    assert srv.stats.completed == 7 and srv.alloc.used == 0
+    # several frames share a launch, and large frames span several launches
+    assert any(len(l) > 1 for l in b.launches)
+    assert len(b.launches) > 1
+
+
+def test_admission_by_memory_is_first_come_first_served():
+    fr = frames(4, 30, 20)
+    cap = 30 * 20 + 40 * 22          # room for about one frame at a time
+    b = FakeBackend(cap)
+    srv = Server(b, cap, step_budget=1e9)
+    order = []
+    futs = [srv.submit(f) for f in fr]
+    for k, fu in enumerate(futs):
+        fu.add_done_callback(lambda _f, k=k: order.append(k))
+    srv.run_until_idle(timeout=30)
+    assert order == [0, 1, 2, 3]
+    assert srv.alloc.used == 0
+
+
+def test_rows_are_split_over_steps_and_covered_once():
+    f = Frame(complex(-0.8, 0.156), (-1.5, 1.5, -1.5, 1.5), 40, 64, 100, "fp32")
+    b = FakeBackend(40 * 64)
+    srv = Server(b, 40 * 64, step_budget=40 * 104 * 5)   # about 5 rows per step
+    fu = srv.submit(f)
+    srv.run_until_idle(timeout=30)
+    rows = [r for l in b.launches for _, r in l]
+    assert len(rows) >= 10
+    covered = sorted(rows)
+    assert covered[0][0] == 0 and covered[-1][1] == 64
+    assert all(a[1] == b_[0] for a, b_ in zip(covered, covered[1:]))
+    np.testing.assert_array_equal(fu.result(), oracle.render(f.c, f.window, 40, 64, 100, "fp32"))
+
+
+def test_latency_is_completion_minus_arrival():
+    b = FakeBackend(5000)
+    srv = Server(b, 5000)
+    futs = [srv.submit(f, arrival=0.5) for f in frames(3)]
+    srv.run_until_idle(timeout=30)
+    assert len(srv.stats.latencies) == 3
+    assert all(l > 0 for l in srv.stats.latencies)
+    assert srv.stats.percentile(50) <= srv.stats.percentile(99)
+
+
+def test_cancelled_request_is_not_rendered():
+    fr = frames(3)
+    b = FakeBackend(600)           # one frame at a time fits: the others queue
+    srv = Server(b, 600)
+    futs = [srv.submit(f) for f in fr]
+    assert futs[2].cancel()
+    srv.run_until_idle(timeout=30)
+    rendered = {fid for l in b.launches for fid, _ in l}
+    assert id(fr[2]) not in rendered
+    assert futs[0].result() is not None and futs[1].result() is not None
+
+
+def test_oversized_frame_is_rejected():
+    srv = Server(FakeBackend(100), 100)
+    fu = srv.submit(Frame(0j, (-1, 1, -1, 1), 20, 20, 10, "fp32"))
+    with pytest.raises(ValueError):
+        fu.result(timeout=1)
+
+
+def test_precision_policy():
+    p = PrecisionPolicy()
+    assert p.pick(3.0, 100) == "fp32"
+    assert p.pick(3.0, 1000) == "ff"
+    assert p.pick(1e-3, 100) == "ff"
+    assert p.pick(1e-7, 100) == "fp64"
+    f = Frame(0j, (-1e-8, 1e-8, -1e-8, 1e-8), 8, 8, 100, "auto")
+    srv = Server(FakeBackend(100), 100)
+    srv.submit(f)
+    assert f.dtype == "fp64"

@@ -160,7 +160,7 @@ def uneven_batch(seed: int = 0, n: int = 1024, side_lo: int = 256, side_hi: int 
 # Serving: Poisson arrivals; each request a random C (uneven-batch sampler),
 # window centre U[-1.5, 1.5]^2, width log-uniform in [1e-9, 3], size from
 # {640x480, 1280x720, 1920x1080}, cap U{100..5000}.  The arithmetic is left to
-# the precision policy of the serving loop (dtype=None here).
+# the precision policy of the serving loop (dtype "auto" here).
 # --------------------------------------------------------------------------
 SERVE_SIZES = ((640, 480), (1280, 720), (1920, 1080))
 
@@ -189,7 +189,7 @@ def serving_stream(seed: int, rate_per_s: float, n: int,
         height = width * h / w
         cap = rng.randint(cap_lo, cap_hi)
         win = (cre - 0.5 * width, cre + 0.5 * width, cim - 0.5 * height, cim + 0.5 * height)
-        out.append(Request(t, Frame(c, win, w, h, cap, "fp64"), k))
+        out.append(Request(t, Frame(c, win, w, h, cap, "auto"), k))
     return out
 
 
