@@ -53,6 +53,9 @@ def parse():
     p.add_argument("--no-extra", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--serve-seconds", type=float, default=2.5)
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="also run an elementwise device copy of 1 GiB (read 1 GiB, write 1 GiB) "
+                        "whose FETCH_SIZE / WRITE_SIZE counters calibrate the traffic figures")
     return p.parse_args()
 
 
@@ -233,6 +236,13 @@ def main():
     import workloads as wl
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     frames = wl.parameter_path()
     sched, sched_src = tuned_schedule(jr, "parameter_path_fp32", frames)
     plan = jr.Plan(frames, sched)
