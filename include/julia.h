@@ -91,7 +91,7 @@ typedef struct {
 } jr_frame;
 
 /*
- * Schedule of the tiled kernel.  None of these fields changes a count: they
+ * Schedule of a batch launch.  None of these fields changes a count: they
  * decide which lane computes which pixel and when, never the arithmetic.
  *   tile_w, tile_h  pixels per work tile: 1 <= tile_w <= 64, 1 <= tile_h <= 64.
  *   unroll          iterations per branch-free block: 1, 2, 4 or 8, or with
@@ -114,7 +114,12 @@ typedef struct {
  *   order           JR_ORDER_TABLE: frames in the order given;
  *                   JR_ORDER_COST: most expensive frames first (estimated
  *                   from size, cap and dtype).
+ *   kernel          JR_KERNEL_TILED: the tiled kernel above;
+ *                   JR_KERNEL_PLAIN: one thread per pixel over the whole batch
+ *                   (16 x 16 tiles, one workgroup each, a test on every
+ *                   iteration); the other fields are then ignored.
  */
+typedef enum { JR_KERNEL_TILED = 0, JR_KERNEL_PLAIN = 1 } jr_kernel;
 typedef struct {
     int32_t tile_w, tile_h;
     int32_t unroll;
@@ -123,6 +128,7 @@ typedef struct {
     int32_t persistent;
     int32_t waves_per_cu;
     int32_t order;
+    int32_t kernel;
 } jr_schedule;
 
 /*

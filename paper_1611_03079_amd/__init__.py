@@ -21,6 +21,7 @@ JR_OK, JR_EINVAL, JR_ENOMEM, JR_ENODEV, JR_ELAUNCH, JR_EINTERNAL = 0, -1, -2, -3
 DTYPES = {"fp64": 0, "fp32": 1, "ff": 2}
 MODES = {"julia": 0, "mandelbrot": 1}
 ORDERS = {"table": 0, "cost": 1}
+KERNELS = {"tiled": 0, "plain": 1}
 
 
 class JuliaError(RuntimeError):
@@ -51,7 +52,8 @@ class jr_schedule(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
                 ("unroll", ctypes.c_int32), ("defer", ctypes.c_int32),
                 ("refill", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("waves_per_cu", ctypes.c_int32), ("order", ctypes.c_int32)]
+                ("waves_per_cu", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("kernel", ctypes.c_int32)]
 
 
 assert ctypes.sizeof(jr_frame) == 88
@@ -68,16 +70,19 @@ class Schedule:
     persistent: int = 1
     waves_per_cu: int = 16
     order: str = "cost"
+    kernel: str = "tiled"
 
     def to_c(self) -> jr_schedule:
         return jr_schedule(self.tile_w, self.tile_h, self.unroll, self.defer, self.refill,
-                           self.persistent, self.waves_per_cu, ORDERS[self.order])
+                           self.persistent, self.waves_per_cu, ORDERS[self.order],
+                           KERNELS[self.kernel])
 
     @staticmethod
     def from_c(s: jr_schedule) -> "Schedule":
         inv = {v: k for k, v in ORDERS.items()}
+        invk = {v: k for k, v in KERNELS.items()}
         return Schedule(s.tile_w, s.tile_h, s.unroll, s.defer, s.refill, s.persistent,
-                        s.waves_per_cu, inv[s.order])
+                        s.waves_per_cu, inv[s.order], invk[s.kernel])
 
 
 EXPORTS = (
@@ -180,15 +185,46 @@ def _out_tensor(out, shape):
     return out
 
 
+_TUNED = None
+
+
+def tuned_schedule(dtype: str, max_iter: int, pixels: int) -> Optional["Schedule"]:
+    """The autotuner's schedule for this (dtype, cap, size) bucket on this
+    device, from the shipped cache (autotune_cache.json), if it has one."""
+    global _TUNED
+    from . import autotune
+    if _TUNED is None:
+        try:
+            _TUNED = autotune.load_cache()
+        except (OSError, ValueError):
+            _TUNED = {}
+    try:
+        return autotune.lookup(_TUNED, dtype, max_iter, pixels)
+    except Exception:
+        return None
+
+
 def render(c, window, width: int, height: int, max_iter: int, dtype: str = "fp64",
-           out=None, stream=None, mode: str = "julia", plain: bool = False):
+           out=None, stream=None, mode: str = "julia", plain: bool = False,
+           schedule: Optional["Schedule"] = None):
     """Counts of one image as an int32 (height, width) CUDA tensor (row 0 = im_max).
 
-    ``plain=True`` uses the one-thread-per-pixel comparator kernel.
+    ``plain=True`` uses the one-thread-per-pixel comparator kernel.  Otherwise
+    the schedule is ``schedule``, else the autotuner's choice for the image's
+    bucket, else the library default (julia_render / mandelbrot_render).
     """
     out = _out_tensor(out, (height, width))
     st = _stream_ptr(stream)
     dt = DTYPES[dtype]
+    if not plain:
+        if schedule is None:
+            schedule = tuned_schedule(dtype, max_iter, width * height)
+        if schedule is not None:
+            f = _OneFrame(c, window, width, height, max_iter, dtype, mode)
+            arr = _frames_array([f], [0])
+            _check(lib.julia_render_batch(arr, 1, ctypes.c_void_p(out.data_ptr()),
+                                          width * height, ctypes.byref(schedule.to_c()), st))
+            return out.view(-1)[: width * height].view(height, width)
     if mode == "julia":
         c = complex(c)
         fn = lib.julia_render_plain if plain else lib.julia_render
@@ -201,6 +237,17 @@ def render(c, window, width: int, height: int, max_iter: int, dtype: str = "fp64
         raise ValueError("mode must be 'julia' or 'mandelbrot'")
     _check(rc)
     return out.view(-1)[: width * height].view(height, width)
+
+
+@dataclass
+class _OneFrame:
+    c: complex
+    window: tuple
+    width: int
+    height: int
+    max_iter: int
+    dtype: str
+    mode: str
 
 
 def _frames_array(frames, offsets, rows=None):

@@ -6,10 +6,12 @@ never changes a count: only which lane computes which pixel and when.  The
 tuner therefore times candidate schedules on a representative batch with HIP
 events around prepared launches (jr_plan_launch) and keeps the fastest.
 
-Search, in three stages from a base schedule:
+Search, in stages from a base schedule:
   1. the iteration block (unroll, defer),
   2. tile shape x scheduling mode x refill threshold,
-  3. resident waves per compute unit (persistent mode only).
+  3. resident waves per compute unit (persistent mode only),
+  4. the iteration block again under the chosen tiling,
+  5. the batched one-thread-per-pixel kernel as a last candidate.
 
 Results are cached in a JSON file keyed by (device, dtype, cap bucket, pixel
 bucket); ``apply_cache`` installs the cached winners as the library defaults
@@ -96,6 +98,12 @@ def tune(frames: Sequence, base: Optional[jr.Schedule] = None, reps: int = 3,
     # re-check the block choice under the final tiling
     s = _stage(frames, s, [dict(unroll=u, defer=d) for u, d in BLOCKS], reps, log)
     best_t = min(t for d, t in log if jr.Schedule(**d) == s)
+    # the one-thread-per-pixel kernel over the batch is a candidate too
+    plain = jr.Schedule(kernel="plain", order=s.order)
+    t = time_plan(frames, plain, reps=reps)
+    log.append((asdict(plain), t))
+    if t < best_t:
+        s, best_t = plain, t
     return s, best_t, log
 
 

@@ -61,5 +61,7 @@ struct PlainArgs {
 hipError_t launch_tiled(int unroll, int defer, int dtmask, int blocks, const PersistentArgs& args,
                         hipStream_t stream);
 hipError_t launch_plain(int dtype, const PlainArgs& args, hipStream_t stream);
+// One thread per pixel over the frame table (tiles of 16 x 16, one workgroup each).
+hipError_t launch_plain_batch(int dtmask, const PersistentArgs& args, hipStream_t stream);
 
 }  // namespace jr

@@ -109,6 +109,8 @@ int check_schedule(const jr_schedule& s) {
         return fail(JR_EINVAL, "schedule: waves_per_cu must be 4..32, a multiple of 4");
     if (s.order != JR_ORDER_TABLE && s.order != JR_ORDER_COST)
         return fail(JR_EINVAL, "schedule: unknown order %d", s.order);
+    if (s.kernel != JR_KERNEL_TILED && s.kernel != JR_KERNEL_PLAIN)
+        return fail(JR_EINVAL, "schedule: unknown kernel %d", s.kernel);
     return JR_OK;
 }
 
@@ -137,11 +139,13 @@ int check_frames(const jr_frame* frames, int32_t n, int64_t capacity) {
 // ------------------------------------------------------------- schedules
 std::mutex g_sched_mu;
 // Defaults per dtype; the autotuner can replace them (jr_set_default_schedule).
+// Starting points from the autotuner's runs on MI355X (one wave per tile was
+// faster than the work queues on every workload measured).
 jr_schedule g_default[3] = {
-    // tile_w, tile_h, unroll, defer, refill, persistent, waves_per_cu, order
-    {64, 16, 4, 0, 16, 1, 16, JR_ORDER_COST},  // FP64
-    {64, 16, 4, 0, 16, 1, 16, JR_ORDER_COST},  // FP32
-    {64, 8, 4, 0, 16, 1, 16, JR_ORDER_COST},   // FF
+    // tile_w, tile_h, unroll, defer, refill, persistent, waves_per_cu, order, kernel
+    {16, 16, 8, 0, 16, 0, 16, JR_ORDER_COST, JR_KERNEL_TILED},  // FP64
+    {64, 16, 8, 1, 32, 0, 16, JR_ORDER_COST, JR_KERNEL_TILED},  // FP32
+    {16, 16, 8, 1, 64, 0, 16, JR_ORDER_COST, JR_KERNEL_TILED},  // FF
 };
 
 jr_schedule default_schedule(int dtype) {
@@ -234,8 +238,10 @@ void build_table(const jr_frame* frames, int32_t n, const jr_schedule& s, Table&
         d.defer = absorbing(f) ? 1 : 0;
         d.row_begin = f.row_begin;
         d.row_end = f.row_end == 0 ? f.height : f.row_end;
-        d.tile_w = std::min(s.tile_w, f.width);
-        d.tile_h = std::min(s.tile_h, d.row_end - d.row_begin);
+        const int32_t tw = s.kernel == JR_KERNEL_PLAIN ? 16 : s.tile_w;
+        const int32_t th = s.kernel == JR_KERNEL_PLAIN ? 16 : s.tile_h;
+        d.tile_w = std::min(tw, f.width);
+        d.tile_h = std::min(th, d.row_end - d.row_begin);
         d.tiles_x = (f.width + d.tile_w - 1) / d.tile_w;
         const int64_t tiles_y = (d.row_end - d.row_begin + d.tile_h - 1) / d.tile_h;
         d.tile_begin = t.total_tiles;
@@ -326,6 +332,7 @@ int get_workspace(int dev, hipStream_t stream, Workspace** out) {
 }
 
 int grid_blocks(const DeviceInfo& info, const jr_schedule& s, int64_t total_tiles) {
+    if (s.kernel == JR_KERNEL_PLAIN) return (int)std::min<int64_t>(total_tiles, INT32_MAX);
     if (!s.persistent) return (int)std::min<int64_t>((total_tiles + 3) / 4, INT32_MAX);
     int64_t blocks = (int64_t)info.num_cus * (s.waves_per_cu / 4);
     // No more waves than tiles: extra waves would only claim and leave.
@@ -392,7 +399,9 @@ int enqueue_batch(const jr_frame* frames, int32_t n, int32_t* out_base, int64_t 
     ws->ev_used[k] = true;
     const int blocks = grid_blocks(info, s, t.total_tiles);
     const jr::PersistentArgs args = make_args(t, ws->d_table, out_base, ws->d_ctr, n, blocks, s);
-    hipError_t e = jr::launch_tiled(s.unroll, s.defer, t.dtmask, blocks, args, stream);
+    hipError_t e = s.kernel == JR_KERNEL_PLAIN
+                       ? jr::launch_plain_batch(t.dtmask, args, stream)
+                       : jr::launch_tiled(s.unroll, s.defer, t.dtmask, blocks, args, stream);
     if (e != hipSuccess) return hip_fail(e, "persistent kernel launch");
     return JR_OK;
 }
@@ -455,7 +464,7 @@ struct jr_plan {
     unsigned long long* d_ctr = nullptr;
     int64_t total_tiles = 0;
     int dtmask = 0;
-    int unroll = 1, defer = 0, blocks = 1;
+    int unroll = 1, defer = 0, blocks = 1, kernel = JR_KERNEL_TILED;
     jr::PersistentArgs args;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -559,6 +568,7 @@ int jr_plan_create(const jr_frame* frames, int32_t n, int32_t* out_base, int64_t
     p->dtmask = t.dtmask;
     p->unroll = s.unroll;
     p->defer = s.defer;
+    p->kernel = s.kernel;
     p->blocks = grid_blocks(info, s, t.total_tiles);
     const size_t bytes = (size_t)n * sizeof(DevFrame);
     hipError_t e = hipMalloc((void**)&p->d_table, bytes);
@@ -575,10 +585,15 @@ int jr_plan_create(const jr_frame* frames, int32_t n, int32_t* out_base, int64_t
     return JR_OK;
 }
 
+static hipError_t plan_enqueue(const jr_plan* p, hipStream_t stream) {
+    return p->kernel == JR_KERNEL_PLAIN
+               ? jr::launch_plain_batch(p->dtmask, p->args, stream)
+               : jr::launch_tiled(p->unroll, p->defer, p->dtmask, p->blocks, p->args, stream);
+}
+
 int jr_plan_launch(jr_plan* p, void* stream) {
     if (!p) return fail(JR_EINVAL, "plan is null");
-    hipError_t e = jr::launch_tiled(p->unroll, p->defer, p->dtmask, p->blocks, p->args,
-                                    (hipStream_t)stream);
+    hipError_t e = plan_enqueue(p, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "plan launch");
     return JR_OK;
 }
@@ -594,7 +609,7 @@ int jr_plan_capture(jr_plan* p, void* stream) {
     }
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t le = jr::launch_tiled(p->unroll, p->defer, p->dtmask, p->blocks, p->args, s);
+        hipError_t le = plan_enqueue(p, s);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(s, &g);
         if (e == hipSuccess && le != hipSuccess) e = le;

@@ -551,6 +551,55 @@ __global__ __launch_bounds__(256) void jr_tiled(PersistentArgs a) {
     }
 }
 
+// One thread per pixel over a table of frames: workgroup b covers tile b
+// (16 x 16 pixels) of the frame that holds it, and every thread runs the
+// per-iteration test like jr_plain.  The batched form of the comparator,
+// and a candidate of the autotuner for images whose counts are low and even.
+template <class A>
+__device__ __forceinline__ void plain_pixel(CFrame& F, int i, int j, int32_t* out) {
+    const double px = pixel_re(F.cx, F.hx, i, F.width);
+    const double py = pixel_im(F.cy, F.hy, j, F.height);
+    typename A::Z z;
+    typename A::C c;
+    if (F.mode == kModeMandelbrot) {
+        z = A::make(A::coord(0.0), A::coord(0.0));
+        c = A::cmake(A::coord(px), A::coord(py));
+    } else {
+        z = A::make(A::coord(px), A::coord(py));
+        c = A::cmake(A::coord(F.cr), A::coord(F.ci));
+    }
+    int n = 0;
+    while (n < F.max_iter) {
+        if (!A::check_step(z, c)) break;
+        n++;
+    }
+    out[(int64_t)j * F.width + i] = n;
+}
+
+template <int DTMASK>
+__global__ __launch_bounds__(256) void jr_plain_batch(PersistentArgs a) {
+    CFrame* frames = cframes(a.frames);
+    const int64_t t = blockIdx.x;
+    // frames of equal size are common: start from the proportional guess
+    int guess = (int)((t * (int64_t)a.nframes) / a.total_tiles);
+    guess = min(max(guess, 0), a.nframes - 1);
+    const int f = find_frame(frames, a.nframes, t, frames[guess].tile_begin <= t ? guess : 0);
+    CFrame& F = frames[f];
+    const uint32_t local = (uint32_t)(t - F.tile_begin);
+    const int ty = (int)(local / (uint32_t)F.tiles_x);
+    const int tx = (int)(local - (uint32_t)ty * (uint32_t)F.tiles_x);
+    const int i = tx * F.tile_w + (int)(threadIdx.x & 15);
+    const int j = F.row_begin + ty * F.tile_h + (int)(threadIdx.x >> 4);
+    if (i >= F.width || j >= F.row_end) return;
+    int32_t* out = a.out_base + F.out_offset;
+    if ((DTMASK & (1 << kFP32)) && F.dtype == kFP32)
+        plain_pixel<ArF32>(F, i, j, out);
+    else if ((DTMASK & (1 << kFP64)) && F.dtype == kFP64)
+        plain_pixel<ArF64>(F, i, j, out);
+    else if ((DTMASK & (1 << kFF)) && F.dtype == kFF)
+        plain_pixel<ArFF>(F, i, j, out);
+}
+
 // Zeroes the kQueues counters before a persistent launch (a kernel, not a
 // memset, so that it can sit inside a captured hipGraph).
 __global__ void jr_reset_queues(unsigned long long* ctr) {
@@ -592,6 +641,22 @@ static TiledFn pick(int unroll, int defer, int dtmask) {
         case 8: return pick_mask<8, 0>(dtmask);
         default: return nullptr;
     }
+}
+
+static TiledFn pick_plain(int dtmask) {
+    switch (dtmask) {
+        case 1 << kFP64: return jr_plain_batch<1 << kFP64>;
+        case 1 << kFP32: return jr_plain_batch<1 << kFP32>;
+        case 1 << kFF: return jr_plain_batch<1 << kFF>;
+        default: return jr_plain_batch<7>;
+    }
+}
+
+hipError_t launch_plain_batch(int dtmask, const PersistentArgs& args, hipStream_t stream) {
+    if (args.total_tiles > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(pick_plain(dtmask), dim3((unsigned)args.total_tiles), dim3(256), 0, stream,
+                       args);
+    return hipGetLastError();
 }
 
 hipError_t launch_tiled(int unroll, int defer, int dtmask, int blocks, const PersistentArgs& args,

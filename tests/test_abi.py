@@ -105,10 +105,17 @@ def test_check_frames():
     ("tile_w", 0), ("tile_w", 65), ("tile_h", 0), ("tile_h", 65), ("unroll", 3),
     ("unroll", 16), ("unroll", 32), ("defer", 2), ("refill", 0), ("refill", 65),
     ("persistent", 2), ("waves_per_cu", 2), ("waves_per_cu", 6), ("waves_per_cu", 36),
+    ("kernel", "other"),
 ])
 def test_check_schedule_rejects(field, value):
     s = jr.Schedule()
     assert jr.check_schedule(s) == jr.JR_OK
+    if field == "kernel":
+        c = s.to_c()
+        c.kernel = 2
+        assert jr.lib.jr_check_schedule(ctypes.byref(c)) == jr.JR_EINVAL
+        assert jr.check_schedule(jr.Schedule(kernel="plain")) == jr.JR_OK
+        return
     assert jr.check_schedule(jr.Schedule(unroll=16, defer=1)) == jr.JR_OK
     assert jr.check_schedule(jr.Schedule(unroll=2, defer=1)) == jr.JR_EINVAL
     bad = jr.Schedule(**{**s.__dict__, field: value})

@@ -30,6 +30,7 @@ SCHEDULES = [
     jr.Schedule(8, 8, 8, 0, 32, 0, 16, "cost"),   # one wave per tile
     jr.Schedule(64, 64, 2, 0, 48, 0, 16, "table"),
     jr.Schedule(1, 1, 1, 0, 1, 1, 4, "cost"),     # one-pixel tiles
+    jr.Schedule(kernel="plain", order="table"),   # one thread per pixel, batched
 ]
 
 
@@ -148,7 +149,8 @@ def test_mixed_batch_one_launch(sched):
 
 @pytest.mark.parametrize("sched", [jr.Schedule(4, 4, 4, 0, 16, 1, 4, "table"),
                                    jr.Schedule(8, 2, 8, 1, 8, 1, 4, "table"),
-                                   jr.Schedule(3, 5, 2, 0, 64, 0, 16, "table")])
+                                   jr.Schedule(3, 5, 2, 0, 64, 0, 16, "table"),
+                                   jr.Schedule(kernel="plain", order="table")])
 def test_variant_switches_inside_a_wave(sched):
     """Frames alternate dtype, mode and absorbing/non-absorbing C in table order
     with small tiles, so a wave's stream changes variant many times."""
