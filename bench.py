@@ -194,22 +194,28 @@ def extra_legs(args, torch, jr, wl, frames, sched, ms_headline, iters):
         "gpixel_iter_s": round(it_u / (ms_u * 1e-3) / 1e9, 2), "ms": round(ms_u, 3),
         "plain_per_frame_ms": round(ms_up, 3), "vs_plain": round(ms_up / ms_u, 3),
         "pixels": sum(f.pixels for f in ub), "pixel_iters": it_u}
-    # serving: Poisson arrivals at several rates
+    # serving: Poisson arrivals at several rates, with the precision policy
+    # as specified (float-float for mid widths) and with FP64 for every window
+    # narrower than FP32 handles (on MI355X FP64 runs at the FP32 rate)
+    from paper_1611_03079_amd.serve import PrecisionPolicy
     serve = {}
-    for rate in (50, 200, 800, 2000):
-        n = max(20, int(rate * args.serve_seconds))
-        reqs = wl.serving_stream(11, float(rate), n)
-        cap = 8 * 1920 * 1080
-        srv = Server(GpuBackend(cap), cap, step_budget=2.0e8, copy_out=False)
-        st = run_open_loop(srv, reqs, drain_timeout=5.0)
-        torch.cuda.synchronize()
-        span = max(st.t_last - st.t_first, 1e-9)
-        serve["rate_%d" % rate] = {
-            "offered": n, "completed": st.completed,
-            "p50_ms": round(st.percentile(50) * 1e3, 2), "p99_ms": round(st.percentile(99) * 1e3, 2),
-            "completed_req_s": round(st.completed / span, 1), "steps": st.steps}
-        del srv
-        torch.cuda.empty_cache()
+    policies = {"ff_mid": PrecisionPolicy(), "fp64_narrow": PrecisionPolicy(ff_min_width=float("inf"))}
+    for pname, rates in (("ff_mid", (50, 200, 800, 2000)), ("fp64_narrow", (200, 2000))):
+        for rate in rates:
+            n = max(20, int(rate * args.serve_seconds))
+            reqs = wl.serving_stream(11, float(rate), n)
+            cap = 8 * 1920 * 1080
+            srv = Server(GpuBackend(cap), cap, step_budget=2.0e8, copy_out=False,
+                         policy=policies[pname])
+            st = run_open_loop(srv, reqs, drain_timeout=5.0)
+            torch.cuda.synchronize()
+            span = max(st.t_last - st.t_first, 1e-9)
+            serve["%s_rate_%d" % (pname, rate)] = {
+                "offered": n, "completed": st.completed,
+                "p50_ms": round(st.percentile(50) * 1e3, 2), "p99_ms": round(st.percentile(99) * 1e3, 2),
+                "completed_req_s": round(st.completed / span, 1), "steps": st.steps}
+            del srv
+            torch.cuda.empty_cache()
     ex["serving"] = serve
     # pixels whose FP32 / float-float count differs from FP64 (GPU vs GPU)
     mism = {}

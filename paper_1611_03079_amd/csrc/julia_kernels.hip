@@ -400,10 +400,9 @@ __device__ __forceinline__ void load_src(Src& s, const PersistentArgs& a, int64_
 //   it  the lane iterates an unfinished pixel,
 //   pe  (DEFER) it escaped inside the last block; the count needs a replay,
 //   fi  its final count is in cnt and not yet stored.
-// Blocks of K iterations run on every lane (a lane that is not iterating
-// computes values nobody reads), and the bookkeeping after a block is
-// selects, so a block costs vector instructions and few scalar ones.  A
-// counted block ends early once every iterating lane has escaped.
+// Blocks of K iterations run on every lane without branches (a lane that is
+// not iterating computes values nobody reads), and the bookkeeping after a
+// block is selects, so a block costs vector instructions and few scalar ones.
 //   DEFER = 0: every iterate is tested and the leading non-escaped iterates
 //     are counted (lead += |Z|^2 <= 4).  Escape being absorbing, the first
 //     escaped iterate is n + lead.  With K = 1 this is the exact test on every
@@ -432,8 +431,10 @@ __device__ void run_stream(Src& s, Claimer& cl, const PersistentArgs& a, double&
     typename A::C c = A::cmake(zero, zero);
     uint64_t running = 0;  // wave-uniform: ballot(it)
 
+    // refill <= 64, so a wave with no running lane always takes this branch
+    const int busy_max = 64 - a.refill;
     for (;;) {
-        if (64 - __popcll(running) >= a.refill || running == 0) {
+        if (__popcll(running) <= busy_max) {
             if (DEFER && __ballot(pe) != 0) {
                 // replay the last block from its start, on every lane
                 typename A::Z zr = zs;
@@ -503,13 +504,7 @@ __device__ void run_stream(Src& s, Claimer& cl, const PersistentArgs& a, double&
         } else {
             int lead = 0;
 #pragma unroll
-            for (int u = 0; u < K; ++u) {
-                const bool ok = A::check_step(z, c);
-                lead += ok ? 1 : 0;
-                // every iterating lane has escaped: the block can end here
-                // (each lane's lead is already final)
-                if (u + 1 < K && __ballot(ok && it) == 0) break;
-            }
+            for (int u = 0; u < K; ++u) lead += A::check_step(z, c) ? 1 : 0;
             const bool stop = (lead < K) || (n + K >= mi);
             const int final_cnt = min(n + lead, mi);
             cnt = (it && stop) ? final_cnt : cnt;

@@ -276,3 +276,29 @@ def test_largest_frame():
     np.testing.assert_array_equal(got, want)
     del out
     torch.cuda.empty_cache()
+
+
+# ------------------------------------------------ paths and zooms (Section 3)
+def test_cardioid_path_batch():
+    """The prescribed path of Section 3: C on f(t) with a = 3.9, then a growing
+    cardioid (a = 3.7), as one batched launch."""
+    frames = (wl.cardioid_path(12, 3.9, width=200, height=112, max_iter=200)
+              + wl.cardioid_path(6, 3.7, width=160, height=90, max_iter=150, dtype="fp64"))
+    _, views = batch(frames)
+    for f, v in zip(frames, views):
+        np.testing.assert_array_equal(v, ref(f))
+
+
+@pytest.mark.parametrize("width", [1e-3, 1e-5, 1e-7])
+def test_deep_zoom_windows(width):
+    """Narrow windows on the Mandelbrot set (C from Figure 3's deep zoom) and on
+    a Julia set: FP64 exact, float-float exact to its formulation, and its
+    difference from FP64 reported."""
+    cx, cy = 0.177078, 0.577384
+    win = (cx - width / 2, cx + width / 2, cy - width / 2, cy + width / 2)
+    for mode in ("mandelbrot", "julia"):
+        c = complex(cx, cy) if mode == "julia" else 0j
+        fr = [Frame(c, win, 96, 96, 600, dt, mode) for dt in ("fp64", "ff")]
+        _, views = batch(fr)
+        for f, v in zip(fr, views):
+            np.testing.assert_array_equal(v, ref(f))
