@@ -20,9 +20,10 @@
  *   - dtype selects the arithmetic of the iteration:
  *       JR_FP64  binary64, each operation rounded: x' = (x*x - y*y) + cr,
  *                y' = ((2x)*y) + ci, test fl(x*x + y*y) > 4.  Exact counts.
- *       JR_FP32  binary32 with fused multiply-add: test fma(x,x,y*y) > 4,
- *                x' = fma(-y, y, fma(x, x, cr)), y' = fma(x+x, y, ci);
- *                Z_0 and C are the binary64 values rounded to binary32.
+ *       JR_FP32  binary32 with fused multiply-add: with t = fma(x, x, cr),
+ *                test fma(y, y, t) > fl(4 + cr), x' = fma(-y, y, t),
+ *                y' = fma(x+x, y, ci); Z_0 and C are the binary64 values
+ *                rounded to binary32.
  *       JR_FF    float-float (a value is hi + lo of two binary32 numbers),
  *                error-free sums and products, for narrow (deep-zoom) windows.
  *     The three give the same count on most pixels; FP32 and FF differ from

@@ -66,21 +66,23 @@ static int32_t count_fp64(double x, double y, double cr, double ci, int32_t max_
 }
 
 /* ------------------------------------------------------------------------ */
-/* FP32 formulation (fixed so a GPU kernel can be compared bit for bit):     */
-/*   |Z|^2   = fma(x, x, y*y)                                                */
-/*   Re Z'   = fma(-y, y, fma(x, x, cr))                                     */
-/*   Im Z'   = fma(x + x, y, ci)                                             */
+/* FP32 formulation (fixed so a GPU kernel can be compared bit for bit).     */
+/* With t = fma(x, x, cr) = x^2 + Re C:                                      */
+/*   escape test   fma(y, y, t) > fl(4 + cr)   (|Z|^2 + Re C > 4 + Re C)     */
+/*   Re Z'       = fma(-y, y, t)                                             */
+/*   Im Z'       = fma(x + x, y, ci)                                         */
+/* The test shares x^2 + Re C with the update; both of its sides carry Re C. */
 /* Z_0 and C are the binary64 values rounded once to binary32.               */
 /* ------------------------------------------------------------------------ */
 static int32_t count_fp32(float x, float y, float cr, float ci, int32_t max_iter)
 {
+    const float lim = 4.0f + cr;
     int32_t n = 0;
     while (n < max_iter) {
-        float yy = y * y;
-        float m = fmaf(x, x, yy);
-        if (m > 4.0f)
-            break;
         float t = fmaf(x, x, cr);
+        float m = fmaf(y, y, t);
+        if (m > lim)
+            break;
         float xn = fmaf(-y, y, t);
         float tx = x + x;
         float yn = fmaf(tx, y, ci);

@@ -53,7 +53,7 @@ struct ArF64 {
     __device__ static V shfl(V v, int src) { return __shfl(v, src); }
     __device__ static Z make(V x, V y) { return Z{x, y}; }
     __device__ static C cmake(V r, V i) { return C{r, i}; }
-    __device__ static bool inside(const Z& z) {
+    __device__ static bool inside(const Z& z, const C&) {
         double x2 = z.x * z.x;
         double y2 = z.y * z.y;
         return x2 + y2 <= 4.0;
@@ -81,29 +81,36 @@ struct ArF64 {
     }
 };
 
+// FP32: with t = fma(x, x, cr) = x^2 + Re C, the escape test is
+// fma(y, y, t) > lim, lim = fl(4 + cr) (both sides carry Re C), and the update
+// x' = fma(-y, y, t), y' = fma(x + x, y, ci): the test shares t with the
+// update, 7 vector instructions per tested iteration with the count.
 struct ArF32 {
     struct Z { float x, y; };
-    struct C { float r, i; };
+    struct C { float r, i, lim; };
     using V = float;
     __device__ static V coord(double v) { return (float)v; }  // one rounding
     __device__ static V shfl(V v, int src) { return __shfl(v, src); }
     __device__ static Z make(V x, V y) { return Z{x, y}; }
-    __device__ static C cmake(V r, V i) { return C{r, i}; }
-    __device__ static bool inside(const Z& z) {
-        float yy = z.y * z.y;
-        return __builtin_fmaf(z.x, z.x, yy) <= 4.0f;
-    }
-    __device__ static void step(Z& z, const C& c) {
+    __device__ static C cmake(V r, V i) { return C{r, i, 4.0f + r}; }
+    __device__ static bool inside(const Z& z, const C& c) {
         float t = __builtin_fmaf(z.x, z.x, c.r);
+        return __builtin_fmaf(z.y, z.y, t) <= c.lim;
+    }
+    __device__ static void advance(Z& z, const C& c, float t) {
         float xn = __builtin_fmaf(-z.y, z.y, t);
         float tx = z.x + z.x;
         float yn = __builtin_fmaf(tx, z.y, c.i);
         z.x = xn;
         z.y = yn;
     }
+    __device__ static void step(Z& z, const C& c) {
+        advance(z, c, __builtin_fmaf(z.x, z.x, c.r));
+    }
     __device__ static bool check_step(Z& z, const C& c) {
-        bool ok = inside(z);
-        step(z, c);
+        float t = __builtin_fmaf(z.x, z.x, c.r);
+        bool ok = __builtin_fmaf(z.y, z.y, t) <= c.lim;
+        advance(z, c, t);
         return ok;
     }
 };
@@ -162,7 +169,7 @@ struct ArFF {
     __device__ static Z make(V x, V y) { return Z{x, y}; }
     __device__ static C cmake(V r, V i) { return C{r, i}; }
     __device__ static bool le4(D m) { return (m.hi < 4.0f) || (m.hi == 4.0f && m.lo <= 0.0f); }
-    __device__ static bool inside(const Z& z) {
+    __device__ static bool inside(const Z& z, const C&) {
         return le4(add(mul(z.x, z.x), mul(z.y, z.y)));
     }
     __device__ static void advance(Z& z, const C& c, D x2, D y2) {
@@ -493,7 +500,7 @@ __device__ void run_stream(Src& s, Claimer& cl, const PersistentArgs& a, double&
             zs = pe ? zs : z;  // a lane waiting for its replay keeps its block start
 #pragma unroll
             for (int u = 0; u < K; ++u) A::step(z, c);
-            const bool esc = !A::inside(z);
+            const bool esc = !A::inside(z, c);
             const bool capped = n + K >= mi;  // no escape up to n + K >= cap: absorbing
             cnt = (it && !esc && capped) ? mi : cnt;
             fi = fi || (it && !esc && capped);

@@ -92,9 +92,11 @@ def counts_fp32(x0, y0, cr, ci, max_iter):
     cr = np.broadcast_to(np.asarray(cr, F64).astype(F32), x0.shape)
     ci = np.broadcast_to(np.asarray(ci, F64).astype(F32), x0.shape)
 
+    lim = F32(4.0) + cr
+
     def esc(s):
         x, y = s
-        return fmaf(x, x, y * y) > F32(4.0)
+        return fmaf(y, y, fmaf(x, x, cr)) > lim
 
     def step(s, act):
         x, y = s

@@ -30,7 +30,8 @@ MUTANTS = {
                       "double hx = (re_max - re_min) / (2.0 * (double)W - 2.0);"),
     "cap_plus_one": ("    while (n < max_iter) {\n        double x2",
                      "    while (n <= max_iter) {\n        double x2"),
-    "fp32_unfused_norm": ("float m = fmaf(x, x, yy);", "float m = x * x + yy;"),
+    "fp32_unfused_norm": ("float m = fmaf(y, y, t);", "float m = y * y + t;"),
+    "fp32_unshifted_limit": ("const float lim = 4.0f + cr;", "const float lim = 4.0f;"),
     "fp32_sign": ("float xn = fmaf(-y, y, t);", "float xn = fmaf(y, y, t);"),
     "ff_lost_sl": ("float c = sl + th;", "float c = th;"),
     "ff_lost_cross": ("float cross = fmaf(x.lo, y.hi, cross1);", "float cross = cross1;"),
@@ -50,7 +51,7 @@ def _battery():
     checks += [("fingerprint", pins.test_c1_fingerprint, ()),
                ("centres", pins.test_pixel_centres, ()),
                ("sub_ulp_escape", pins.test_escape_by_less_than_fp32_ulp, ()),
-               ("fp32_fused", pins.test_fp32_escape_test_is_fused, ()),
+               ("fp32_formulation", pins.test_fp32_escape_test_formulation, ()),
                ("cap01_fp64", pins.test_cap_zero_and_one, ("fp64",)),
                ("eft", pins.test_error_free_transforms, ()),
                ("dw_bounds", pins.test_double_word_error_bounds, ())]

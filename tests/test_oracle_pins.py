@@ -82,28 +82,32 @@ def _rn32(q):
     return sign * Fr(lo) / scale
 
 
-def test_fp32_escape_test_is_fused():
-    """The FP32 formulation tests fma(x, x, RN(y*y)) > 4, one rounding after the
-    exact x^2 + RN(y^2).  Points near |Z| = 2 where this and the unfused
-    RN(RN(x^2) + RN(y^2)) disagree pin that the oracle fuses (expected values
-    from exact rational arithmetic)."""
+def test_fp32_escape_test_formulation():
+    """The FP32 formulation tests fma(y, y, fma(x, x, cr)) > fl(4 + cr): two
+    single roundings of x^2 + cr and then + y^2, against 4 + cr rounded once.
+    Points near |Z| = 2 where this decision differs from the plain
+    RN(RN(x^2) + RN(y^2)) > 4 pin the formulation (expected values from exact
+    rational arithmetic)."""
     rng = np.random.default_rng(11)
     found = 0
-    for _ in range(200000):
-        t = rng.uniform(0, np.pi / 2)
-        x = np.float32(2 * np.cos(t))
-        y = np.float32(2 * np.sin(t))
-        X, Y = Fraction(float(x)), Fraction(float(y))
-        yy = _rn32(Y * Y)
-        fused = _rn32(X * X + yy) > 4
-        unfused = _rn32(_rn32(X * X) + yy) > 4
-        if fused != unfused:
-            got = oracle.count(complex(float(x), float(y)), 0j, 1, "fp32")
-            assert got == (0 if fused else 1), (x, y)
-            found += 1
-            if found == 5:
-                break
-    assert found == 5
+    for cr in (-0.8, 0.285, -1.75):
+        crf = Fraction(float(np.float32(cr)))
+        lim = _rn32(4 + crf)
+        for _ in range(100000):
+            t = rng.uniform(0, np.pi / 2)
+            x = np.float32(2 * np.cos(t))
+            y = np.float32(2 * np.sin(t))
+            X, Y = Fraction(float(x)), Fraction(float(y))
+            m = _rn32(Y * Y + _rn32(X * X + crf))
+            ours = m > lim
+            other = _rn32(_rn32(X * X) + _rn32(Y * Y)) > 4
+            if ours != other:
+                got = oracle.count(complex(float(x), float(y)), complex(cr, 0.0), 1, "fp32")
+                assert got == (0 if ours else 1), (cr, x, y)
+                found += 1
+                if found % 4 == 0:
+                    break
+    assert found >= 8
 
 
 # --------------------------------------------------- independent reimplementations
