@@ -39,7 +39,8 @@ constexpr int kQueueStride = 512;  // u64 elements between two counters (4 KiB)
 constexpr size_t kCounterBytes = (size_t)kQueues * kQueueStride * sizeof(unsigned long long);
 
 struct PersistentArgs {
-    const DevFrame* frames;
+    DevFrame frame0;         // the frame itself when frames == nullptr (one-frame launches)
+    const DevFrame* frames;  // device frame table, or nullptr: use frame0
     int32_t* out_base;
     unsigned long long* ctr;
     int64_t total_tiles;

@@ -196,6 +196,7 @@ int32_t granule_size(const Table& t, int blocks) {
 jr::PersistentArgs make_args(const Table& t, const DevFrame* d_table, int32_t* out,
                              unsigned long long* ctr, int32_t n, int blocks, const jr_schedule& s) {
     jr::PersistentArgs a;
+    std::memset(&a, 0, sizeof a);
     a.frames = d_table;
     a.out_base = out;
     a.ctr = ctr;
@@ -359,16 +360,28 @@ int enqueue_batch(const jr_frame* frames, int32_t n, int32_t* out_base, int64_t 
     int dev;
     DeviceInfo info;
     if ((rc = current_device(&dev, &info))) return rc;
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    HIP_TRY(hipStreamIsCapturing(stream, &cap), "hipStreamIsCapturing");
-    if (cap != hipStreamCaptureStatusNone)
-        return fail(JR_EINVAL, "batch: stream is being captured; use jr_plan_capture for graphs");
-
     Table t;
     build_table(frames, n, s, t);
     Workspace* ws;
     if ((rc = get_workspace(dev, stream, &ws))) return rc;
     std::lock_guard<std::mutex> g(ws->mu);
+    const int blocks = grid_blocks(info, s, t.total_tiles);
+    if (n == 1) {
+        // one frame travels inside the kernel arguments: no table upload
+        jr::PersistentArgs args = make_args(t, nullptr, out_base, ws->d_ctr, n, blocks, s);
+        args.frame0 = t.rows[0];
+        hipError_t e = s.kernel == JR_KERNEL_PLAIN
+                           ? jr::launch_plain_batch(t.dtmask, args, stream)
+                           : jr::launch_tiled(s.unroll, s.defer, t.dtmask, blocks, args, stream);
+        if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        return JR_OK;
+    }
+    // Several frames go through the pinned staging ring, whose copy a graph
+    // would replay from memory the ring reuses: refuse capture (plans capture).
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(stream, &cap), "hipStreamIsCapturing");
+    if (cap != hipStreamCaptureStatusNone)
+        return fail(JR_EINVAL, "batch of %d frames on a capturing stream; use jr_plan_capture", n);
     const size_t bytes = (size_t)n * sizeof(DevFrame);
     if (ws->table_cap < bytes) {
         // The old table may still be read by work queued on this stream.
@@ -397,7 +410,6 @@ int enqueue_batch(const jr_frame* frames, int32_t n, int32_t* out_base, int64_t 
             "hipMemcpyAsync frame table");
     HIP_TRY(hipEventRecord(ws->ev[k], stream), "hipEventRecord");
     ws->ev_used[k] = true;
-    const int blocks = grid_blocks(info, s, t.total_tiles);
     const jr::PersistentArgs args = make_args(t, ws->d_table, out_base, ws->d_ctr, n, blocks, s);
     hipError_t e = s.kernel == JR_KERNEL_PLAIN
                        ? jr::launch_plain_batch(t.dtmask, args, stream)

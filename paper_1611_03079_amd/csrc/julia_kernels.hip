@@ -326,7 +326,17 @@ __device__ __forceinline__ int64_t next_tile(Claimer& cl, const PersistentArgs& 
 // is wave-uniform), which it cannot prove safe through a generic pointer that
 // might alias the output.
 typedef const __attribute__((address_space(4))) DevFrame CFrame;
-__device__ __forceinline__ CFrame* cframes(const DevFrame* p) { return (CFrame*)p; }
+typedef const __attribute__((address_space(4))) char CByte;
+
+// The frame table of a launch: the device table, or for a one-frame launch
+// the copy inside the kernel arguments (the single by-value PersistentArgs
+// argument sits at offset 0 of the kernel-argument segment), which saves the
+// host a table upload per image.
+__device__ __forceinline__ CFrame* cframes(const PersistentArgs& a) {
+    if (a.frames) return (CFrame*)a.frames;
+    CByte* k = (CByte*)__builtin_amdgcn_kernarg_segment_ptr();
+    return (CFrame*)(k + offsetof(PersistentArgs, frame0));
+}
 
 // Largest frame index f with frames[f].tile_begin <= t.  A short forward scan
 // from the previous frame usually ends it; otherwise binary search.
@@ -375,7 +385,7 @@ __device__ __forceinline__ void load_src(Src& s, const PersistentArgs& a, int64_
                                          double& xd, double& yd, double& cr, double& ci) {
     s.t = t;
     if (t < 0) return;
-    CFrame* frames = cframes(a.frames);
+    CFrame* frames = cframes(a);
     s.f = find_frame(frames, a.nframes, t, s.f);
     CFrame& F = frames[s.f];
     const uint32_t local = (uint32_t)(t - F.tile_begin);  // < 2^31 tiles per frame
@@ -580,12 +590,15 @@ __device__ __forceinline__ void plain_pixel(CFrame& F, int i, int j, int32_t* ou
 
 template <int DTMASK>
 __global__ __launch_bounds__(256) void jr_plain_batch(PersistentArgs a) {
-    CFrame* frames = cframes(a.frames);
+    CFrame* frames = cframes(a);
     const int64_t t = blockIdx.x;
-    // frames of equal size are common: start from the proportional guess
-    int guess = (int)((t * (int64_t)a.nframes) / a.total_tiles);
-    guess = min(max(guess, 0), a.nframes - 1);
-    const int f = find_frame(frames, a.nframes, t, frames[guess].tile_begin <= t ? guess : 0);
+    int f = 0;
+    if (a.nframes > 1) {
+        // frames of equal size are common: start from the proportional guess
+        int guess = (int)((double)t * (double)a.nframes / (double)a.total_tiles);
+        guess = min(max(guess, 0), a.nframes - 1);
+        f = find_frame(frames, a.nframes, t, frames[guess].tile_begin <= t ? guess : 0);
+    }
     CFrame& F = frames[f];
     const uint32_t local = (uint32_t)(t - F.tile_begin);
     const int ty = (int)(local / (uint32_t)F.tiles_x);

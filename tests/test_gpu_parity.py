@@ -203,6 +203,27 @@ def test_plan_launch_and_graph_replay():
     plan.close()
 
 
+def test_single_frame_render_in_torch_graph():
+    """A one-frame render carries its frame in the kernel arguments, so a torch
+    CUDA graph can capture it; every replay (with eager work between) gives
+    the oracle's counts."""
+    f = Frame(C1, UNIT, 300, 200, 150, "fp32")
+    out = torch.empty((200, 300), dtype=torch.int32, device="cuda")
+    jr.render(f.c, f.window, 300, 200, 150, "fp32", out=out)   # warm up outside capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        jr.render(f.c, f.window, 300, 200, 150, "fp32", out=out,
+                  schedule=jr.Schedule(64, 16, 8, 0, 32, 0, 16, "cost"))
+    want = ref(f)
+    for _ in range(3):
+        out.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out.cpu().numpy(), want)
+
+
 def test_streams_are_independent():
     f1 = Frame(C1, UNIT, 256, 256, 300, "fp64")
     f2 = Frame(complex(0.3, 0.5), UNIT, 256, 256, 300, "fp32")
