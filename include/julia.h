@@ -118,9 +118,14 @@ typedef struct {
  *   kernel          JR_KERNEL_TILED: the tiled kernel above;
  *                   JR_KERNEL_PLAIN: one thread per pixel over the whole batch
  *                   (16 x 16 tiles, one workgroup each, a test on every
- *                   iteration); the other fields are then ignored.
+ *                   iteration); the other fields are then ignored;
+ *                   JR_KERNEL_HYBRID: the tiled kernel where each wave runs 64
+ *                   fresh pixels at a time with a test on every iteration and
+ *                   only the pixels still running after `bail` iterations
+ *                   continue in refilled blocks (they wait in shared memory).
+ *   bail            JR_KERNEL_HYBRID: 1..4096 (other kernels ignore it).
  */
-typedef enum { JR_KERNEL_TILED = 0, JR_KERNEL_PLAIN = 1 } jr_kernel;
+typedef enum { JR_KERNEL_TILED = 0, JR_KERNEL_PLAIN = 1, JR_KERNEL_HYBRID = 2 } jr_kernel;
 typedef struct {
     int32_t tile_w, tile_h;
     int32_t unroll;
@@ -130,6 +135,7 @@ typedef struct {
     int32_t waves_per_cu;
     int32_t order;
     int32_t kernel;
+    int32_t bail;
 } jr_schedule;
 
 /*

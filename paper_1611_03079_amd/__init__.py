@@ -21,7 +21,7 @@ JR_OK, JR_EINVAL, JR_ENOMEM, JR_ENODEV, JR_ELAUNCH, JR_EINTERNAL = 0, -1, -2, -3
 DTYPES = {"fp64": 0, "fp32": 1, "ff": 2}
 MODES = {"julia": 0, "mandelbrot": 1}
 ORDERS = {"table": 0, "cost": 1}
-KERNELS = {"tiled": 0, "plain": 1}
+KERNELS = {"tiled": 0, "plain": 1, "hybrid": 2}
 
 
 class JuliaError(RuntimeError):
@@ -53,7 +53,7 @@ class jr_schedule(ctypes.Structure):
                 ("unroll", ctypes.c_int32), ("defer", ctypes.c_int32),
                 ("refill", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("waves_per_cu", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("kernel", ctypes.c_int32)]
+                ("kernel", ctypes.c_int32), ("bail", ctypes.c_int32)]
 
 
 assert ctypes.sizeof(jr_frame) == 88
@@ -71,18 +71,19 @@ class Schedule:
     waves_per_cu: int = 16
     order: str = "cost"
     kernel: str = "tiled"
+    bail: int = 8
 
     def to_c(self) -> jr_schedule:
         return jr_schedule(self.tile_w, self.tile_h, self.unroll, self.defer, self.refill,
                            self.persistent, self.waves_per_cu, ORDERS[self.order],
-                           KERNELS[self.kernel])
+                           KERNELS[self.kernel], self.bail)
 
     @staticmethod
     def from_c(s: jr_schedule) -> "Schedule":
         inv = {v: k for k, v in ORDERS.items()}
         invk = {v: k for k, v in KERNELS.items()}
         return Schedule(s.tile_w, s.tile_h, s.unroll, s.defer, s.refill, s.persistent,
-                        s.waves_per_cu, inv[s.order], invk[s.kernel])
+                        s.waves_per_cu, inv[s.order], invk[s.kernel], s.bail)
 
 
 EXPORTS = (

@@ -11,7 +11,9 @@ Search, in stages from a base schedule:
   2. tile shape x scheduling mode x refill threshold,
   3. resident waves per compute unit (persistent mode only),
   4. the iteration block again under the chosen tiling,
-  5. the batched one-thread-per-pixel kernel as a last candidate.
+  5. the hybrid stream (fresh packets tested every iteration, survivors
+     refilled) under that tiling, for several bail points,
+  6. the batched one-thread-per-pixel kernel as a last candidate.
 
 Results are cached in a JSON file keyed by (device, dtype, cap bucket, pixel
 bucket); ``apply_cache`` installs the cached winners as the library defaults
@@ -30,6 +32,7 @@ BLOCKS = [(1, 0), (2, 0), (4, 0), (8, 0), (4, 1), (8, 1), (16, 1)]
 TILES = [(64, 1), (64, 4), (64, 16), (32, 8), (16, 16), (64, 64)]
 REFILLS = [8, 16, 32, 64]
 WAVES = [8, 16, 24, 32]
+HYBRID_BAILS = [4, 8, 16, 32]
 
 DEFAULT_CACHE = os.environ.get(
     "JR_AUTOTUNE_CACHE",
@@ -98,6 +101,14 @@ def tune(frames: Sequence, base: Optional[jr.Schedule] = None, reps: int = 3,
     # re-check the block choice under the final tiling
     s = _stage(frames, s, [dict(unroll=u, defer=d) for u, d in BLOCKS], reps, log)
     best_t = min(t for d, t in log if jr.Schedule(**d) == s)
+    # the hybrid stream under the chosen tiling, with several bail points
+    tiled = s
+    for bail in HYBRID_BAILS:
+        h = replace(tiled, kernel="hybrid", bail=bail)
+        t = time_plan(frames, h, reps=reps)
+        log.append((asdict(h), t))
+        if t < best_t:
+            s, best_t = h, t
     # the one-thread-per-pixel kernel over the batch is a candidate too
     plain = jr.Schedule(kernel="plain", order=s.order)
     t = time_plan(frames, plain, reps=reps)

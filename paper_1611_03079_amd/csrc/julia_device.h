@@ -49,6 +49,8 @@ struct PersistentArgs {
     int32_t granule;     // tiles per granule
     int32_t refill;
     int32_t persistent;  // 1: work queues; 0: one wave per tile
+    int32_t hybrid;      // 1: fresh packets + survivor queue (run_hybrid)
+    int32_t bail;        // hybrid: iterations of a fresh packet before its survivors park
 };
 
 struct PlainArgs {

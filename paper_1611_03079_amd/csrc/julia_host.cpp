@@ -109,8 +109,11 @@ int check_schedule(const jr_schedule& s) {
         return fail(JR_EINVAL, "schedule: waves_per_cu must be 4..32, a multiple of 4");
     if (s.order != JR_ORDER_TABLE && s.order != JR_ORDER_COST)
         return fail(JR_EINVAL, "schedule: unknown order %d", s.order);
-    if (s.kernel != JR_KERNEL_TILED && s.kernel != JR_KERNEL_PLAIN)
+    if (s.kernel != JR_KERNEL_TILED && s.kernel != JR_KERNEL_PLAIN &&
+        s.kernel != JR_KERNEL_HYBRID)
         return fail(JR_EINVAL, "schedule: unknown kernel %d", s.kernel);
+    if (s.kernel == JR_KERNEL_HYBRID && (s.bail < 1 || s.bail > 4096))
+        return fail(JR_EINVAL, "schedule: bail must be in 1..4096 (got %d)", s.bail);
     return JR_OK;
 }
 
@@ -142,10 +145,10 @@ std::mutex g_sched_mu;
 // Starting points from the autotuner's runs on MI355X (one wave per tile was
 // faster than the work queues on every workload measured).
 jr_schedule g_default[3] = {
-    // tile_w, tile_h, unroll, defer, refill, persistent, waves_per_cu, order, kernel
-    {16, 16, 8, 0, 16, 0, 16, JR_ORDER_COST, JR_KERNEL_TILED},  // FP64
-    {64, 16, 8, 1, 32, 0, 16, JR_ORDER_COST, JR_KERNEL_TILED},  // FP32
-    {16, 16, 8, 1, 64, 0, 16, JR_ORDER_COST, JR_KERNEL_TILED},  // FF
+    // tile_w, tile_h, unroll, defer, refill, persistent, waves_per_cu, order, kernel, bail
+    {16, 16, 8, 0, 16, 0, 16, JR_ORDER_COST, JR_KERNEL_TILED, 8},  // FP64
+    {64, 16, 8, 1, 32, 0, 16, JR_ORDER_COST, JR_KERNEL_TILED, 8},  // FP32
+    {16, 16, 8, 1, 64, 0, 16, JR_ORDER_COST, JR_KERNEL_TILED, 8},  // FF
 };
 
 jr_schedule default_schedule(int dtype) {
@@ -206,6 +209,8 @@ jr::PersistentArgs make_args(const Table& t, const DevFrame* d_table, int32_t* o
     a.granules = (t.total_tiles + a.granule - 1) / a.granule;
     a.refill = s.refill;
     a.persistent = s.persistent;
+    a.hybrid = s.kernel == JR_KERNEL_HYBRID ? 1 : 0;
+    a.bail = s.bail;
     return a;
 }
 

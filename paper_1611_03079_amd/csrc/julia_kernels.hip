@@ -533,34 +533,249 @@ __device__ void run_stream(Src& s, Claimer& cl, const PersistentArgs& a, double&
     }
 }
 
+// ---------------------------------------------------------------------------
+// Hybrid stream: fresh pixels run like the plain kernel, survivors refill.
+// ---------------------------------------------------------------------------
+// A wave takes 64 fresh pixels at a time (a packet) and iterates them with
+// the exact per-iteration test; the packet ends as soon as every lane has
+// escaped or hit its cap, or after `bail` iterations.  Pixels still running
+// then (the survivors, typically a small minority) are parked in a per-wave
+// queue in LDS.  When a packet's survivors no longer fit, the wave drains the
+// queue with the refill stream (blocks of K, lanes refilled from the queue);
+// once the queue is empty and few lanes are still running, those are parked
+// and fresh packets resume.  Fresh pixels so pay no block overshoot, and the
+// long orbits still keep every lane busy.
+constexpr int kQ = 64;            // queue slots per wave
+constexpr int kQWordsMax = 12;    // 32-bit words of one parked lane, at most
+
+template <class A>
+struct Parked {
+    typename A::Z z;
+    typename A::C c;
+    int n, mi;
+    int32_t* outp;
+};
+
+template <class A>
+__device__ __forceinline__ void park(uint32_t* q, int slot, const Parked<A>& p) {
+    constexpr int W = (int)(sizeof(Parked<A>) / 4);
+    static_assert(W <= kQWordsMax, "parked lane too large");
+    uint32_t w[W];
+    __builtin_memcpy(w, &p, sizeof(Parked<A>));
+#pragma unroll
+    for (int j = 0; j < W; ++j) q[j * kQ + slot] = w[j];
+}
+
+template <class A>
+__device__ __forceinline__ Parked<A> unpark(const uint32_t* q, int slot) {
+    constexpr int W = (int)(sizeof(Parked<A>) / 4);
+    uint32_t w[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) w[j] = q[j * kQ + slot];
+    Parked<A> p;
+    __builtin_memcpy(&p, w, sizeof(Parked<A>));
+    return p;
+}
+
+template <class A, int K, int DEFER>
+__device__ void run_hybrid(Src& s, Claimer& cl, const PersistentArgs& a, double& xd, double& yd,
+                           double& crd, double& cid, uint32_t* q) {
+    using V = typename A::V;
+    const int my_variant = s.variant;
+    const V zero = A::coord(0.0);
+    V xcol = A::coord(xd), yrow = A::coord(yd);
+    V cre = A::coord(crd), cim = A::coord(cid);
+    bool src_ok = true;
+    bool it = false, pe = false, fi = false;
+    int n = 0, cnt = 0, mi = 0;
+    int32_t* outp = s.out;
+    typename A::Z z = A::make(zero, zero);
+    typename A::Z zs = z;
+    typename A::C c = A::cmake(zero, zero);
+    int qn = 0;  // wave-uniform: lanes parked in q
+    const int busy_max = 64 - a.refill;
+
+    for (;;) {
+        // ------------------------------------------------ fresh packet
+        if (src_ok) {
+            uint64_t idle = ~__ballot(it);  // all lanes: nothing runs here
+            while (idle != 0 && src_ok) {
+                const int k = s.next + lanes_below(idle);
+                const int kk = min(k, s.npix - 1);
+                const int row = (int)(((uint32_t)kk * s.magic) >> 18);
+                const int col = kk - row * s.tw;
+                const V x0 = A::shfl(xcol, col);
+                const V y0 = A::shfl(yrow, row);
+                if (!it && k < s.npix) {
+                    if (s.mode == kModeMandelbrot) {
+                        z = A::make(zero, zero);
+                        c = A::cmake(x0, y0);
+                    } else {
+                        z = A::make(x0, y0);
+                        c = A::cmake(cre, cim);
+                    }
+                    n = 0;
+                    mi = s.max_iter;
+                    outp = s.out + (row * s.W + col);
+                    it = true;
+                }
+                s.next += __popcll(idle);
+                if (s.next >= s.npix) {
+                    load_src(s, a, next_tile(cl, a), xd, yd, crd, cid);
+                    if (s.t < 0 || s.variant != my_variant) {
+                        src_ok = false;
+                    } else {
+                        xcol = A::coord(xd);
+                        yrow = A::coord(yd);
+                        cre = A::coord(crd);
+                        cim = A::coord(cid);
+                    }
+                }
+                idle = ~__ballot(it);
+            }
+            // the exact test on every iteration, until every lane is done
+            for (int u = 0; u < a.bail; ++u) {
+                const bool ok = A::check_step(z, c);
+                const bool stop = it && (!ok || n >= mi);
+                cnt = stop ? n : cnt;
+                fi = fi || stop;
+                it = it && !stop;
+                n += it ? 1 : 0;
+                if (__ballot(it) == 0) break;
+            }
+            if (fi) {
+                *outp = cnt;
+                fi = false;
+            }
+            const uint64_t surv = __ballot(it);
+            const int ns = __popcll(surv);
+            if (qn + ns <= kQ && (src_ok || ns == 0)) {
+                if (it) {
+                    Parked<A> p{z, c, n, mi, outp};
+                    park<A>(q, qn + lanes_below(surv), p);
+                    it = false;
+                }
+                qn += ns;
+                if (src_ok) continue;
+            }
+            // survivors do not fit (or the source is done): drain below
+        }
+        // ------------------------------------------------ drain the queue
+        uint64_t running = __ballot(it);
+        for (;;) {
+            if (__popcll(running) <= busy_max) {
+                if (DEFER && __ballot(pe) != 0) {
+                    typename A::Z zr = zs;
+                    int lead = 0;
+#pragma unroll
+                    for (int u = 0; u < K; ++u) lead += A::check_step(zr, c) ? 1 : 0;
+                    if (pe) {
+                        cnt = min(n + lead, mi);
+                        fi = true;
+                        pe = false;
+                    }
+                }
+                if (fi) {
+                    *outp = cnt;
+                    fi = false;
+                }
+                const uint64_t idle = ~__ballot(it);
+                const int take = min(qn, __popcll(idle));
+                if (take > 0) {
+                    const int r = lanes_below(idle);
+                    if (!it && r < take) {
+                        const Parked<A> p = unpark<A>(q, qn - 1 - r);
+                        z = p.z;
+                        c = p.c;
+                        n = p.n;
+                        mi = p.mi;
+                        outp = p.outp;
+                        it = true;
+                    }
+                    qn -= take;
+                }
+                running = __ballot(it);
+                if (qn == 0) {
+                    if (src_ok && __popcll(running) <= busy_max) {
+                        // park the few lanes still running and go back to fresh packets
+                        if (it) {
+                            Parked<A> p{z, c, n, mi, outp};
+                            park<A>(q, lanes_below(running), p);
+                            it = false;
+                        }
+                        qn = __popcll(running);
+                        break;
+                    }
+                    if (!src_ok && running == 0) return;
+                }
+            }
+            if (DEFER) {
+                zs = pe ? zs : z;
+#pragma unroll
+                for (int u = 0; u < K; ++u) A::step(z, c);
+                const bool esc = !A::inside(z, c);
+                const bool capped = n + K >= mi;
+                cnt = (it && !esc && capped) ? mi : cnt;
+                fi = fi || (it && !esc && capped);
+                pe = pe || (it && esc);
+                it = it && !esc && !capped;
+                n += K;
+                n -= (pe && !it) ? K : 0;
+            } else {
+                int lead = 0;
+#pragma unroll
+                for (int u = 0; u < K; ++u) lead += A::check_step(z, c) ? 1 : 0;
+                const bool stop = (lead < K) || (n + K >= mi);
+                const int final_cnt = min(n + lead, mi);
+                cnt = (it && stop) ? final_cnt : cnt;
+                fi = fi || (it && stop);
+                it = it && !stop;
+                n += K;
+            }
+            running = __ballot(it);
+        }
+    }
+}
+
 // Persistent (or one-wave-per-tile) kernel over a table of frames: 256-thread
 // workgroups of 4 independent waves.  Each wave takes tiles from its Claimer
 // and hands them to the stream of the variant they need.
-template <int K, int DEFER, int DTMASK>
+template <int K, int DEFER, int DTMASK, int HYB>
 __global__ __launch_bounds__(256) void jr_tiled(PersistentArgs a) {
+    // per-wave survivor queues of the hybrid stream (unused otherwise)
+    __shared__ uint32_t qmem[HYB ? 4 * kQWordsMax * kQ : 1];
+    uint32_t* q = qmem + (HYB ? (threadIdx.x >> 6) * kQWordsMax * kQ : 0);
     Claimer cl;
     claimer_init(cl, a);
     Src s;
     s.f = 0;
     double xd, yd, cr, ci;
     load_src(s, a, next_tile(cl, a), xd, yd, cr, ci);
+#define JR_STREAM(A_, K_, D_)                                         \
+    do {                                                              \
+        if (HYB)                                                      \
+            run_hybrid<A_, K_, D_>(s, cl, a, xd, yd, cr, ci, q);      \
+        else                                                          \
+            run_stream<A_, K_, D_>(s, cl, a, xd, yd, cr, ci);         \
+    } while (0)
     while (s.t >= 0) {
         const int v = s.variant;
         if ((DTMASK & (1 << kFP32)) && v == variant_of(kFP32, 1))
-            run_stream<ArF32, K, DEFER>(s, cl, a, xd, yd, cr, ci);
+            JR_STREAM(ArF32, K, DEFER);
         else if ((DTMASK & (1 << kFP32)) && v == variant_of(kFP32, 0))
-            run_stream<ArF32, 1, 0>(s, cl, a, xd, yd, cr, ci);
+            JR_STREAM(ArF32, 1, 0);
         else if ((DTMASK & (1 << kFP64)) && v == variant_of(kFP64, 1))
-            run_stream<ArF64, K, DEFER>(s, cl, a, xd, yd, cr, ci);
+            JR_STREAM(ArF64, K, DEFER);
         else if ((DTMASK & (1 << kFP64)) && v == variant_of(kFP64, 0))
-            run_stream<ArF64, 1, 0>(s, cl, a, xd, yd, cr, ci);
+            JR_STREAM(ArF64, 1, 0);
         else if ((DTMASK & (1 << kFF)) && v == variant_of(kFF, 1))
-            run_stream<ArFF, K, DEFER>(s, cl, a, xd, yd, cr, ci);
+            JR_STREAM(ArFF, K, DEFER);
         else if ((DTMASK & (1 << kFF)) && v == variant_of(kFF, 0))
-            run_stream<ArFF, 1, 0>(s, cl, a, xd, yd, cr, ci);
+            JR_STREAM(ArFF, 1, 0);
         else
             load_src(s, a, next_tile(cl, a), xd, yd, cr, ci);  // not reached
     }
+#undef JR_STREAM
 }
 
 // One thread per pixel over a table of frames: workgroup b covers tile b
@@ -630,32 +845,37 @@ namespace jr {
 
 using TiledFn = void (*)(PersistentArgs);
 
-template <int K, int DEFER>
+template <int K, int DEFER, int HYB>
 static TiledFn pick_mask(int dtmask) {
     switch (dtmask) {
-        case 1 << kFP64: return jr_tiled<K, DEFER, 1 << kFP64>;
-        case 1 << kFP32: return jr_tiled<K, DEFER, 1 << kFP32>;
-        case 1 << kFF: return jr_tiled<K, DEFER, 1 << kFF>;
-        default: return jr_tiled<K, DEFER, 7>;
+        case 1 << kFP64: return jr_tiled<K, DEFER, 1 << kFP64, HYB>;
+        case 1 << kFP32: return jr_tiled<K, DEFER, 1 << kFP32, HYB>;
+        case 1 << kFF: return jr_tiled<K, DEFER, 1 << kFF, HYB>;
+        default: return jr_tiled<K, DEFER, 7, HYB>;
     }
 }
 
-static TiledFn pick(int unroll, int defer, int dtmask) {
+template <int HYB>
+static TiledFn pick_block(int unroll, int defer, int dtmask) {
     if (defer) {
         switch (unroll) {
-            case 4: return pick_mask<4, 1>(dtmask);
-            case 8: return pick_mask<8, 1>(dtmask);
-            case 16: return pick_mask<16, 1>(dtmask);
+            case 4: return pick_mask<4, 1, HYB>(dtmask);
+            case 8: return pick_mask<8, 1, HYB>(dtmask);
+            case 16: return pick_mask<16, 1, HYB>(dtmask);
             default: return nullptr;
         }
     }
     switch (unroll) {
-        case 1: return pick_mask<1, 0>(dtmask);
-        case 2: return pick_mask<2, 0>(dtmask);
-        case 4: return pick_mask<4, 0>(dtmask);
-        case 8: return pick_mask<8, 0>(dtmask);
+        case 1: return pick_mask<1, 0, HYB>(dtmask);
+        case 2: return pick_mask<2, 0, HYB>(dtmask);
+        case 4: return pick_mask<4, 0, HYB>(dtmask);
+        case 8: return pick_mask<8, 0, HYB>(dtmask);
         default: return nullptr;
     }
+}
+
+static TiledFn pick(int unroll, int defer, int dtmask, int hybrid) {
+    return hybrid ? pick_block<1>(unroll, defer, dtmask) : pick_block<0>(unroll, defer, dtmask);
 }
 
 static TiledFn pick_plain(int dtmask) {
@@ -676,7 +896,7 @@ hipError_t launch_plain_batch(int dtmask, const PersistentArgs& args, hipStream_
 
 hipError_t launch_tiled(int unroll, int defer, int dtmask, int blocks, const PersistentArgs& args,
                         hipStream_t stream) {
-    TiledFn fn = pick(unroll, defer, dtmask);
+    TiledFn fn = pick(unroll, defer, dtmask, args.hybrid);
     if (!fn) return hipErrorInvalidValue;
     if (args.persistent) {
         hipLaunchKernelGGL(jr_reset_queues, dim3(1), dim3(kQueues), 0, stream, args.ctr);

@@ -112,9 +112,12 @@ def test_check_schedule_rejects(field, value):
     assert jr.check_schedule(s) == jr.JR_OK
     if field == "kernel":
         c = s.to_c()
-        c.kernel = 2
+        c.kernel = 3
         assert jr.lib.jr_check_schedule(ctypes.byref(c)) == jr.JR_EINVAL
         assert jr.check_schedule(jr.Schedule(kernel="plain")) == jr.JR_OK
+        assert jr.check_schedule(jr.Schedule(kernel="hybrid", bail=16)) == jr.JR_OK
+        assert jr.check_schedule(jr.Schedule(kernel="hybrid", bail=0)) == jr.JR_EINVAL
+        assert jr.check_schedule(jr.Schedule(kernel="tiled", bail=0)) == jr.JR_OK
         return
     assert jr.check_schedule(jr.Schedule(unroll=16, defer=1)) == jr.JR_OK
     assert jr.check_schedule(jr.Schedule(unroll=2, defer=1)) == jr.JR_EINVAL
@@ -127,7 +130,7 @@ def test_default_schedules_are_valid_and_settable():
         s = jr.default_schedule(dt)
         assert jr.check_schedule(s) == jr.JR_OK
     old = jr.default_schedule("fp32")
-    new = jr.Schedule(32, 8, 8, 1, 8, 1, 24, "table")
+    new = jr.Schedule(32, 8, 8, 1, 8, 1, 24, "table", "hybrid", 12)
     jr.set_default_schedule("fp32", new)
     assert jr.default_schedule("fp32") == new
     jr.set_default_schedule("fp32", old)

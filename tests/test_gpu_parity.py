@@ -31,6 +31,9 @@ SCHEDULES = [
     jr.Schedule(64, 64, 2, 0, 48, 0, 16, "table"),
     jr.Schedule(1, 1, 1, 0, 1, 1, 4, "cost"),     # one-pixel tiles
     jr.Schedule(kernel="plain", order="table"),   # one thread per pixel, batched
+    jr.Schedule(64, 16, 8, 0, 16, 0, 16, "cost", "hybrid", 8),
+    jr.Schedule(32, 8, 8, 1, 32, 1, 16, "table", "hybrid", 3),
+    jr.Schedule(16, 16, 4, 0, 48, 0, 16, "cost", "hybrid", 1),
 ]
 
 
@@ -150,7 +153,9 @@ def test_mixed_batch_one_launch(sched):
 @pytest.mark.parametrize("sched", [jr.Schedule(4, 4, 4, 0, 16, 1, 4, "table"),
                                    jr.Schedule(8, 2, 8, 1, 8, 1, 4, "table"),
                                    jr.Schedule(3, 5, 2, 0, 64, 0, 16, "table"),
-                                   jr.Schedule(kernel="plain", order="table")])
+                                   jr.Schedule(kernel="plain", order="table"),
+                                   jr.Schedule(5, 3, 8, 1, 16, 1, 4, "table", "hybrid", 2),
+                                   jr.Schedule(8, 8, 2, 0, 8, 0, 16, "table", "hybrid", 5)])
 def test_variant_switches_inside_a_wave(sched):
     """Frames alternate dtype, mode and absorbing/non-absorbing C in table order
     with small tiles, so a wave's stream changes variant many times."""
