@@ -168,9 +168,10 @@ int mandelbrot_render_plain(jr_window w, int32_t width, int32_t height,
  * int32 elements holding every frame at its out_offset.  sched: NULL for the
  * default schedule of the batch's dominant dtype.  Frames must not overlap in
  * the arena where their computed rows overlap.  A one-frame call passes the
- * frame inside the kernel arguments and may be captured into a hipGraph; a
- * call with several frames uploads a table and returns JR_EINVAL on a
- * capturing stream (use jr_plan_capture).
+ * frame inside the kernel arguments; without the persistent work queues it is
+ * a single kernel launch that a hipGraph capture may record.  A call with
+ * several frames uploads a table and returns JR_EINVAL on a capturing stream
+ * (use jr_plan_capture).
  */
 int julia_render_batch(const jr_frame *frames, int32_t n, int32_t *out_base,
                        int64_t out_capacity, const jr_schedule *sched, void *stream);

@@ -319,12 +319,12 @@ int get_workspace(int dev, hipStream_t stream, Workspace** out) {
         *out = it->second;
         return JR_OK;
     }
+    // The queue counters need no initial value: every persistent launch is
+    // preceded by the kernel that zeroes them.
     Workspace* ws = new Workspace();
     hipError_t e = hipMalloc((void**)&ws->d_ctr, jr::kCounterBytes);
-    if (e == hipSuccess) e = hipMemset(ws->d_ctr, 0, jr::kCounterBytes);
     for (int k = 0; k < kStages && e == hipSuccess; ++k)
         e = hipEventCreateWithFlags(&ws->ev[k], hipEventDisableTiming);
-    if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         if (ws->d_ctr) (void)hipFree(ws->d_ctr);
         for (int k = 0; k < kStages; ++k)
@@ -367,17 +367,26 @@ int enqueue_batch(const jr_frame* frames, int32_t n, int32_t* out_base, int64_t 
     if ((rc = current_device(&dev, &info))) return rc;
     Table t;
     build_table(frames, n, s, t);
-    Workspace* ws;
-    if ((rc = get_workspace(dev, stream, &ws))) return rc;
-    std::lock_guard<std::mutex> g(ws->mu);
     const int blocks = grid_blocks(info, s, t.total_tiles);
-    if (n == 1) {
-        // one frame travels inside the kernel arguments: no table upload
-        jr::PersistentArgs args = make_args(t, nullptr, out_base, ws->d_ctr, n, blocks, s);
+    const bool queues = s.persistent && s.kernel != JR_KERNEL_PLAIN;
+    if (n == 1 && !queues) {
+        // One frame travels inside the kernel arguments and no workspace is
+        // touched: a single launch, which a hipGraph capture may record.
+        jr::PersistentArgs args = make_args(t, nullptr, out_base, nullptr, n, blocks, s);
         args.frame0 = t.rows[0];
         hipError_t e = s.kernel == JR_KERNEL_PLAIN
                            ? jr::launch_plain_batch(t.dtmask, args, stream)
                            : jr::launch_tiled(s.unroll, s.defer, t.dtmask, blocks, args, stream);
+        if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        return JR_OK;
+    }
+    Workspace* ws;
+    if ((rc = get_workspace(dev, stream, &ws))) return rc;
+    std::lock_guard<std::mutex> g(ws->mu);
+    if (n == 1) {
+        jr::PersistentArgs args = make_args(t, nullptr, out_base, ws->d_ctr, n, blocks, s);
+        args.frame0 = t.rows[0];
+        hipError_t e = jr::launch_tiled(s.unroll, s.defer, t.dtmask, blocks, args, stream);
         if (e != hipSuccess) return hip_fail(e, "kernel launch");
         return JR_OK;
     }
