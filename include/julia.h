@@ -177,6 +177,39 @@ int julia_render_batch(const jr_frame *frames, int32_t n, int32_t *out_base,
                        int64_t out_capacity, const jr_schedule *sched, void *stream);
 
 /*
+ * Fused count -> colour store (Section 2: every pixel is given a colour level
+ * by its iteration count).  The frames, schedules and kernels are those of
+ * julia_render_batch; only the stored value changes: each pixel stores the
+ * 32-bit table entry
+ *     palette[min(count, palette_len - 1)]
+ * in place of its count (for example an RGBA8 colour packed into 32 bits), so
+ * no count image is written and read back to colour it.
+ *   palette      device, palette_len uint32 entries, 4-byte aligned.  It is
+ *                read when the kernel runs, so it must stay valid and
+ *                unchanged until the stream has passed the launch.  Each
+ *                workgroup copies it into shared memory: a long table lowers
+ *                the number of resident workgroups.
+ *   palette_len  1 .. JR_PALETTE_MAX.
+ *   out_base     device arena as in julia_render_batch, one uint32 per pixel.
+ * Errors: JR_EINVAL for a null or misaligned palette, a length out of range,
+ * or what julia_render_batch rejects.  Capture rules are julia_render_batch's.
+ */
+#define JR_PALETTE_MAX 8192
+int julia_render_batch_colored(const jr_frame *frames, int32_t n, const uint32_t *palette,
+                               int32_t palette_len, uint32_t *out_base,
+                               int64_t out_capacity, const jr_schedule *sched,
+                               void *stream);
+
+/*
+ * One Julia image (Section 2) with the fused colour store: the image of
+ * julia_render, each pixel stored as palette[min(count, palette_len - 1)].
+ * out: device, width*height uint32, row-major.  Palette rules as above.
+ */
+int julia_render_colored(jr_complex c, jr_window w, int32_t width, int32_t height,
+                         int32_t max_iter, int32_t dtype, const uint32_t *palette,
+                         int32_t palette_len, uint32_t *out, void *stream);
+
+/*
  * Prepared batch: validates and uploads the frame table once (synchronously),
  * so that repeated launches or a captured hipGraph replay cost one kernel
  * launch.  A plan's launches must not overlap each other (they share the
@@ -189,6 +222,14 @@ int jr_plan_launch(jr_plan *plan, void *stream);
 /* Capture one launch into a hipGraph on `stream` (once), then replay it. */
 int jr_plan_capture(jr_plan *plan, void *stream);
 int jr_plan_replay(jr_plan *plan, void *stream);
+/*
+ * Make the plan's launches store colours from this table (see
+ * julia_render_batch_colored); palette NULL with palette_len 0 returns to
+ * counts.  A graph captured earlier is discarded: capture again before the
+ * next replay (replay returns JR_EINVAL until then).  The table must stay
+ * valid while launches that use it are in flight.
+ */
+int jr_plan_set_palette(jr_plan *plan, const uint32_t *palette, int32_t palette_len);
 /* Number of tiles of the plan and the grid it launches (for accounting). */
 int jr_plan_info(const jr_plan *plan, int64_t *tiles, int32_t *workgroups);
 void jr_plan_destroy(jr_plan *plan);

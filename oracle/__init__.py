@@ -62,6 +62,9 @@ def _open(path):
         getattr(lib, name).restype = None
     lib.jro_dw_split.argtypes = [d, p_f, p_f]
     lib.jro_dw_split.restype = None
+    p_u32 = ctypes.POINTER(ctypes.c_uint32)
+    lib.jro_colorize.argtypes = [p_i32, i64, p_u32, i32, p_u32]
+    lib.jro_colorize.restype = None
     return lib
 
 
@@ -97,6 +100,21 @@ def render_pixels(c, window, width, height, max_iter, ii, jj, dtype="fp64",
                           *[float(v) for v in window], int(width), int(height),
                           int(max_iter), ii.size, _as_ptr(ii), _as_ptr(jj),
                           _as_ptr(out))
+    return out
+
+
+def colorize(counts, palette):
+    """Colour levels of a count image: out[k] = palette[min(counts[k], len - 1)]
+    as a uint32 array of the counts' shape (Section 2: a pixel's colour level
+    follows from its iteration count)."""
+    lib = _load()
+    counts = np.ascontiguousarray(counts, dtype=np.int32)
+    palette = np.ascontiguousarray(palette, dtype=np.uint32)
+    assert palette.ndim == 1 and palette.size >= 1 and (counts >= 0).all()
+    out = np.empty(counts.shape, dtype=np.uint32)
+    u32 = ctypes.POINTER(ctypes.c_uint32)
+    lib.jro_colorize(_as_ptr(counts), counts.size, palette.ctypes.data_as(u32), palette.size,
+                     out.ctypes.data_as(u32))
     return out
 
 

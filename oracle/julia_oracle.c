@@ -263,6 +263,21 @@ static int32_t pixel_count(int32_t dtype, int32_t mode, double cr, double ci,
     return jro_count(dtype, x, y, cr, ci, max_iter);       /* Z_0 = pixel       */
 }
 
+/* ------------------------------------------------------------------------ */
+/* Colour levels (Section 2): count k takes entry k of the table; counts    */
+/* beyond its last entry take the last entry.                                */
+/* ------------------------------------------------------------------------ */
+void jro_colorize(const int32_t *counts, int64_t n, const uint32_t *palette,
+                  int32_t palette_len, uint32_t *out)
+{
+    for (int64_t k = 0; k < n; k++) {
+        int32_t level = counts[k];
+        if (level > palette_len - 1)
+            level = palette_len - 1;
+        out[k] = palette[level];
+    }
+}
+
 /* The sequential version of Section 2: one main loop over the pixel region. */
 void jro_render(int32_t dtype, int32_t mode, double cr, double ci,
                 double re_min, double re_max, double im_min, double im_max,

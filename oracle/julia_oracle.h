@@ -70,6 +70,12 @@ void jro_pixel_center(double re_min, double re_max, double im_min, double im_max
 int32_t jro_count(int32_t dtype, double x0, double y0, double cr, double ci,
                   int32_t max_iter);
 
+/* Colour levels from counts (Section 2: each pixel is given a colour level by
+ * its iteration count): out[k] = palette[min(counts[k], palette_len - 1)],
+ * for counts >= 0 and palette_len >= 1. */
+void jro_colorize(const int32_t *counts, int64_t n, const uint32_t *palette,
+                  int32_t palette_len, uint32_t *out);
+
 /* Float-float building blocks, exported so that their error-free and
  * error-bound properties can be checked against exact rational arithmetic. */
 void jro_two_sum(float a, float b, float *s, float *e);

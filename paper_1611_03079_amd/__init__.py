@@ -88,7 +88,8 @@ class Schedule:
 
 EXPORTS = (
     "julia_render", "julia_render_plain", "mandelbrot_render", "mandelbrot_render_plain",
-    "julia_render_batch", "jr_plan_create", "jr_plan_launch", "jr_plan_capture",
+    "julia_render_batch", "julia_render_batch_colored", "julia_render_colored",
+    "jr_plan_create", "jr_plan_set_palette", "jr_plan_launch", "jr_plan_capture",
     "jr_plan_replay", "jr_plan_info", "jr_plan_destroy", "jr_get_default_schedule",
     "jr_set_default_schedule", "jr_check_schedule", "jr_check_frames", "jr_strerror",
     "jr_last_error_message", "jr_device_info", "jr_shutdown",
@@ -124,6 +125,14 @@ def _load():
         getattr(lib, name).restype = ctypes.c_int
     lib.julia_render_batch.argtypes = [P(jr_frame), i32, vp, i64, P(jr_schedule), vp]
     lib.julia_render_batch.restype = ctypes.c_int
+    lib.julia_render_batch_colored.argtypes = [P(jr_frame), i32, vp, i32, vp, i64,
+                                               P(jr_schedule), vp]
+    lib.julia_render_batch_colored.restype = ctypes.c_int
+    lib.julia_render_colored.argtypes = [jr_complex, jr_window, i32, i32, i32, i32, vp, i32,
+                                         vp, vp]
+    lib.julia_render_colored.restype = ctypes.c_int
+    lib.jr_plan_set_palette.argtypes = [vp, vp, i32]
+    lib.jr_plan_set_palette.restype = ctypes.c_int
     lib.jr_plan_create.argtypes = [P(jr_frame), i32, vp, i64, P(jr_schedule), P(vp)]
     lib.jr_plan_create.restype = ctypes.c_int
     for name in ("jr_plan_launch", "jr_plan_capture", "jr_plan_replay"):
@@ -186,6 +195,21 @@ def _out_tensor(out, shape):
     return out
 
 
+PALETTE_MAX = 8192  # JR_PALETTE_MAX
+
+
+def _palette_ptr(palette):
+    """(pointer, length) of a colour table: a 1-D contiguous int32 or uint32
+    CUDA tensor of 1..PALETTE_MAX entries."""
+    import torch
+    if palette.dim() != 1 or not palette.is_cuda or not palette.is_contiguous() or \
+            palette.dtype not in (torch.int32, torch.uint32):
+        raise ValueError("palette must be a 1-D contiguous int32/uint32 CUDA tensor")
+    if not 1 <= palette.numel() <= PALETTE_MAX:
+        raise ValueError("palette holds %d entries, allowed 1..%d" % (palette.numel(), PALETTE_MAX))
+    return ctypes.c_void_p(palette.data_ptr()), palette.numel()
+
+
 _TUNED = None
 
 
@@ -207,16 +231,38 @@ def tuned_schedule(dtype: str, max_iter: int, pixels: int) -> Optional["Schedule
 
 def render(c, window, width: int, height: int, max_iter: int, dtype: str = "fp64",
            out=None, stream=None, mode: str = "julia", plain: bool = False,
-           schedule: Optional["Schedule"] = None):
+           schedule: Optional["Schedule"] = None, palette=None):
     """Counts of one image as an int32 (height, width) CUDA tensor (row 0 = im_max).
 
     ``plain=True`` uses the one-thread-per-pixel comparator kernel.  Otherwise
     the schedule is ``schedule``, else the autotuner's choice for the image's
     bucket, else the library default (julia_render / mandelbrot_render).
+
+    With ``palette`` (see _palette_ptr) each pixel holds the 32 bits of
+    palette[min(count, len - 1)] instead of its count, stored by the kernel
+    itself (julia_render_batch_colored).
     """
     out = _out_tensor(out, (height, width))
     st = _stream_ptr(stream)
     dt = DTYPES[dtype]
+    if palette is not None:
+        pp, plen = _palette_ptr(palette)
+        if plain:
+            schedule = Schedule(kernel="plain")
+        elif schedule is None:
+            schedule = tuned_schedule(dtype, max_iter, width * height)
+        if schedule is None and mode == "julia":
+            c = complex(c)
+            _check(lib.julia_render_colored(jr_complex(c.real, c.imag), _window(window), width,
+                                            height, max_iter, dt, pp, plen,
+                                            ctypes.c_void_p(out.data_ptr()), st))
+        else:
+            arr = _frames_array([_OneFrame(c, window, width, height, max_iter, dtype, mode)], [0])
+            sched = ctypes.byref(schedule.to_c()) if schedule is not None else None
+            _check(lib.julia_render_batch_colored(arr, 1, pp, plen,
+                                                  ctypes.c_void_p(out.data_ptr()),
+                                                  width * height, sched, st))
+        return out.view(-1)[: width * height].view(height, width)
     if not plain:
         if schedule is None:
             schedule = tuned_schedule(dtype, max_iter, width * height)
@@ -272,10 +318,11 @@ def arena_layout(frames) -> Tuple[list, int]:
 
 
 def render_batch(frames: Sequence, schedule: Optional[Schedule] = None, arena=None,
-                 offsets=None, stream=None, rows=None):
+                 offsets=None, stream=None, rows=None, palette=None):
     """Render frames (objects with c, window, width, height, max_iter, dtype, mode)
     in one persistent launch.  Returns (arena, views): views[k] is frame k's
-    (height, width) counts inside the int32 arena."""
+    (height, width) counts inside the int32 arena, or with ``palette`` its
+    colours (julia_render_batch_colored)."""
     import torch
     if offsets is None:
         offsets, total = arena_layout(frames)
@@ -285,8 +332,14 @@ def render_batch(frames: Sequence, schedule: Optional[Schedule] = None, arena=No
         arena = torch.empty(total, dtype=torch.int32, device="cuda")
     arr = _frames_array(frames, offsets, rows)
     sched = ctypes.byref(schedule.to_c()) if schedule is not None else None
-    rc = lib.julia_render_batch(arr, len(frames), ctypes.c_void_p(arena.data_ptr()),
-                                arena.numel(), sched, _stream_ptr(stream))
+    if palette is not None:
+        pp, plen = _palette_ptr(palette)
+        rc = lib.julia_render_batch_colored(arr, len(frames), pp, plen,
+                                            ctypes.c_void_p(arena.data_ptr()), arena.numel(),
+                                            sched, _stream_ptr(stream))
+    else:
+        rc = lib.julia_render_batch(arr, len(frames), ctypes.c_void_p(arena.data_ptr()),
+                                    arena.numel(), sched, _stream_ptr(stream))
     _check(rc)
     views = [arena[o: o + f.width * f.height].view(f.height, f.width)
              for o, f in zip(offsets, frames)]
@@ -325,6 +378,16 @@ class Plan:
 
     def replay(self, stream=None):
         _check(lib.jr_plan_replay(self._h, _stream_ptr(stream)))
+
+    def set_palette(self, palette=None):
+        """Store colours from ``palette`` (None: counts) in later launches; a
+        captured graph is dropped and must be captured again."""
+        if palette is None:
+            _check(lib.jr_plan_set_palette(self._h, None, 0))
+        else:
+            pp, plen = _palette_ptr(palette)
+            _check(lib.jr_plan_set_palette(self._h, pp, plen))
+        self.palette = palette  # keep the table alive while the plan may use it
 
     def info(self):
         t, w = ctypes.c_int64(), ctypes.c_int32()

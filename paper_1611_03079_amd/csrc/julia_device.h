@@ -51,7 +51,12 @@ struct PersistentArgs {
     int32_t persistent;  // 1: work queues; 0: one wave per tile
     int32_t hybrid;      // 1: fresh packets + survivor queue (run_hybrid)
     int32_t bail;        // hybrid: iterations of a fresh packet before its survivors park
+    int32_t palette_len; // > 0: a pixel stores palette[min(count, palette_len - 1)]
+    const uint32_t* palette;
 };
+
+// Largest colour table of the fused colour store; it is staged in LDS.
+constexpr int kPaletteMax = 8192;
 
 struct PlainArgs {
     int32_t* out;

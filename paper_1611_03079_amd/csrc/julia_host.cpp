@@ -29,6 +29,8 @@ namespace {
 
 thread_local std::string g_last_msg;
 
+static_assert(jr::kPaletteMax == JR_PALETTE_MAX, "one palette limit");
+
 int fail(int code, const char* fmt, ...) {
     char buf[512];
     va_list ap;
@@ -347,8 +349,19 @@ int grid_blocks(const DeviceInfo& info, const jr_schedule& s, int64_t total_tile
     return (int)blocks;
 }
 
+int check_palette(const uint32_t* palette, int32_t len, bool required, const char* who) {
+    if (!required && palette == nullptr && len == 0) return JR_OK;
+    if (palette == nullptr) return fail(JR_EINVAL, "%s: palette is null", who);
+    if (reinterpret_cast<uintptr_t>(palette) % 4 != 0)
+        return fail(JR_EINVAL, "%s: palette is not 4-byte aligned", who);
+    if (len < 1 || len > JR_PALETTE_MAX)
+        return fail(JR_EINVAL, "%s: palette_len %d outside 1..%d", who, len, JR_PALETTE_MAX);
+    return JR_OK;
+}
+
 int enqueue_batch(const jr_frame* frames, int32_t n, int32_t* out_base, int64_t capacity,
-                  const jr_schedule* sched, hipStream_t stream) {
+                  const jr_schedule* sched, hipStream_t stream, const uint32_t* palette = nullptr,
+                  int32_t palette_len = 0) {
     int rc = check_frames(frames, n, capacity);
     if (rc) return rc;
     if ((rc = check_out(out_base, "batch"))) return rc;
@@ -374,6 +387,8 @@ int enqueue_batch(const jr_frame* frames, int32_t n, int32_t* out_base, int64_t 
         // touched: a single launch, which a hipGraph capture may record.
         jr::PersistentArgs args = make_args(t, nullptr, out_base, nullptr, n, blocks, s);
         args.frame0 = t.rows[0];
+        args.palette = palette;
+        args.palette_len = palette_len;
         hipError_t e = s.kernel == JR_KERNEL_PLAIN
                            ? jr::launch_plain_batch(t.dtmask, args, stream)
                            : jr::launch_tiled(s.unroll, s.defer, t.dtmask, blocks, args, stream);
@@ -386,6 +401,8 @@ int enqueue_batch(const jr_frame* frames, int32_t n, int32_t* out_base, int64_t 
     if (n == 1) {
         jr::PersistentArgs args = make_args(t, nullptr, out_base, ws->d_ctr, n, blocks, s);
         args.frame0 = t.rows[0];
+        args.palette = palette;
+        args.palette_len = palette_len;
         hipError_t e = jr::launch_tiled(s.unroll, s.defer, t.dtmask, blocks, args, stream);
         if (e != hipSuccess) return hip_fail(e, "kernel launch");
         return JR_OK;
@@ -424,7 +441,9 @@ int enqueue_batch(const jr_frame* frames, int32_t n, int32_t* out_base, int64_t 
             "hipMemcpyAsync frame table");
     HIP_TRY(hipEventRecord(ws->ev[k], stream), "hipEventRecord");
     ws->ev_used[k] = true;
-    const jr::PersistentArgs args = make_args(t, ws->d_table, out_base, ws->d_ctr, n, blocks, s);
+    jr::PersistentArgs args = make_args(t, ws->d_table, out_base, ws->d_ctr, n, blocks, s);
+    args.palette = palette;
+    args.palette_len = palette_len;
     hipError_t e = s.kernel == JR_KERNEL_PLAIN
                        ? jr::launch_plain_batch(t.dtmask, args, stream)
                        : jr::launch_tiled(s.unroll, s.defer, t.dtmask, blocks, args, stream);
@@ -454,6 +473,20 @@ int render_one(jr_complex c, jr_window w, int32_t W, int32_t H, int32_t max_iter
     jr_frame f = single_frame(c, w, W, H, max_iter, dtype, mode);
     jr_schedule s = default_schedule(dtype);
     return enqueue_batch(&f, 1, out, (int64_t)W * H, &s, (hipStream_t)stream);
+}
+
+int render_one_colored(jr_complex c, jr_window w, int32_t W, int32_t H, int32_t max_iter,
+                       int32_t dtype, const uint32_t* palette, int32_t palette_len,
+                       uint32_t* out, void* stream) {
+    const char* who = "julia_render_colored";
+    int rc = check_image(W, H, max_iter, dtype, JR_JULIA, c, w, who);
+    if (rc) return rc;
+    if ((rc = check_out(out, who))) return rc;
+    if ((rc = check_palette(palette, palette_len, true, who))) return rc;
+    jr_frame f = single_frame(c, w, W, H, max_iter, dtype, JR_JULIA);
+    jr_schedule s = default_schedule(dtype);
+    return enqueue_batch(&f, 1, reinterpret_cast<int32_t*>(out), (int64_t)W * H, &s,
+                         (hipStream_t)stream, palette, palette_len);
 }
 
 int render_plain(jr_complex c, jr_window w, int32_t W, int32_t H, int32_t max_iter,
@@ -567,6 +600,22 @@ int julia_render_batch(const jr_frame* frames, int32_t n, int32_t* out_base,
     return enqueue_batch(frames, n, out_base, out_capacity, sched, (hipStream_t)stream);
 }
 
+int julia_render_batch_colored(const jr_frame* frames, int32_t n, const uint32_t* palette,
+                               int32_t palette_len, uint32_t* out_base, int64_t out_capacity,
+                               const jr_schedule* sched, void* stream) {
+    int rc = check_palette(palette, palette_len, true, "julia_render_batch_colored");
+    if (rc) return rc;
+    return enqueue_batch(frames, n, reinterpret_cast<int32_t*>(out_base), out_capacity, sched,
+                         (hipStream_t)stream, palette, palette_len);
+}
+
+int julia_render_colored(jr_complex c, jr_window w, int32_t width, int32_t height,
+                         int32_t max_iter, int32_t dtype, const uint32_t* palette,
+                         int32_t palette_len, uint32_t* out, void* stream) {
+    return render_one_colored(c, w, width, height, max_iter, dtype, palette, palette_len, out,
+                              stream);
+}
+
 int jr_plan_create(const jr_frame* frames, int32_t n, int32_t* out_base, int64_t out_capacity,
                    const jr_schedule* sched, jr_plan** plan) {
     if (!plan) return fail(JR_EINVAL, "plan is null");
@@ -655,6 +704,24 @@ int jr_plan_replay(jr_plan* p, void* stream) {
     if (!p) return fail(JR_EINVAL, "plan is null");
     if (!p->exec) return fail(JR_EINVAL, "plan has no captured graph; call jr_plan_capture");
     HIP_TRY(hipGraphLaunch(p->exec, (hipStream_t)stream), "hipGraphLaunch");
+    return JR_OK;
+}
+
+int jr_plan_set_palette(jr_plan* p, const uint32_t* palette, int32_t palette_len) {
+    if (!p) return fail(JR_EINVAL, "plan is null");
+    int rc = check_palette(palette, palette_len, false, "jr_plan_set_palette");
+    if (rc) return rc;
+    if (p->exec) {
+        // The captured launch carries the old table in its arguments.
+        HIP_TRY(hipGraphExecDestroy(p->exec), "hipGraphExecDestroy");
+        p->exec = nullptr;
+    }
+    if (p->graph) {
+        HIP_TRY(hipGraphDestroy(p->graph), "hipGraphDestroy");
+        p->graph = nullptr;
+    }
+    p->args.palette = palette;
+    p->args.palette_len = palette_len;
     return JR_OK;
 }
 

@@ -210,6 +210,30 @@ __device__ __forceinline__ double pixel_im(double cy, double hy, int j, int H) {
 }
 
 // ---------------------------------------------------------------------------
+// Fused colour store: the workgroup copies the colour table into LDS once, and
+// a pixel then stores palette[min(count, palette_len - 1)] in place of its
+// count.  palette_len is a kernel argument, the same for the whole grid, so
+// every thread of a workgroup reaches the barrier or none does.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t* palette_lds() {
+    extern __shared__ uint32_t jr_dynamic_lds[];
+    return jr_dynamic_lds;
+}
+
+__device__ __forceinline__ void stage_palette(const PersistentArgs& a) {
+    if (a.palette_len <= 0) return;
+    uint32_t* pal = palette_lds();
+    for (int k = threadIdx.x; k < a.palette_len; k += blockDim.x) pal[k] = a.palette[k];
+    __syncthreads();
+}
+
+// The 32 bits a pixel stores: its count, or its colour.
+__device__ __forceinline__ int32_t shade(const PersistentArgs& a, int cnt) {
+    if (a.palette_len <= 0) return cnt;
+    return (int32_t)palette_lds()[min(cnt, a.palette_len - 1)];
+}
+
+// ---------------------------------------------------------------------------
 // Plain kernel: one thread per pixel, 16x16 workgroups, test every iteration.
 // ---------------------------------------------------------------------------
 template <class A>
@@ -465,7 +489,7 @@ __device__ void run_stream(Src& s, Claimer& cl, const PersistentArgs& a, double&
                 }
             }
             if (fi) {
-                *outp = cnt;
+                *outp = shade(a, cnt);
                 fi = false;
             }
             uint64_t idle = ~running;
@@ -644,7 +668,7 @@ __device__ void run_hybrid(Src& s, Claimer& cl, const PersistentArgs& a, double&
                 if (__ballot(it) == 0) break;
             }
             if (fi) {
-                *outp = cnt;
+                *outp = shade(a, cnt);
                 fi = false;
             }
             const uint64_t surv = __ballot(it);
@@ -676,7 +700,7 @@ __device__ void run_hybrid(Src& s, Claimer& cl, const PersistentArgs& a, double&
                     }
                 }
                 if (fi) {
-                    *outp = cnt;
+                    *outp = shade(a, cnt);
                     fi = false;
                 }
                 const uint64_t idle = ~__ballot(it);
@@ -745,6 +769,7 @@ __global__ __launch_bounds__(256) void jr_tiled(PersistentArgs a) {
     // per-wave survivor queues of the hybrid stream (unused otherwise)
     __shared__ uint32_t qmem[HYB ? 4 * kQWordsMax * kQ : 1];
     uint32_t* q = qmem + (HYB ? (threadIdx.x >> 6) * kQWordsMax * kQ : 0);
+    stage_palette(a);
     Claimer cl;
     claimer_init(cl, a);
     Src s;
@@ -783,7 +808,8 @@ __global__ __launch_bounds__(256) void jr_tiled(PersistentArgs a) {
 // per-iteration test like jr_plain.  The batched form of the comparator,
 // and a candidate of the autotuner for images whose counts are low and even.
 template <class A>
-__device__ __forceinline__ void plain_pixel(CFrame& F, int i, int j, int32_t* out) {
+__device__ __forceinline__ void plain_pixel(const PersistentArgs& a, CFrame& F, int i, int j,
+                                            int32_t* out) {
     const double px = pixel_re(F.cx, F.hx, i, F.width);
     const double py = pixel_im(F.cy, F.hy, j, F.height);
     typename A::Z z;
@@ -800,11 +826,12 @@ __device__ __forceinline__ void plain_pixel(CFrame& F, int i, int j, int32_t* ou
         if (!A::check_step(z, c)) break;
         n++;
     }
-    out[(int64_t)j * F.width + i] = n;
+    out[(int64_t)j * F.width + i] = shade(a, n);
 }
 
 template <int DTMASK>
 __global__ __launch_bounds__(256) void jr_plain_batch(PersistentArgs a) {
+    stage_palette(a);
     CFrame* frames = cframes(a);
     const int64_t t = blockIdx.x;
     int f = 0;
@@ -823,11 +850,11 @@ __global__ __launch_bounds__(256) void jr_plain_batch(PersistentArgs a) {
     if (i >= F.width || j >= F.row_end) return;
     int32_t* out = a.out_base + F.out_offset;
     if ((DTMASK & (1 << kFP32)) && F.dtype == kFP32)
-        plain_pixel<ArF32>(F, i, j, out);
+        plain_pixel<ArF32>(a, F, i, j, out);
     else if ((DTMASK & (1 << kFP64)) && F.dtype == kFP64)
-        plain_pixel<ArF64>(F, i, j, out);
+        plain_pixel<ArF64>(a, F, i, j, out);
     else if ((DTMASK & (1 << kFF)) && F.dtype == kFF)
-        plain_pixel<ArFF>(F, i, j, out);
+        plain_pixel<ArFF>(a, F, i, j, out);
 }
 
 // Zeroes the kQueues counters before a persistent launch (a kernel, not a
@@ -887,23 +914,28 @@ static TiledFn pick_plain(int dtmask) {
     }
 }
 
+static unsigned palette_bytes(const PersistentArgs& a) {
+    return a.palette_len > 0 ? (unsigned)a.palette_len * 4u : 0u;
+}
+
 hipError_t launch_plain_batch(int dtmask, const PersistentArgs& args, hipStream_t stream) {
+    if (args.palette_len > kPaletteMax) return hipErrorInvalidValue;
     if (args.total_tiles > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(pick_plain(dtmask), dim3((unsigned)args.total_tiles), dim3(256), 0, stream,
-                       args);
+    hipLaunchKernelGGL(pick_plain(dtmask), dim3((unsigned)args.total_tiles), dim3(256),
+                       palette_bytes(args), stream, args);
     return hipGetLastError();
 }
 
 hipError_t launch_tiled(int unroll, int defer, int dtmask, int blocks, const PersistentArgs& args,
                         hipStream_t stream) {
     TiledFn fn = pick(unroll, defer, dtmask, args.hybrid);
-    if (!fn) return hipErrorInvalidValue;
+    if (!fn || args.palette_len > kPaletteMax) return hipErrorInvalidValue;
     if (args.persistent) {
         hipLaunchKernelGGL(jr_reset_queues, dim3(1), dim3(kQueues), 0, stream, args.ctr);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), 0, stream, args);
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), palette_bytes(args), stream, args);
     return hipGetLastError();
 }
 

@@ -157,3 +157,32 @@ def test_valid_call_without_gpu_reports_no_device():
     rc = _render()
     assert rc in (jr.JR_ENODEV, jr.JR_ELAUNCH), rc
     assert jr.last_error()
+
+
+FAKE_PAL = ctypes.c_void_p(0x20000)  # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("pal,plen", [
+    (ctypes.c_void_p(0), 16), (ctypes.c_void_p(0x20002), 16), (FAKE_PAL, 0), (FAKE_PAL, -1),
+    (FAKE_PAL, 8193),
+])
+def test_colored_entry_points_reject_bad_palettes(pal, plen):
+    fr = _frames()
+    arr = jr._frames_array(fr, [0, 64 * 48])
+    rc = jr.lib.julia_render_batch_colored(arr, 2, pal, plen, FAKE_OUT, 1 << 20, None, None)
+    assert rc == jr.JR_EINVAL
+    assert "palette" in jr.last_error()
+    rc = jr.lib.julia_render_colored(jr.jr_complex(-0.8, 0.156), jr.jr_window(-1.5, 1.5, -1.5, 1.5),
+                                     64, 32, 100, 0, pal, plen, FAKE_OUT, None)
+    assert rc == jr.JR_EINVAL
+
+
+def test_colored_batch_validates_frames_and_plan_palette():
+    fr = _frames()
+    arr = jr._frames_array(fr, [0, 64 * 48])
+    # a valid palette does not hide a bad arena
+    assert jr.lib.julia_render_batch_colored(arr, 2, FAKE_PAL, 8192, FAKE_OUT, 10, None,
+                                             None) == jr.JR_EINVAL
+    assert jr.lib.jr_plan_set_palette(None, FAKE_PAL, 4) == jr.JR_EINVAL
+    assert jr.PALETTE_MAX == 8192
+    assert "#define JR_PALETTE_MAX 8192" in open(HEADER).read()

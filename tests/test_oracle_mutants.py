@@ -37,6 +37,9 @@ MUTANTS = {
     "ff_lost_cross": ("float cross = fmaf(x.lo, y.hi, cross1);", "float cross = cross1;"),
     "ff_lost_tl": ("float w = tl + vl;", "float w = vl;"),
     "ff_escape_lo": ("(m.hi == 4.0f && m.lo <= 0.0f)", "(m.hi == 4.0f)"),
+    "colour_level_shift": ("out[k] = palette[level];",
+                           "out[k] = palette[level > 0 ? level - 1 : 0];"),
+    "colour_clamp_to_first": ("            level = palette_len - 1;", "            level = 0;"),
     "mandel_z0_is_c": ("return jro_count(dtype, 0.0, 0.0, x, y, max_iter);",
                        "return jro_count(dtype, x, y, x, y, max_iter);"),
 }
@@ -54,6 +57,7 @@ def _battery():
                ("fp32_formulation", pins.test_fp32_escape_test_formulation, ()),
                ("cap01_fp64", pins.test_cap_zero_and_one, ("fp64",)),
                ("eft", pins.test_error_free_transforms, ()),
+               ("colour_table", pins.test_colorize_literal_table, ()),
                ("dw_bounds", pins.test_double_word_error_bounds, ())]
     for name, fn, args in checks:
         try:

@@ -435,3 +435,54 @@ def test_mismatch_fraction_unit_window(dtype, bound):
     got = oracle.render(C1, UNIT, W, H, 100, dtype)
     frac = float((ref != got).mean())
     assert frac <= bound, frac
+
+
+# ------------------------------------------------ colour levels (Section 2)
+def test_colorize_literal_table():
+    """Count k takes entry k of the table; counts past its end take the last
+    entry; a one-entry table paints everything."""
+    counts = np.array([[0, 1, 2], [3, 4, 100]], dtype=np.int32)
+    pal = np.array([0xFF000000, 0xFF0000FF, 0xFF00FF00, 0xFFFF0000], dtype=np.uint32)
+    want = np.array([[0xFF000000, 0xFF0000FF, 0xFF00FF00],
+                     [0xFFFF0000, 0xFFFF0000, 0xFFFF0000]], dtype=np.uint32)
+    got = oracle.colorize(counts, pal)
+    assert got.dtype == np.uint32 and got.shape == counts.shape
+    np.testing.assert_array_equal(got, want)
+    one = oracle.colorize(counts, np.array([0xDEADBEEF], dtype=np.uint32))
+    assert (one == 0xDEADBEEF).all()
+
+
+def test_colorize_identity_table_gives_the_counts():
+    """Entry k = k over 0..cap returns the count image itself."""
+    a = oracle.render(complex(-0.8, 0.156), (-1.5, 1.5, -1.5, 1.5), 96, 80, 100)
+    got = oracle.colorize(a, np.arange(101, dtype=np.uint32))
+    np.testing.assert_array_equal(got.astype(np.int64), a.astype(np.int64))
+
+
+def test_colorize_two_levels_mark_the_bounded_set():
+    """A table that is 0 below the cap and all ones at the cap marks the
+    bounded pixels.  For C = 0 they are exactly the closed unit disc; a
+    Mandelbrot window inside the main cardioid is bounded everywhere."""
+    cap = 60
+    pal = np.zeros(cap + 1, dtype=np.uint32)
+    pal[cap] = 0xFFFFFFFF
+    W = H = 64
+    win = (-1.7, 1.7, -1.7, 1.7)
+    img = oracle.colorize(oracle.render(0j, win, W, H, cap), pal)
+    checked = 0
+    for j in range(H):
+        for i in range(W):
+            r = abs(complex(*oracle.pixel_center(win, W, H, i, j)))
+            if abs(r - 1.0) < 1e-3:
+                continue
+            assert (img[j, i] == 0xFFFFFFFF) == (r <= 1.0), (i, j, r)
+            checked += 1
+    assert checked > 0.95 * W * H
+    mwin = (-0.3, 0.15, -0.25, 0.25)
+    for j in range(0, 33, 4):
+        for i in range(0, 41, 4):
+            c = complex(*oracle.pixel_center(mwin, 41, 33, i, j))
+            mu = 1.0 - np.sqrt(1.0 - 4.0 * c + 0j)  # c = mu/2 - mu^2/4
+            assert abs(mu) < 0.95
+    m = oracle.colorize(oracle.render(0j, mwin, 41, 33, cap, "fp64", "mandelbrot"), pal)
+    assert (m == 0xFFFFFFFF).all()
