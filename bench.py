@@ -17,7 +17,8 @@ launch on the stream it runs on), the single-threaded CPU oracle on a bounded
 sample of the same workload, and further legs in "extra": the plain
 one-thread-per-pixel kernel on the same frames, the persistent-queue mode, the
 single 4096x4096 images in FP32 and FP64, the 512x512 FP64 image's latency,
-an uneven batch (FP32 + float-float, one launch), the serving loop's p50/p99
+an uneven batch (FP32 + float-float, one launch), the same batch with the
+fused colour store, the serving loop's p50/p99
 latency under Poisson arrivals, and the FP32 / float-float pixel fractions that
 differ from FP64.
 """
@@ -153,6 +154,18 @@ def extra_legs(args, torch, jr, wl, frames, sched, ms_headline, iters):
     plan.close()
     ex["parameter_path_persistent_queues"] = {"ms_per_step": round(ms_p, 4),
                                               "gpixel_iter_s": round(iters / (ms_p * 1e-3) / 1e9, 2)}
+    # fused colour store: the same batch storing colours from a 101-entry table
+    import numpy as np
+    pal = torch.from_numpy(np.random.default_rng(0).integers(
+        0, 2 ** 31, size=101, dtype=np.int64).astype(np.int32)).cuda()
+    plan = jr.Plan(frames, sched)
+    plan.set_palette(pal)
+    plan.capture()
+    ms_c, kms_c = time_plan_steps(torch, plan, 10, 2, graph=True)
+    plan.close()
+    ex["parameter_path_colour_store"] = {
+        "ms_per_step": round(ms_c, 4), "kernel_ms": round(kms_c, 4),
+        "palette_entries": 101, "counts_over_colours_time": round(ms_headline / ms_c, 3)}
     # single 4096x4096 images, FP32 and FP64, tuned vs plain
     for dt in ("fp32", "fp64"):
         fr = [wl.single_4096(s, it, dt) for it in (100, 1000) for s in range(4)]
