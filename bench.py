@@ -17,9 +17,9 @@ launch on the stream it runs on), the single-threaded CPU oracle on a bounded
 sample of the same workload, and further legs in "extra": the plain
 one-thread-per-pixel kernel on the same frames, the persistent-queue mode, the
 single 4096x4096 images in FP32 and FP64, the 512x512 FP64 image's latency,
-an uneven batch (FP32 + float-float, one launch), the same batch with the
-fused colour store, the serving loop's p50/p99
-latency under Poisson arrivals, and the FP32 / float-float pixel fractions that
+an uneven batch (FP32 + float-float, one launch), the headline batch with
+the fused colour store, the serving loop's p50/p99 latency under Poisson
+arrivals, and the FP32 / float-float pixel fractions that
 differ from FP64.
 """
 import argparse
