@@ -109,11 +109,14 @@ def count_sum(torch, views):
 
 
 def cpu_baseline(frames, seconds):
-    """The oracle, single-threaded, on whole rows: every 2nd row of every 2nd
-    frame, rows interleaved over the frames, until `seconds` of CPU work."""
+    """The oracle, single-threaded, on whole rows taken in a fixed interleaved
+    order (row j of every frame, rows stepping by 7 through the image), until
+    `seconds` of CPU work."""
     import numpy as np
     import oracle
-    picks = [(fi, j) for j in range(0, frames[0].height, 2) for fi in range(0, len(frames), 2)]
+    H = frames[0].height
+    rows = [(3 + 7 * m) % H for m in range(H)]  # 7 and 1080 are coprime: every row once
+    picks = [(fi, j) for j in rows for fi in range(len(frames))]
     iters = px = 0
     spent = 0.0
     done = 0
@@ -129,9 +132,9 @@ def cpu_baseline(frames, seconds):
         iters += int(c.sum(dtype=np.int64))
         px += f.width
         done += 1
-    sample = ("%d whole 1920-pixel rows taken row-major over every 2nd row of every 2nd "
-              "frame (%d pixels), oracle FP32 formulation, %.1f s single-threaded"
-              % (done, px, spent))
+    sample = ("%d whole 1920-pixel rows (%d pixels): rows j = 3, 10, 17, ... (step 7 mod "
+              "1080) of all 256 frames in turn, oracle FP32 formulation, %.1f s "
+              "single-threaded" % (done, px, spent))
     return iters / spent, sample
 
 
