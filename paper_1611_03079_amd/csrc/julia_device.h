@@ -57,6 +57,9 @@ struct PersistentArgs {
 
 // Largest colour table of the fused colour store; it is staged in LDS.
 constexpr int kPaletteMax = 8192;
+// Kernel variants that store colours carry this bit beside the dtype bits
+// (compile-time, so the counting kernels hold no colour code).
+constexpr int kColorBit = 8;
 
 struct PlainArgs {
     int32_t* out;

@@ -212,24 +212,27 @@ __device__ __forceinline__ double pixel_im(double cy, double hy, int j, int H) {
 // ---------------------------------------------------------------------------
 // Fused colour store: the workgroup copies the colour table into LDS once, and
 // a pixel then stores palette[min(count, palette_len - 1)] in place of its
-// count.  palette_len is a kernel argument, the same for the whole grid, so
-// every thread of a workgroup reaches the barrier or none does.
+// count.  Only the kernel variants built with COLOR = 1 (launched when a table
+// is given) hold this code; every thread of their workgroups reaches the
+// barrier.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t* palette_lds() {
     extern __shared__ uint32_t jr_dynamic_lds[];
     return jr_dynamic_lds;
 }
 
+template <int COLOR>
 __device__ __forceinline__ void stage_palette(const PersistentArgs& a) {
-    if (a.palette_len <= 0) return;
+    if (!COLOR) return;
     uint32_t* pal = palette_lds();
     for (int k = threadIdx.x; k < a.palette_len; k += blockDim.x) pal[k] = a.palette[k];
     __syncthreads();
 }
 
-// The 32 bits a pixel stores: its count, or its colour.
+// The 32 bits a pixel stores: its count, or (COLOR) its colour.
+template <int COLOR>
 __device__ __forceinline__ int32_t shade(const PersistentArgs& a, int cnt) {
-    if (a.palette_len <= 0) return cnt;
+    if (!COLOR) return cnt;
     return (int32_t)palette_lds()[min(cnt, a.palette_len - 1)];
 }
 
@@ -455,7 +458,7 @@ __device__ __forceinline__ void load_src(Src& s, const PersistentArgs& a, int64_
 // the next pixels of the tile, and of the following tiles when it runs out.
 // Returns when the next tile needs another variant (left in s, its coordinate
 // tables in xd, yd and its constant in crd, cid) or none is left.
-template <class A, int K, int DEFER>
+template <class A, int K, int DEFER, int COLOR>
 __device__ void run_stream(Src& s, Claimer& cl, const PersistentArgs& a, double& xd, double& yd,
                            double& crd, double& cid) {
     using V = typename A::V;
@@ -489,7 +492,7 @@ __device__ void run_stream(Src& s, Claimer& cl, const PersistentArgs& a, double&
                 }
             }
             if (fi) {
-                *outp = shade(a, cnt);
+                *outp = shade<COLOR>(a, cnt);
                 fi = false;
             }
             uint64_t idle = ~running;
@@ -601,7 +604,7 @@ __device__ __forceinline__ Parked<A> unpark(const uint32_t* q, int slot) {
     return p;
 }
 
-template <class A, int K, int DEFER>
+template <class A, int K, int DEFER, int COLOR>
 __device__ void run_hybrid(Src& s, Claimer& cl, const PersistentArgs& a, double& xd, double& yd,
                            double& crd, double& cid, uint32_t* q) {
     using V = typename A::V;
@@ -668,7 +671,7 @@ __device__ void run_hybrid(Src& s, Claimer& cl, const PersistentArgs& a, double&
                 if (__ballot(it) == 0) break;
             }
             if (fi) {
-                *outp = shade(a, cnt);
+                *outp = shade<COLOR>(a, cnt);
                 fi = false;
             }
             const uint64_t surv = __ballot(it);
@@ -700,7 +703,7 @@ __device__ void run_hybrid(Src& s, Claimer& cl, const PersistentArgs& a, double&
                     }
                 }
                 if (fi) {
-                    *outp = shade(a, cnt);
+                    *outp = shade<COLOR>(a, cnt);
                     fi = false;
                 }
                 const uint64_t idle = ~__ballot(it);
@@ -766,10 +769,11 @@ __device__ void run_hybrid(Src& s, Claimer& cl, const PersistentArgs& a, double&
 // and hands them to the stream of the variant they need.
 template <int K, int DEFER, int DTMASK, int HYB>
 __global__ __launch_bounds__(256) void jr_tiled(PersistentArgs a) {
+    constexpr int COLOR = (DTMASK & kColorBit) ? 1 : 0;
     // per-wave survivor queues of the hybrid stream (unused otherwise)
     __shared__ uint32_t qmem[HYB ? 4 * kQWordsMax * kQ : 1];
     uint32_t* q = qmem + (HYB ? (threadIdx.x >> 6) * kQWordsMax * kQ : 0);
-    stage_palette(a);
+    stage_palette<COLOR>(a);
     Claimer cl;
     claimer_init(cl, a);
     Src s;
@@ -779,9 +783,9 @@ __global__ __launch_bounds__(256) void jr_tiled(PersistentArgs a) {
 #define JR_STREAM(A_, K_, D_)                                         \
     do {                                                              \
         if (HYB)                                                      \
-            run_hybrid<A_, K_, D_>(s, cl, a, xd, yd, cr, ci, q);      \
+            run_hybrid<A_, K_, D_, COLOR>(s, cl, a, xd, yd, cr, ci, q); \
         else                                                          \
-            run_stream<A_, K_, D_>(s, cl, a, xd, yd, cr, ci);         \
+            run_stream<A_, K_, D_, COLOR>(s, cl, a, xd, yd, cr, ci); \
     } while (0)
     while (s.t >= 0) {
         const int v = s.variant;
@@ -807,7 +811,7 @@ __global__ __launch_bounds__(256) void jr_tiled(PersistentArgs a) {
 // (16 x 16 pixels) of the frame that holds it, and every thread runs the
 // per-iteration test like jr_plain.  The batched form of the comparator,
 // and a candidate of the autotuner for images whose counts are low and even.
-template <class A>
+template <class A, int COLOR>
 __device__ __forceinline__ void plain_pixel(const PersistentArgs& a, CFrame& F, int i, int j,
                                             int32_t* out) {
     const double px = pixel_re(F.cx, F.hx, i, F.width);
@@ -826,12 +830,13 @@ __device__ __forceinline__ void plain_pixel(const PersistentArgs& a, CFrame& F, 
         if (!A::check_step(z, c)) break;
         n++;
     }
-    out[(int64_t)j * F.width + i] = shade(a, n);
+    out[(int64_t)j * F.width + i] = shade<COLOR>(a, n);
 }
 
 template <int DTMASK>
 __global__ __launch_bounds__(256) void jr_plain_batch(PersistentArgs a) {
-    stage_palette(a);
+    constexpr int COLOR = (DTMASK & kColorBit) ? 1 : 0;
+    stage_palette<COLOR>(a);
     CFrame* frames = cframes(a);
     const int64_t t = blockIdx.x;
     int f = 0;
@@ -850,11 +855,11 @@ __global__ __launch_bounds__(256) void jr_plain_batch(PersistentArgs a) {
     if (i >= F.width || j >= F.row_end) return;
     int32_t* out = a.out_base + F.out_offset;
     if ((DTMASK & (1 << kFP32)) && F.dtype == kFP32)
-        plain_pixel<ArF32>(a, F, i, j, out);
+        plain_pixel<ArF32, COLOR>(a, F, i, j, out);
     else if ((DTMASK & (1 << kFP64)) && F.dtype == kFP64)
-        plain_pixel<ArF64>(a, F, i, j, out);
+        plain_pixel<ArF64, COLOR>(a, F, i, j, out);
     else if ((DTMASK & (1 << kFF)) && F.dtype == kFF)
-        plain_pixel<ArFF>(a, F, i, j, out);
+        plain_pixel<ArFF, COLOR>(a, F, i, j, out);
 }
 
 // Zeroes the kQueues counters before a persistent launch (a kernel, not a
@@ -874,6 +879,7 @@ using TiledFn = void (*)(PersistentArgs);
 
 template <int K, int DEFER, int HYB>
 static TiledFn pick_mask(int dtmask) {
+    if (dtmask & kColorBit) return jr_tiled<K, DEFER, 7 | kColorBit, HYB>;
     switch (dtmask) {
         case 1 << kFP64: return jr_tiled<K, DEFER, 1 << kFP64, HYB>;
         case 1 << kFP32: return jr_tiled<K, DEFER, 1 << kFP32, HYB>;
@@ -906,6 +912,7 @@ static TiledFn pick(int unroll, int defer, int dtmask, int hybrid) {
 }
 
 static TiledFn pick_plain(int dtmask) {
+    if (dtmask & kColorBit) return jr_plain_batch<7 | kColorBit>;
     switch (dtmask) {
         case 1 << kFP64: return jr_plain_batch<1 << kFP64>;
         case 1 << kFP32: return jr_plain_batch<1 << kFP32>;
@@ -921,6 +928,7 @@ static unsigned palette_bytes(const PersistentArgs& a) {
 hipError_t launch_plain_batch(int dtmask, const PersistentArgs& args, hipStream_t stream) {
     if (args.palette_len > kPaletteMax) return hipErrorInvalidValue;
     if (args.total_tiles > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (args.palette_len > 0) dtmask |= kColorBit;
     hipLaunchKernelGGL(pick_plain(dtmask), dim3((unsigned)args.total_tiles), dim3(256),
                        palette_bytes(args), stream, args);
     return hipGetLastError();
@@ -928,6 +936,7 @@ hipError_t launch_plain_batch(int dtmask, const PersistentArgs& args, hipStream_
 
 hipError_t launch_tiled(int unroll, int defer, int dtmask, int blocks, const PersistentArgs& args,
                         hipStream_t stream) {
+    if (args.palette_len > 0) dtmask |= kColorBit;
     TiledFn fn = pick(unroll, defer, dtmask, args.hybrid);
     if (!fn || args.palette_len > kPaletteMax) return hipErrorInvalidValue;
     if (args.persistent) {
