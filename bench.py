@@ -38,11 +38,13 @@ FLOP_PER_ITER = 8
 BYTES_PER_PIXEL = 4
 METRIC = "Gpixel-iters/s (FP64/FP32/float-float) vs plain kernel; p99 frame latency"
 
-# HBM bytes per launch of the headline kernel from rocprofv3 --pmc FETCH_SIZE
-# and WRITE_SIZE (KiB summed over dispatch), scaled by the ratio the same
-# counters give for a plain device copy of known size.  None until measured on
-# the current kernel.
-MEASURED_TRAFFIC_BYTES = None
+# HBM bytes per launch of the headline kernel (jr_tiled<8,0,2,0>) from
+# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB summed over a dispatch),
+# scaled by what the same counters read for a device copy of 1 GiB (fetch x2.0,
+# write x1.0): 662,559 B fetched + 2,123,534,697 B written.  The summary with
+# the commands is profiles/jr_tiled_fp32_parameter_path_hbm_traffic.txt; set
+# to None when that kernel changes until it is measured again.
+MEASURED_TRAFFIC_BYTES = 2124197256
 
 
 def parse():
