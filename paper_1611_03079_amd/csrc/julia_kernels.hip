@@ -879,7 +879,15 @@ using TiledFn = void (*)(PersistentArgs);
 
 template <int K, int DEFER, int HYB>
 static TiledFn pick_mask(int dtmask) {
-    if (dtmask & kColorBit) return jr_tiled<K, DEFER, 7 | kColorBit, HYB>;
+    if (dtmask & kColorBit) {
+        // one-dtype colour kernels for the common cases (the all-dtype
+        // variant holds the float-float registers and runs fewer waves)
+        if (!HYB && dtmask == ((1 << kFP32) | kColorBit))
+            return jr_tiled<K, DEFER, (1 << kFP32) | kColorBit, HYB>;
+        if (!HYB && dtmask == ((1 << kFP64) | kColorBit))
+            return jr_tiled<K, DEFER, (1 << kFP64) | kColorBit, HYB>;
+        return jr_tiled<K, DEFER, 7 | kColorBit, HYB>;
+    }
     switch (dtmask) {
         case 1 << kFP64: return jr_tiled<K, DEFER, 1 << kFP64, HYB>;
         case 1 << kFP32: return jr_tiled<K, DEFER, 1 << kFP32, HYB>;
@@ -912,6 +920,8 @@ static TiledFn pick(int unroll, int defer, int dtmask, int hybrid) {
 }
 
 static TiledFn pick_plain(int dtmask) {
+    if (dtmask == ((1 << kFP32) | kColorBit)) return jr_plain_batch<(1 << kFP32) | kColorBit>;
+    if (dtmask == ((1 << kFP64) | kColorBit)) return jr_plain_batch<(1 << kFP64) | kColorBit>;
     if (dtmask & kColorBit) return jr_plain_batch<7 | kColorBit>;
     switch (dtmask) {
         case 1 << kFP64: return jr_plain_batch<1 << kFP64>;
