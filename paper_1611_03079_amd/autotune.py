@@ -51,6 +51,11 @@ def cache_key(device: str, dtype: str, max_iter: int, pixels: int) -> str:
     return "|".join((device, dtype, cap_bucket(max_iter), pixel_bucket(pixels)))
 
 
+def time_singles(frames, schedule: jr.Schedule, reps: int = 3) -> float:
+    """Sum over the frames of the median time of each rendered on its own."""
+    return sum(time_plan([f], schedule, reps=reps) for f in frames)
+
+
 def time_plan(frames, schedule: jr.Schedule, reps: int = 3, warmup: int = 1) -> float:
     """Median device time (ms) of one launch of `frames` under `schedule`."""
     import torch
@@ -73,7 +78,12 @@ def time_plan(frames, schedule: jr.Schedule, reps: int = 3, warmup: int = 1) -> 
         plan.close()
 
 
-def _stage(frames, base: jr.Schedule, variants: List[dict], reps: int, log: list) -> jr.Schedule:
+def _time(frames, s, reps, singles):
+    return time_singles(frames, s, reps) if singles else time_plan(frames, s, reps=reps)
+
+
+def _stage(frames, base: jr.Schedule, variants: List[dict], reps: int, log: list,
+           singles: bool = False) -> jr.Schedule:
     best, best_t = base, math.inf
     seen = set()
     for v in variants:
@@ -81,7 +91,7 @@ def _stage(frames, base: jr.Schedule, variants: List[dict], reps: int, log: list
         if s in seen or jr.check_schedule(s) != jr.JR_OK:
             continue
         seen.add(s)
-        t = time_plan(frames, s, reps=reps)
+        t = _time(frames, s, reps, singles)
         log.append((asdict(s), t))
         if t < best_t:
             best, best_t = s, t
@@ -89,29 +99,32 @@ def _stage(frames, base: jr.Schedule, variants: List[dict], reps: int, log: list
 
 
 def tune(frames: Sequence, base: Optional[jr.Schedule] = None, reps: int = 3,
-         log: Optional[list] = None) -> Tuple[jr.Schedule, float, list]:
-    """Search schedules for `frames`; returns (best, its median ms, log)."""
+         log: Optional[list] = None, singles: bool = False) -> Tuple[jr.Schedule, float, list]:
+    """Search schedules for `frames`; returns (best, its median ms, log).
+    With ``singles`` each frame is timed as a launch of its own (the way
+    single images are rendered) and the times are summed."""
     log = [] if log is None else log
     base = base or jr.Schedule()
-    s = _stage(frames, base, [dict(unroll=u, defer=d) for u, d in BLOCKS], reps, log)
+    s = _stage(frames, base, [dict(unroll=u, defer=d) for u, d in BLOCKS], reps, log, singles)
     s = _stage(frames, s, [dict(tile_w=tw, tile_h=th, persistent=p, refill=r)
-                           for tw, th in TILES for p in (1, 0) for r in REFILLS], reps, log)
+                           for tw, th in TILES for p in (1, 0) for r in REFILLS], reps, log,
+               singles)
     if s.persistent:
-        s = _stage(frames, s, [dict(waves_per_cu=w) for w in WAVES], reps, log)
+        s = _stage(frames, s, [dict(waves_per_cu=w) for w in WAVES], reps, log, singles)
     # re-check the block choice under the final tiling
-    s = _stage(frames, s, [dict(unroll=u, defer=d) for u, d in BLOCKS], reps, log)
+    s = _stage(frames, s, [dict(unroll=u, defer=d) for u, d in BLOCKS], reps, log, singles)
     best_t = min(t for d, t in log if jr.Schedule(**d) == s)
     # the hybrid stream under the chosen tiling, with several bail points
     tiled = s
     for bail in HYBRID_BAILS:
         h = replace(tiled, kernel="hybrid", bail=bail)
-        t = time_plan(frames, h, reps=reps)
+        t = _time(frames, h, reps, singles)
         log.append((asdict(h), t))
         if t < best_t:
             s, best_t = h, t
     # the one-thread-per-pixel kernel over the batch is a candidate too
     plain = jr.Schedule(kernel="plain", order=s.order)
-    t = time_plan(frames, plain, reps=reps)
+    t = _time(frames, plain, reps, singles)
     log.append((asdict(plain), t))
     if t < best_t:
         s, best_t = plain, t
@@ -138,10 +151,13 @@ def save_cache(cache: Dict[str, dict], path: str = DEFAULT_CACHE):
     os.replace(tmp, path)
 
 
-def record(cache: Dict[str, dict], frames: Sequence, schedule: jr.Schedule, ms: float):
+def record(cache: Dict[str, dict], frames: Sequence, schedule: jr.Schedule, ms: float,
+           singles: bool = False):
+    """File the winner under the bucket its launches fall in: the batch, or
+    with ``singles`` one of its frames."""
     dtype = max(set(f.dtype for f in frames), key=lambda d: sum(f.pixels for f in frames if f.dtype == d))
     cap = max(f.max_iter for f in frames)
-    px = sum(f.pixels for f in frames)
+    px = max(f.pixels for f in frames) if singles else sum(f.pixels for f in frames)
     cache[cache_key(device_name(), dtype, cap, px)] = {"schedule": asdict(schedule), "ms": ms}
 
 
@@ -159,13 +175,21 @@ def apply_cache(cache: Dict[str, dict], max_iter: int = 100, pixels: int = 1 << 
 
 
 # ------------------------------------------------------------------ command line
+# workloads rendered one image per launch (tuned and filed per image)
+SINGLES = {"single_4096_fp32_cap100", "single_4096_fp32_cap1000", "single_4096_fp64_cap100",
+           "single_4096_fp64_cap1000", "single_512_fp64"}
+
+
 def standard_workloads():
-    """Representative batches of the workloads the library is tuned for."""
+    """Representative workloads the library is tuned for: batches rendered in
+    one launch, and single images (SINGLES) rendered one per launch."""
     import workloads as wl
     return {
         "parameter_path_fp32": wl.parameter_path(),
-        "single_4096_fp32": [wl.single_4096(s, it, "fp32") for it in (100, 1000) for s in range(2)],
-        "single_4096_fp64": [wl.single_4096(s, it, "fp64") for it in (100, 1000) for s in range(2)],
+        "single_4096_fp32_cap100": [wl.single_4096(s, 100, "fp32") for s in range(2)],
+        "single_4096_fp32_cap1000": [wl.single_4096(s, 1000, "fp32") for s in range(2)],
+        "single_4096_fp64_cap100": [wl.single_4096(s, 100, "fp64") for s in range(2)],
+        "single_4096_fp64_cap1000": [wl.single_4096(s, 1000, "fp64") for s in range(2)],
         "single_512_fp64": [wl.single_512("fp64")],
         "uneven_fp32_ff": wl.uneven_batch(0, n=16),
         "cardioid_path_fp32": wl.cardioid_path(64),
@@ -185,8 +209,9 @@ def main(argv=None):
     for name, frames in standard_workloads().items():
         if args.only and name not in args.only:
             continue
-        best, ms, log = tune(frames, reps=args.reps)
-        record(cache, frames, best, ms)
+        singles = name in SINGLES
+        best, ms, log = tune(frames, reps=args.reps, singles=singles)
+        record(cache, frames, best, ms, singles=singles)
         cache.setdefault("_workloads", {})[name] = {"schedule": asdict(best), "ms": ms,
                                                     "candidates": len(log)}
         print("%-22s %9.4f ms  %s" % (name, ms, best), flush=True)
