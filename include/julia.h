@@ -123,9 +123,23 @@ typedef struct {
  *                   fresh pixels at a time with a test on every iteration and
  *                   only the pixels still running after `bail` iterations
  *                   continue in refilled blocks (they wait in shared memory).
- *   bail            JR_KERNEL_HYBRID: 1..4096 (other kernels ignore it).
+ *                   JR_KERNEL_ROWS: each wave takes a tile row by row (lane
+ *                   = column); every pixel of a row first runs `bail` counted
+ *                   iterations with no exchange between lanes, pixels that
+ *                   finish store at once, and the others wait in a per-wave
+ *                   list in shared memory, which the wave then drains with
+ *                   refilled counted blocks of `unroll` (4 or 8, defer 0).
+ *                   tile_h is capped at 16 rows for batches of FP32 frames
+ *                   only, 8 otherwise (the list's size).
+ *   bail            JR_KERNEL_HYBRID: 1..4096; JR_KERNEL_ROWS: 1..64 (other
+ *                   kernels ignore it).
  */
-typedef enum { JR_KERNEL_TILED = 0, JR_KERNEL_PLAIN = 1, JR_KERNEL_HYBRID = 2 } jr_kernel;
+typedef enum {
+    JR_KERNEL_TILED = 0,
+    JR_KERNEL_PLAIN = 1,
+    JR_KERNEL_HYBRID = 2,
+    JR_KERNEL_ROWS = 3
+} jr_kernel;
 typedef struct {
     int32_t tile_w, tile_h;
     int32_t unroll;

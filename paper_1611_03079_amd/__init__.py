@@ -21,7 +21,7 @@ JR_OK, JR_EINVAL, JR_ENOMEM, JR_ENODEV, JR_ELAUNCH, JR_EINTERNAL = 0, -1, -2, -3
 DTYPES = {"fp64": 0, "fp32": 1, "ff": 2}
 MODES = {"julia": 0, "mandelbrot": 1}
 ORDERS = {"table": 0, "cost": 1}
-KERNELS = {"tiled": 0, "plain": 1, "hybrid": 2}
+KERNELS = {"tiled": 0, "plain": 1, "hybrid": 2, "rows": 3}
 
 
 class JuliaError(RuntimeError):

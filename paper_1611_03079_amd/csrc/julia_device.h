@@ -50,13 +50,20 @@ struct PersistentArgs {
     int32_t refill;
     int32_t persistent;  // 1: work queues; 0: one wave per tile
     int32_t hybrid;      // 1: fresh packets + survivor queue (run_hybrid)
-    int32_t bail;        // hybrid: iterations of a fresh packet before its survivors park
+    int32_t bail;        // hybrid: iterations of a fresh packet before its survivors park;
+                         // rows: length of the first counted block of every row
+    int32_t rows;        // 1: two-phase row-packet kernel (jr_rows)
+    int32_t pad_;
     int32_t palette_len; // > 0: a pixel stores palette[min(count, palette_len - 1)]
     const uint32_t* palette;
 };
 
 // Largest colour table of the fused colour store; it is staged in LDS.
 constexpr int kPaletteMax = 8192;
+// Row-packet kernel: rows of a tile a wave's survivor list holds (64 pixels
+// each): 16 for FP32-only launches, 8 when FP64 or float-float frames are in.
+constexpr int kRowsFP32 = 16;
+constexpr int kRowsWide = 8;
 // Kernel variants that store colours carry this bit beside the dtype bits
 // (compile-time, so the counting kernels hold no colour code).
 constexpr int kColorBit = 8;

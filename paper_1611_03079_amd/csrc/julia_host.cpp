@@ -112,10 +112,16 @@ int check_schedule(const jr_schedule& s) {
     if (s.order != JR_ORDER_TABLE && s.order != JR_ORDER_COST)
         return fail(JR_EINVAL, "schedule: unknown order %d", s.order);
     if (s.kernel != JR_KERNEL_TILED && s.kernel != JR_KERNEL_PLAIN &&
-        s.kernel != JR_KERNEL_HYBRID)
+        s.kernel != JR_KERNEL_HYBRID && s.kernel != JR_KERNEL_ROWS)
         return fail(JR_EINVAL, "schedule: unknown kernel %d", s.kernel);
     if (s.kernel == JR_KERNEL_HYBRID && (s.bail < 1 || s.bail > 4096))
         return fail(JR_EINVAL, "schedule: bail must be in 1..4096 (got %d)", s.bail);
+    if (s.kernel == JR_KERNEL_ROWS) {
+        if (s.defer != 0 || (s.unroll != 4 && s.unroll != 8))
+            return fail(JR_EINVAL, "schedule: the rows kernel takes defer 0 and unroll 4 or 8");
+        if (s.bail < 1 || s.bail > 64)
+            return fail(JR_EINVAL, "schedule: rows kernel bail must be in 1..64 (got %d)", s.bail);
+    }
     return JR_OK;
 }
 
@@ -212,6 +218,7 @@ jr::PersistentArgs make_args(const Table& t, const DevFrame* d_table, int32_t* o
     a.refill = s.refill;
     a.persistent = s.persistent;
     a.hybrid = s.kernel == JR_KERNEL_HYBRID ? 1 : 0;
+    a.rows = s.kernel == JR_KERNEL_ROWS ? 1 : 0;
     a.bail = s.bail;
     return a;
 }
@@ -226,6 +233,13 @@ void build_table(const jr_frame* frames, int32_t n, const jr_schedule& s, Table&
     t.rows.resize(n);
     t.total_tiles = 0;
     t.dtmask = 0;
+    // The rows kernel's per-wave list holds a fixed number of tile rows.
+    int32_t rows_cap = 64;
+    if (s.kernel == JR_KERNEL_ROWS) {
+        int mask = 0;
+        for (int32_t k = 0; k < n; ++k) mask |= 1 << frames[k].dtype;
+        rows_cap = mask == (1 << JR_FP32) ? jr::kRowsFP32 : jr::kRowsWide;
+    }
     for (int32_t k = 0; k < n; ++k) {
         const jr_frame& f = frames[idx[k]];
         DevFrame& d = t.rows[k];
@@ -247,7 +261,7 @@ void build_table(const jr_frame* frames, int32_t n, const jr_schedule& s, Table&
         d.row_begin = f.row_begin;
         d.row_end = f.row_end == 0 ? f.height : f.row_end;
         const int32_t tw = s.kernel == JR_KERNEL_PLAIN ? 16 : s.tile_w;
-        const int32_t th = s.kernel == JR_KERNEL_PLAIN ? 16 : s.tile_h;
+        const int32_t th = s.kernel == JR_KERNEL_PLAIN ? 16 : std::min(s.tile_h, rows_cap);
         d.tile_w = std::min(tw, f.width);
         d.tile_h = std::min(th, d.row_end - d.row_begin);
         d.tiles_x = (f.width + d.tile_w - 1) / d.tile_w;

@@ -862,6 +862,217 @@ __global__ __launch_bounds__(256) void jr_plain_batch(PersistentArgs a) {
         plain_pixel<ArFF, COLOR>(a, F, i, j, out);
 }
 
+// ---------------------------------------------------------------------------
+// Row-packet kernel (two phases per tile).
+// ---------------------------------------------------------------------------
+// Most pixels of a light image escape within a few iterations, and in the
+// refill stream each of them still costs a block of K iterations and a share of
+// a refill round.  Here a wave takes its tile (at most 64 columns, lane L =
+// column L) row by row:
+//   phase 1  every lane runs its pixel of the row for P counted iterations,
+//            without branches; the row's coordinate is one value for the whole
+//            wave and the column's is the lane's own, so nothing is exchanged
+//            between lanes.  Pixels that escape (or reach the cap) within P
+//            store their count at once, one coalesced row store;
+//   survivors append their iterate (Z_P) and position to the wave's list in
+//            LDS (stored one array per word, so lanes hit distinct banks);
+//   phase 2  once the tile's rows are done, the wave drains the list with the
+//            refill stream in counted blocks of K: idle lanes read the next
+//            entries straight from the list, and C is the frame's constant.
+// Counts: phase 1 counts the leading non-escaped iterates of Z_0..Z_{P-1}; with
+// escape absorbing (|C| <= 1.9) that is min(count, P), so a pixel with fewer
+// than P is final and the others continue from Z_P with n = P.  Frames where
+// escape may not be absorbing run P = 1 and K = 1, the exact test on every
+// iteration.
+template <int DTMASK>
+struct RowsShape {
+    static constexpr int kMask = DTMASK & 7;
+    static constexpr int rows = kMask == (1 << kFP32) ? kRowsFP32 : kRowsWide;
+    // widest iterate among the dtypes of the kernel, plus the position word
+    static constexpr int words = ((kMask & ((1 << kFP64) | (1 << kFF))) ? 4 : 2) + 1;
+};
+
+template <class A>
+__device__ __forceinline__ typename A::V bcast(typename A::V v, int lane) {
+    constexpr int W = (int)(sizeof(typename A::V) / 4);
+    uint32_t w[W];
+    __builtin_memcpy(w, &v, sizeof(v));
+#pragma unroll
+    for (int j = 0; j < W; ++j) w[j] = __builtin_amdgcn_readlane(w[j], lane);
+    typename A::V r;
+    __builtin_memcpy(&r, w, sizeof(r));
+    return r;
+}
+
+template <class A>
+__device__ __forceinline__ void list_put(uint32_t* list, int cap, int e, const typename A::Z& z) {
+    constexpr int W = (int)(sizeof(typename A::Z) / 4);
+    uint32_t w[W];
+    __builtin_memcpy(w, &z, sizeof(z));
+#pragma unroll
+    for (int j = 0; j < W; ++j) list[j * cap + e] = w[j];
+}
+
+template <class A>
+__device__ __forceinline__ typename A::Z list_get(const uint32_t* list, int cap, int e) {
+    constexpr int W = (int)(sizeof(typename A::Z) / 4);
+    uint32_t w[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) w[j] = list[j * cap + e];
+    typename A::Z z;
+    __builtin_memcpy(&z, w, sizeof(z));
+    return z;
+}
+
+// One tile: phase 1 over its rows, then phase 2 over the survivors.  `list`
+// holds `cap` entries; word W of entry e is list[W * cap + e], the position
+// (row << 6 | column) is the last word.
+template <class A, int K, int MANDEL, int COLOR>
+__device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, uint32_t* list,
+                          int cap, int rows_max) {
+    using V = typename A::V;
+    constexpr int ZW = (int)(sizeof(typename A::Z) / 4);
+    const uint32_t local = (uint32_t)(t - F.tile_begin);
+    const int ty = (int)(local / (uint32_t)F.tiles_x);
+    const int tx = (int)(local - (uint32_t)ty * (uint32_t)F.tiles_x);
+    const int col0 = tx * F.tile_w;
+    const int row0 = F.row_begin + ty * F.tile_h;
+    const int tw = min(F.tile_w, F.width - col0);
+    const int th = min(min(F.tile_h, F.row_end - row0), rows_max);
+    const int W = F.width;
+    const int mi = F.max_iter;
+    const int lane = lane_id();
+    const V zero = A::coord(0.0);
+    const V xl = A::coord(pixel_re(F.cx, F.hx, col0 + min(lane, tw - 1), W));
+    const V yl = A::coord(pixel_im(F.cy, F.hy, row0 + min(lane, th - 1), F.height));
+    const typename A::C cj = A::cmake(A::coord(F.cr), A::coord(F.ci));
+    int32_t* tout = a.out_base + F.out_offset + ((int64_t)row0 * W + col0);
+    const bool col_ok = lane < tw;
+
+    // phase 1
+    int qn = 0;
+    for (int r = 0; r < th; ++r) {
+        const V y = bcast<A>(yl, r);
+        typename A::Z z;
+        typename A::C c;
+        if (MANDEL) {
+            z = A::make(zero, zero);
+            c = A::cmake(xl, y);
+        } else {
+            z = A::make(xl, y);
+            c = cj;
+        }
+        int lead = 0;
+#pragma unroll 1
+        for (int u = 0; u < P; ++u) lead += A::check_step(z, c) ? 1 : 0;
+        const bool fin = col_ok && (lead < P || P >= mi);
+        if (fin) tout[r * W + lane] = shade<COLOR>(a, min(lead, mi));
+        const bool sv = col_ok && !fin;
+        const uint64_t m = __ballot(sv);
+        if (sv) {
+            const int e = qn + lanes_below(m);
+            list_put<A>(list, cap, e, z);
+            list[ZW * cap + e] = ((uint32_t)r << 6) | (uint32_t)lane;
+        }
+        qn += __popcll(m);
+    }
+    // Other lanes read the entries written above: keep the compiler from
+    // moving LDS accesses across this point (one wave runs them in order).
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+
+    // phase 2
+    bool it = false, fi = false;
+    int n = 0, cnt = 0, off = 0;
+    typename A::Z z = A::make(zero, zero);
+    typename A::C c = cj;
+    int next = 0;
+    uint64_t running = 0;
+    const int busy_max = 64 - a.refill;
+    for (;;) {
+        if (__popcll(running) <= busy_max) {
+            if (fi) {
+                tout[off] = shade<COLOR>(a, cnt);
+                fi = false;
+            }
+            if (next < qn) {
+                const uint64_t idle = ~running;
+                const int e = next + lanes_below(idle);
+                const int ee = min(e, qn - 1);
+                const typename A::Z zl = list_get<A>(list, cap, ee);
+                const uint32_t id = list[ZW * cap + ee];
+                const int r = (int)(id >> 6);
+                const int col = (int)(id & 63u);
+                V cx = zero, cy = zero;
+                if (MANDEL) {
+                    cx = A::shfl(xl, col);
+                    cy = A::shfl(yl, r);
+                }
+                if (!it && e < qn) {
+                    z = zl;
+                    if (MANDEL) c = A::cmake(cx, cy);
+                    off = r * W + col;
+                    n = P;
+                    it = true;
+                }
+                next += __popcll(idle);
+            }
+            running = __ballot(it);
+            if (running == 0) {
+                // the next tile's first phase overwrites entries read here
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                return;
+            }
+        }
+        int lead = 0;
+#pragma unroll
+        for (int u = 0; u < K; ++u) lead += A::check_step(z, c) ? 1 : 0;
+        const bool stop = (lead < K) || (n + K >= mi);
+        cnt = (it && stop) ? min(n + lead, mi) : cnt;
+        fi = fi || (it && stop);
+        it = it && !stop;
+        n += K;
+        running = __ballot(it);
+    }
+}
+
+// Waves of 64 lanes, one tile at a time (from the dispatcher or the work
+// queues), each tile in two phases (rows_tile).  P, the first block's length,
+// is the schedule's bail field; K is the second phase's block length.
+template <int K, int DTMASK>
+__global__ __launch_bounds__(256) void jr_rows(PersistentArgs a) {
+    constexpr int COLOR = (DTMASK & kColorBit) ? 1 : 0;
+    using S = RowsShape<DTMASK>;
+    constexpr int cap = 64 * S::rows;
+    __shared__ uint32_t lmem[4 * S::words * cap];
+    uint32_t* list = lmem + (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * S::words * cap;
+    stage_palette<COLOR>(a);
+    Claimer cl;
+    claimer_init(cl, a);
+    CFrame* frames = cframes(a);
+    int f = 0;
+    for (int64_t t = next_tile(cl, a); t >= 0; t = next_tile(cl, a)) {
+        f = find_frame(frames, a.nframes, t, f);
+        CFrame& F = frames[f];
+        const bool abs = F.defer != 0;
+        const int P = abs ? a.bail : 1;
+        const bool mandel = F.mode == kModeMandelbrot;
+#define JR_ROWS(A_)                                                                      \
+    do {                                                                                 \
+        if (abs && !mandel) rows_tile<A_, K, 0, COLOR>(a, F, t, P, list, cap, S::rows);  \
+        else if (abs) rows_tile<A_, K, 1, COLOR>(a, F, t, P, list, cap, S::rows);        \
+        else if (!mandel) rows_tile<A_, 1, 0, COLOR>(a, F, t, P, list, cap, S::rows);    \
+        else rows_tile<A_, 1, 1, COLOR>(a, F, t, P, list, cap, S::rows);                 \
+    } while (0)
+        if ((DTMASK & (1 << kFP32)) && F.dtype == kFP32)
+            JR_ROWS(ArF32);
+        else if ((DTMASK & (1 << kFP64)) && F.dtype == kFP64)
+            JR_ROWS(ArF64);
+        else if ((DTMASK & (1 << kFF)) && F.dtype == kFF)
+            JR_ROWS(ArFF);
+#undef JR_ROWS
+    }
+}
+
 // Zeroes the kQueues counters before a persistent launch (a kernel, not a
 // memset, so that it can sit inside a captured hipGraph).
 __global__ void jr_reset_queues(unsigned long long* ctr) {
@@ -915,6 +1126,25 @@ static TiledFn pick_block(int unroll, int defer, int dtmask) {
     }
 }
 
+template <int K>
+static TiledFn pick_rows_mask(int dtmask) {
+    switch (dtmask) {
+        case 1 << kFP32: return jr_rows<K, 1 << kFP32>;
+        case 1 << kFP64: return jr_rows<K, 1 << kFP64>;
+        case 1 << kFF: return jr_rows<K, 1 << kFF>;
+        case (1 << kFP32) | kColorBit: return jr_rows<K, (1 << kFP32) | kColorBit>;
+        default: return (dtmask & kColorBit) ? jr_rows<K, 7 | kColorBit> : jr_rows<K, 7>;
+    }
+}
+
+static TiledFn pick_rows(int unroll, int dtmask) {
+    switch (unroll) {
+        case 4: return pick_rows_mask<4>(dtmask);
+        case 8: return pick_rows_mask<8>(dtmask);
+        default: return nullptr;
+    }
+}
+
 static TiledFn pick(int unroll, int defer, int dtmask, int hybrid) {
     return hybrid ? pick_block<1>(unroll, defer, dtmask) : pick_block<0>(unroll, defer, dtmask);
 }
@@ -947,7 +1177,7 @@ hipError_t launch_plain_batch(int dtmask, const PersistentArgs& args, hipStream_
 hipError_t launch_tiled(int unroll, int defer, int dtmask, int blocks, const PersistentArgs& args,
                         hipStream_t stream) {
     if (args.palette_len > 0) dtmask |= kColorBit;
-    TiledFn fn = pick(unroll, defer, dtmask, args.hybrid);
+    TiledFn fn = args.rows ? pick_rows(unroll, dtmask) : pick(unroll, defer, dtmask, args.hybrid);
     if (!fn || args.palette_len > kPaletteMax) return hipErrorInvalidValue;
     if (args.persistent) {
         hipLaunchKernelGGL(jr_reset_queues, dim3(1), dim3(kQueues), 0, stream, args.ctr);

@@ -112,12 +112,16 @@ def test_check_schedule_rejects(field, value):
     assert jr.check_schedule(s) == jr.JR_OK
     if field == "kernel":
         c = s.to_c()
-        c.kernel = 3
+        c.kernel = 4
         assert jr.lib.jr_check_schedule(ctypes.byref(c)) == jr.JR_EINVAL
         assert jr.check_schedule(jr.Schedule(kernel="plain")) == jr.JR_OK
         assert jr.check_schedule(jr.Schedule(kernel="hybrid", bail=16)) == jr.JR_OK
         assert jr.check_schedule(jr.Schedule(kernel="hybrid", bail=0)) == jr.JR_EINVAL
         assert jr.check_schedule(jr.Schedule(kernel="tiled", bail=0)) == jr.JR_OK
+        rows = jr.Schedule(64, 16, 8, 0, 16, 0, 16, "cost", "rows", 4)
+        assert jr.check_schedule(rows) == jr.JR_OK
+        for bad in (dict(bail=0), dict(bail=65), dict(unroll=2), dict(unroll=8, defer=1)):
+            assert jr.check_schedule(jr.Schedule(**{**rows.__dict__, **bad})) == jr.JR_EINVAL
         return
     assert jr.check_schedule(jr.Schedule(unroll=16, defer=1)) == jr.JR_OK
     assert jr.check_schedule(jr.Schedule(unroll=2, defer=1)) == jr.JR_EINVAL

@@ -34,6 +34,10 @@ SCHEDULES = [
     jr.Schedule(64, 16, 8, 0, 16, 0, 16, "cost", "hybrid", 8),
     jr.Schedule(32, 8, 8, 1, 32, 1, 16, "table", "hybrid", 3),
     jr.Schedule(16, 16, 4, 0, 48, 0, 16, "cost", "hybrid", 1),
+    jr.Schedule(64, 16, 8, 0, 16, 0, 16, "cost", "rows", 4),   # two phases per tile
+    jr.Schedule(37, 5, 4, 0, 32, 1, 8, "table", "rows", 2),   # ragged tiles, work queues
+    jr.Schedule(64, 64, 8, 0, 8, 0, 16, "cost", "rows", 1),   # tile height clamped
+    jr.Schedule(1, 1, 4, 0, 1, 1, 4, "cost", "rows", 64),     # one-pixel tiles, long first block
 ]
 
 
