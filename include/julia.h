@@ -129,8 +129,8 @@ typedef struct {
  *                   finish store at once, and the others wait in a per-wave
  *                   list in shared memory, which the wave then drains with
  *                   refilled counted blocks of `unroll` (4 or 8, defer 0).
- *                   tile_h is capped at 16 rows for batches of FP32 frames
- *                   only, 8 otherwise (the list's size).
+ *                   tile_h is capped at 8 rows for batches of FP32 frames
+ *                   only, 4 otherwise (the list's size).
  *   bail            JR_KERNEL_HYBRID: 1..4096; JR_KERNEL_ROWS: 1..64 (other
  *                   kernels ignore it).
  */

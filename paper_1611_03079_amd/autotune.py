@@ -13,7 +13,9 @@ Search, in stages from a base schedule:
   4. the iteration block again under the chosen tiling,
   5. the hybrid stream (fresh packets tested every iteration, survivors
      refilled) under that tiling, for several bail points,
-  6. the batched one-thread-per-pixel kernel as a last candidate.
+  6. the two-phase row-packet kernel: its first block, then scheduling mode,
+     refill, resident waves and tile shape, then its first block again,
+  7. the batched one-thread-per-pixel kernel as a last candidate.
 
 Results are cached in a JSON file keyed by (device, dtype, cap bucket, pixel
 bucket); ``apply_cache`` installs the cached winners as the library defaults
@@ -33,6 +35,7 @@ TILES = [(64, 1), (64, 4), (64, 16), (32, 8), (16, 16), (64, 64)]
 REFILLS = [8, 16, 32, 64]
 WAVES = [8, 16, 24, 32]
 HYBRID_BAILS = [4, 8, 16, 32]
+ROWS_FIRST = [2, 3, 4, 6, 8]
 
 DEFAULT_CACHE = os.environ.get(
     "JR_AUTOTUNE_CACHE",
@@ -122,6 +125,18 @@ def tune(frames: Sequence, base: Optional[jr.Schedule] = None, reps: int = 3,
         log.append((asdict(h), t))
         if t < best_t:
             s, best_t = h, t
+    # the two-phase row-packet kernel: first-block length x second block,
+    # then scheduling mode, refill and resident waves, then the first block again
+    r = jr.Schedule(64, 8, 8, 0, 16, 1, 32, s.order, "rows", 4)
+    r = _stage(frames, r, [dict(bail=p, unroll=k) for p in ROWS_FIRST for k in (4, 8)], reps, log,
+               singles)
+    r = _stage(frames, r, [dict(persistent=p, refill=rf, waves_per_cu=w, tile_w=tw, tile_h=th)
+                           for p in (1, 0) for rf in (8, 16, 32) for w in (16, 32)
+                           for tw, th in ((64, 8), (64, 4), (32, 8))], reps, log, singles)
+    r = _stage(frames, r, [dict(bail=p) for p in ROWS_FIRST], reps, log, singles)
+    t = min(tt for d, tt in log if jr.Schedule(**d) == r)
+    if t < best_t:
+        s, best_t = r, t
     # the one-thread-per-pixel kernel over the batch is a candidate too
     plain = jr.Schedule(kernel="plain", order=s.order)
     t = _time(frames, plain, reps, singles)
