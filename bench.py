@@ -38,13 +38,23 @@ FLOP_PER_ITER = 8
 BYTES_PER_PIXEL = 4
 METRIC = "Gpixel-iters/s (FP64/FP32/float-float) vs plain kernel; p99 frame latency"
 
-# HBM bytes per launch of the headline kernel (jr_tiled<8,0,2,0>) from
-# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB summed over a dispatch),
-# scaled by what the same counters read for a device copy of 1 GiB (fetch x2.0,
-# write x1.0): 662,559 B fetched + 2,123,534,697 B written.  The summary with
-# the commands is profiles/jr_tiled_fp32_parameter_path_hbm_traffic.txt; set
-# to None when that kernel changes until it is measured again.
-MEASURED_TRAFFIC_BYTES = 2124197256
+# HBM bytes per launch of the headline kernel from rocprofv3 --pmc FETCH_SIZE
+# and WRITE_SIZE (KiB summed over a dispatch), scaled by what the same
+# counters read for a device copy of 1 GiB (fetch x2.0, write x1.0), keyed by
+# the kernel instance they were taken on.  The summaries with their commands
+# are in profiles/.  A kernel without an entry reports null.
+MEASURED_TRAFFIC_BYTES = {
+    "jr_tiled<8, 0, 2, 0>": 2124197256,  # 662,559 B fetched + 2,123,534,697 B written
+}
+
+# The kernel instance a schedule launches for an FP32-only batch that stores
+# counts (template arguments as rocprofv3 prints them).
+def kernel_instance(sched):
+    if sched.kernel == "rows":
+        return "jr_rows<%d, 2>" % sched.unroll
+    if sched.kernel == "plain":
+        return "jr_plain_batch<2>"
+    return "jr_tiled<%d, %d, 2, %d>" % (sched.unroll, sched.defer, int(sched.kernel == "hybrid"))
 
 
 def parse():
@@ -301,13 +311,13 @@ def main():
                    "tiles": info["tiles"], "workgroups": info["workgroups"]},
         "roofline": {"bound": "hbm", "achieved": round(store_gbs, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(store_gbs / PEAK_HBM_GBS, 4),
-                     "traffic": MEASURED_TRAFFIC_BYTES,
+                     "traffic": MEASURED_TRAFFIC_BYTES.get(kernel_instance(sched)),
                      "algorithmic_bytes_per_launch": BYTES_PER_PIXEL * pixels,
                      "kernel_ms": round(kernel_ms, 4),
                      "alu": {"achieved": round(alu_tflops, 2), "peak": PEAK_FP32_TFLOPS,
                              "unit": "TFLOP/s", "frac": round(alu_tflops / PEAK_FP32_TFLOPS, 4),
                              "flops_per_launch": FLOP_PER_ITER * iters},
-                     "kernel": "jr_tiled (libjulia.so)"},
+                     "kernel": kernel_instance(sched) + " (libjulia.so)"},
     }
     if not args.no_extra:
         line["extra"] = extra_legs(args, torch, jr, wl, frames, sched, ms_step, iters)

@@ -266,7 +266,9 @@ def render(c, window, width: int, height: int, max_iter: int, dtype: str = "fp64
     if not plain:
         if schedule is None:
             schedule = tuned_schedule(dtype, max_iter, width * height)
-        if schedule is not None:
+            # one image with the one-thread-per-pixel kernel: its 2-D grid form
+            plain = schedule is not None and schedule.kernel == "plain"
+        if schedule is not None and not plain:
             f = _OneFrame(c, window, width, height, max_iter, dtype, mode)
             arr = _frames_array([f], [0])
             _check(lib.julia_render_batch(arr, 1, ctypes.c_void_p(out.data_ptr()),

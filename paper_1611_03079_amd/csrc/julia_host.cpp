@@ -150,12 +150,13 @@ int check_frames(const jr_frame* frames, int32_t n, int64_t capacity) {
 // ------------------------------------------------------------- schedules
 std::mutex g_sched_mu;
 // Defaults per dtype; the autotuner can replace them (jr_set_default_schedule).
-// Starting points from the autotuner's runs on MI355X (one wave per tile was
-// faster than the work queues on every workload measured).
+// Starting points from the autotuner's runs on MI355X.  FP32 takes the
+// two-phase rows kernel, which won every FP32 workload measured; one wave per
+// tile keeps one-image calls free of the work queues (and so capturable).
 jr_schedule g_default[3] = {
     // tile_w, tile_h, unroll, defer, refill, persistent, waves_per_cu, order, kernel, bail
     {16, 16, 8, 0, 16, 0, 16, JR_ORDER_COST, JR_KERNEL_TILED, 8},  // FP64
-    {64, 16, 8, 1, 32, 0, 16, JR_ORDER_COST, JR_KERNEL_TILED, 8},  // FP32
+    {64, 8, 8, 0, 32, 0, 16, JR_ORDER_COST, JR_KERNEL_ROWS, 6},    // FP32
     {16, 16, 8, 1, 64, 0, 16, JR_ORDER_COST, JR_KERNEL_TILED, 8},  // FF
 };
 
