@@ -50,8 +50,11 @@ def pixel_bucket(pixels: int) -> str:
     return "px<1M" if pixels < (1 << 20) else "px<64M" if pixels < (64 << 20) else "px>=64M"
 
 
-def cache_key(device: str, dtype: str, max_iter: int, pixels: int) -> str:
-    return "|".join((device, dtype, cap_bucket(max_iter), pixel_bucket(pixels)))
+def cache_key(device: str, dtype: str, max_iter: int, pixels: int, batch: bool = False) -> str:
+    """Bucket of a single image, or (batch) of a batch launch: batches are
+    filed apart so that a batch's winner never serves one image."""
+    parts = [device, dtype, cap_bucket(max_iter), pixel_bucket(pixels)]
+    return "|".join(parts + (["batch"] if batch else []))
 
 
 def time_singles(frames, schedule: jr.Schedule, reps: int = 3) -> float:
@@ -173,7 +176,8 @@ def record(cache: Dict[str, dict], frames: Sequence, schedule: jr.Schedule, ms: 
     dtype = max(set(f.dtype for f in frames), key=lambda d: sum(f.pixels for f in frames if f.dtype == d))
     cap = max(f.max_iter for f in frames)
     px = max(f.pixels for f in frames) if singles else sum(f.pixels for f in frames)
-    cache[cache_key(device_name(), dtype, cap, px)] = {"schedule": asdict(schedule), "ms": ms}
+    cache[cache_key(device_name(), dtype, cap, px, batch=not singles)] = {
+        "schedule": asdict(schedule), "ms": ms}
 
 
 def lookup(cache: Dict[str, dict], dtype: str, max_iter: int, pixels: int) -> Optional[jr.Schedule]:
