@@ -61,9 +61,9 @@ struct PersistentArgs {
 // Largest colour table of the fused colour store; it is staged in LDS.
 constexpr int kPaletteMax = 8192;
 // Row-packet kernel: rows of a tile a wave's survivor list holds (64 pixels
-// each): 8 for FP32-only launches (24 KiB of LDS per 4-wave workgroup), 4 when
-// FP64 or float-float frames are in (20 KiB).  Larger lists cost more in
-// resident waves than they save in drains.
+// each): 8 for FP32-only launches (20 KiB of LDS per 4-wave workgroup, so 8
+// workgroups fit a CU), 4 when FP64 or float-float frames are in (18 KiB).
+// Larger lists cost more in resident waves than they save in drains.
 constexpr int kRowsFP32 = 8;
 constexpr int kRowsWide = 4;
 // Kernel variants that store colours carry this bit beside the dtype bits

@@ -888,8 +888,10 @@ template <int DTMASK>
 struct RowsShape {
     static constexpr int kMask = DTMASK & 7;
     static constexpr int rows = kMask == (1 << kFP32) ? kRowsFP32 : kRowsWide;
-    // widest iterate among the dtypes of the kernel, plus the position word
-    static constexpr int words = ((kMask & ((1 << kFP64) | (1 << kFF))) ? 4 : 2) + 1;
+    // 32-bit words of the widest iterate among the dtypes of the kernel
+    static constexpr int zwords = (kMask & ((1 << kFP64) | (1 << kFF))) ? 4 : 2;
+    // one wave's list in 32-bit words: the iterates, then 16-bit positions
+    static constexpr int wave_words = zwords * 64 * rows + 32 * rows;
 };
 
 template <class A>
@@ -925,8 +927,9 @@ __device__ __forceinline__ typename A::Z list_get(const uint32_t* list, int cap,
 }
 
 // One tile: phase 1 over its rows, then phase 2 over the survivors.  `list`
-// holds `cap` entries; word W of entry e is list[W * cap + e], the position
-// (row << 6 | column) is the last word.
+// holds `cap` entries; word W of entry e's iterate is list[W * cap + e], and
+// its position (row << 6 | column) is the 16-bit element e of the array that
+// follows the iterate words.
 template <class A, int K, int MANDEL, int COLOR>
 __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, uint32_t* list,
                           int cap, int rows_max) {
@@ -948,6 +951,7 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
     const typename A::C cj = A::cmake(A::coord(F.cr), A::coord(F.ci));
     int32_t* tout = a.out_base + F.out_offset + ((int64_t)row0 * W + col0);
     const bool col_ok = lane < tw;
+    uint16_t* pos = (uint16_t*)(list + ZW * cap);
 
     // phase 1
     int qn = 0;
@@ -963,8 +967,13 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
             c = cj;
         }
         int lead = 0;
+        int u = 0;
 #pragma unroll 1
-        for (int u = 0; u < P; ++u) lead += A::check_step(z, c) ? 1 : 0;
+        for (; u + 2 <= P; u += 2) {
+            lead += A::check_step(z, c) ? 1 : 0;
+            lead += A::check_step(z, c) ? 1 : 0;
+        }
+        if (u < P) lead += A::check_step(z, c) ? 1 : 0;
         const bool fin = col_ok && (lead < P || P >= mi);
         if (fin) tout[r * W + lane] = shade<COLOR>(a, min(lead, mi));
         const bool sv = col_ok && !fin;
@@ -972,7 +981,7 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
         if (sv) {
             const int e = qn + lanes_below(m);
             list_put<A>(list, cap, e, z);
-            list[ZW * cap + e] = ((uint32_t)r << 6) | (uint32_t)lane;
+            pos[e] = (uint16_t)((r << 6) | lane);
         }
         qn += __popcll(m);
     }
@@ -999,7 +1008,7 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
                 const int e = next + lanes_below(idle);
                 const int ee = min(e, qn - 1);
                 const typename A::Z zl = list_get<A>(list, cap, ee);
-                const uint32_t id = list[ZW * cap + ee];
+                const uint32_t id = pos[ee];
                 const int r = (int)(id >> 6);
                 const int col = (int)(id & 63u);
                 V cx = zero, cy = zero;
@@ -1043,8 +1052,8 @@ __global__ __launch_bounds__(256) void jr_rows(PersistentArgs a) {
     constexpr int COLOR = (DTMASK & kColorBit) ? 1 : 0;
     using S = RowsShape<DTMASK>;
     constexpr int cap = 64 * S::rows;
-    __shared__ uint32_t lmem[4 * S::words * cap];
-    uint32_t* list = lmem + (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * S::words * cap;
+    __shared__ uint32_t lmem[4 * S::wave_words];
+    uint32_t* list = lmem + (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * S::wave_words;
     stage_palette<COLOR>(a);
     Claimer cl;
     claimer_init(cl, a);
