@@ -223,10 +223,17 @@ def tuned_schedule(dtype: str, max_iter: int, pixels: int) -> Optional["Schedule
             _TUNED = autotune.load_cache()
         except (OSError, ValueError):
             _TUNED = {}
-    try:
-        return autotune.lookup(_TUNED, dtype, max_iter, pixels)
-    except Exception:
-        return None
+    key = (autotune.device_name(), dtype, autotune.cap_bucket(max_iter),
+           autotune.pixel_bucket(pixels))
+    if key not in _TUNED_MEMO:
+        try:
+            _TUNED_MEMO[key] = autotune.lookup(_TUNED, dtype, max_iter, pixels)
+        except Exception:
+            _TUNED_MEMO[key] = None
+    return _TUNED_MEMO[key]
+
+
+_TUNED_MEMO = {}
 
 
 def render(c, window, width: int, height: int, max_iter: int, dtype: str = "fp64",

@@ -149,10 +149,16 @@ def tune(frames: Sequence, base: Optional[jr.Schedule] = None, reps: int = 3,
     return s, best_t, log
 
 
+_DEVICE_NAMES: Dict[int, str] = {}
+
+
 def device_name() -> str:
     import torch
-    p = torch.cuda.get_device_properties(torch.cuda.current_device())
-    return getattr(p, "gcnArchName", p.name).split(":")[0]
+    d = torch.cuda.current_device()
+    if d not in _DEVICE_NAMES:
+        p = torch.cuda.get_device_properties(d)
+        _DEVICE_NAMES[d] = getattr(p, "gcnArchName", p.name).split(":")[0]
+    return _DEVICE_NAMES[d]
 
 
 def load_cache(path: str = DEFAULT_CACHE) -> Dict[str, dict]:
