@@ -62,6 +62,13 @@ def _open(path):
         getattr(lib, name).restype = None
     lib.jro_dw_split.argtypes = [d, p_f, p_f]
     lib.jro_dw_split.restype = None
+    lib.jro_count_general.argtypes = [i32, i32, d, d, d, d, i32]
+    lib.jro_count_general.restype = i32
+    lib.jro_render_general.argtypes = [i32, i32, i32, d, d, d, d, d, d, i32, i32, i32, p_i32]
+    lib.jro_render_general.restype = None
+    lib.jro_render_pixels_general.argtypes = [i32, i32, i32, d, d, d, d, d, d, i32, i32, i32,
+                                              i64, p_i32, p_i32, p_i32]
+    lib.jro_render_pixels_general.restype = None
     p_u32 = ctypes.POINTER(ctypes.c_uint32)
     lib.jro_colorize.argtypes = [p_i32, i64, p_u32, i32, p_u32]
     lib.jro_colorize.restype = None
@@ -72,23 +79,40 @@ def _as_ptr(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
 
 
-def render(c, window, width, height, max_iter, dtype="fp64", mode="julia"):
+def render(c, window, width, height, max_iter, dtype="fp64", mode="julia", degree=2):
     """Counts of a whole image: int32 array of shape (height, width), row 0 = im_max.
 
     ``c`` is a complex (ignored in Mandelbrot mode); ``window`` is
-    (re_min, re_max, im_min, im_max).
+    (re_min, re_max, im_min, im_max).  ``degree`` 3..8 iterates the general
+    map Z^d + C (jro_render_general); 2 is the paper's Z^2 + C.
     """
     lib = _load()
     c = complex(c)
     out = np.empty((int(height), int(width)), dtype=np.int32)
-    lib.jro_render(DTYPES[dtype], MODES[mode], c.real, c.imag,
-                   *[float(v) for v in window], int(width), int(height),
-                   int(max_iter), _as_ptr(out))
+    if degree == 2:
+        lib.jro_render(DTYPES[dtype], MODES[mode], c.real, c.imag,
+                       *[float(v) for v in window], int(width), int(height),
+                       int(max_iter), _as_ptr(out))
+    else:
+        lib.jro_render_general(DTYPES[dtype], MODES[mode], int(degree), c.real, c.imag,
+                               *[float(v) for v in window], int(width), int(height),
+                               int(max_iter), _as_ptr(out))
+    return out
+
+
+def render_general(c, window, width, height, max_iter, dtype="fp64", mode="julia", degree=2):
+    """The general-map formulation for any degree 2..8, d = 2 included."""
+    lib = _load()
+    c = complex(c)
+    out = np.empty((int(height), int(width)), dtype=np.int32)
+    lib.jro_render_general(DTYPES[dtype], MODES[mode], int(degree), c.real, c.imag,
+                           *[float(v) for v in window], int(width), int(height),
+                           int(max_iter), _as_ptr(out))
     return out
 
 
 def render_pixels(c, window, width, height, max_iter, ii, jj, dtype="fp64",
-                  mode="julia"):
+                  mode="julia", degree=2):
     """Counts at the pixels (column ii[k], row jj[k]) of the image ``render`` gives."""
     lib = _load()
     c = complex(c)
@@ -96,10 +120,16 @@ def render_pixels(c, window, width, height, max_iter, ii, jj, dtype="fp64",
     jj = np.ascontiguousarray(jj, dtype=np.int32)
     assert ii.shape == jj.shape and ii.ndim == 1
     out = np.empty(ii.shape, dtype=np.int32)
-    lib.jro_render_pixels(DTYPES[dtype], MODES[mode], c.real, c.imag,
-                          *[float(v) for v in window], int(width), int(height),
-                          int(max_iter), ii.size, _as_ptr(ii), _as_ptr(jj),
-                          _as_ptr(out))
+    if degree == 2:
+        lib.jro_render_pixels(DTYPES[dtype], MODES[mode], c.real, c.imag,
+                              *[float(v) for v in window], int(width), int(height),
+                              int(max_iter), ii.size, _as_ptr(ii), _as_ptr(jj),
+                              _as_ptr(out))
+    else:
+        lib.jro_render_pixels_general(DTYPES[dtype], MODES[mode], int(degree), c.real, c.imag,
+                                      *[float(v) for v in window], int(width), int(height),
+                                      int(max_iter), ii.size, _as_ptr(ii), _as_ptr(jj),
+                                      _as_ptr(out))
     return out
 
 
@@ -126,12 +156,16 @@ def pixel_center(window, width, height, i, j):
     return x.value, y.value
 
 
-def count(z0, c, max_iter, dtype="fp64"):
-    """Count of one orbit with explicit Z_0 and C."""
+def count(z0, c, max_iter, dtype="fp64", degree=None):
+    """Count of one orbit with explicit Z_0 and C.  ``degree`` None: the
+    Z^2 + C formulations; 2..8: the general-map formulations."""
     lib = _load()
     z0, c = complex(z0), complex(c)
-    return int(lib.jro_count(DTYPES[dtype], z0.real, z0.imag, c.real, c.imag,
-                             int(max_iter)))
+    if degree is None:
+        return int(lib.jro_count(DTYPES[dtype], z0.real, z0.imag, c.real, c.imag,
+                                 int(max_iter)))
+    return int(lib.jro_count_general(DTYPES[dtype], int(degree), z0.real, z0.imag, c.real,
+                                     c.imag, int(max_iter)))
 
 
 def _pair(fn, *args):

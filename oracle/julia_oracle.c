@@ -239,6 +239,135 @@ static int32_t count_ff(dw x, dw y, dw cr, dw ci, int32_t max_iter)
 }
 
 /* ------------------------------------------------------------------------ */
+/* General maps Z^d + C (d = 2..8): Z^d by d - 1 complex products from Z.    */
+/* ------------------------------------------------------------------------ */
+static int32_t count_fp64_general(double x, double y, double cr, double ci, int32_t d,
+                                  int32_t max_iter)
+{
+    int32_t n = 0;
+    while (n < max_iter) {
+        double x2 = x * x;
+        double y2 = y * y;
+        double m = x2 + y2;
+        if (m > 4.0)
+            break;
+        double wr = x, wi = y;
+        for (int32_t k = 1; k < d; k++) {
+            double p_rr = wr * x;  /* Re W Re Z */
+            double p_ii = wi * y;  /* Im W Im Z */
+            double p_ri = wr * y;  /* Re W Im Z */
+            double p_ir = wi * x;  /* Im W Re Z */
+            double nr = p_rr - p_ii;
+            double ni = p_ri + p_ir;
+            wr = nr;
+            wi = ni;
+        }
+        x = wr + cr;
+        y = wi + ci;
+        n = n + 1;
+    }
+    return n;
+}
+
+static int32_t count_fp32_general(float x, float y, float cr, float ci, int32_t d,
+                                  int32_t max_iter)
+{
+    int32_t n = 0;
+    while (n < max_iter) {
+        float x2 = x * x;
+        float y2 = y * y;
+        float m = x2 + y2;
+        if (m > 4.0f)
+            break;
+        float wr = x, wi = y;
+        for (int32_t k = 1; k < d; k++) {
+            float p_rr = wr * x;
+            float p_ii = wi * y;
+            float p_ri = wr * y;
+            float p_ir = wi * x;
+            float nr = p_rr - p_ii;
+            float ni = p_ri + p_ir;
+            wr = nr;
+            wi = ni;
+        }
+        x = wr + cr;
+        y = wi + ci;
+        n = n + 1;
+    }
+    return n;
+}
+
+static int32_t count_ff_general(dw x, dw y, dw cr, dw ci, int32_t d, int32_t max_iter)
+{
+    int32_t n = 0;
+    while (n < max_iter) {
+        dw m = dw_add(dw_mul(x, x), dw_mul(y, y));
+        if (!dw_not_above_four(m))
+            break;
+        dw wr = x, wi = y;
+        for (int32_t k = 1; k < d; k++) {
+            dw p_rr = dw_mul(wr, x);
+            dw p_ii = dw_mul(wi, y);
+            dw p_ri = dw_mul(wr, y);
+            dw p_ir = dw_mul(wi, x);
+            dw nr = dw_add(p_rr, dw_neg(p_ii));
+            dw ni = dw_add(p_ri, p_ir);
+            wr = nr;
+            wi = ni;
+        }
+        x = dw_add(wr, cr);
+        y = dw_add(wi, ci);
+        n = n + 1;
+    }
+    return n;
+}
+
+int32_t jro_count_general(int32_t dtype, int32_t degree, double x0, double y0,
+                          double cr, double ci, int32_t max_iter)
+{
+    if (dtype == JRO_FP32)
+        return count_fp32_general((float)x0, (float)y0, (float)cr, (float)ci, degree,
+                                  max_iter);
+    if (dtype == JRO_FF)
+        return count_ff_general(dw_from_double(x0), dw_from_double(y0), dw_from_double(cr),
+                                dw_from_double(ci), degree, max_iter);
+    return count_fp64_general(x0, y0, cr, ci, degree, max_iter);
+}
+
+static int32_t pixel_count_general(int32_t dtype, int32_t mode, int32_t degree, double cr,
+                                   double ci, double re_min, double re_max, double im_min,
+                                   double im_max, int32_t W, int32_t H, int32_t max_iter,
+                                   int32_t i, int32_t j)
+{
+    double x, y;
+    jro_pixel_center(re_min, re_max, im_min, im_max, W, H, i, j, &x, &y);
+    if (mode == JRO_MANDELBROT)
+        return jro_count_general(dtype, degree, 0.0, 0.0, x, y, max_iter);
+    return jro_count_general(dtype, degree, x, y, cr, ci, max_iter);
+}
+
+void jro_render_general(int32_t dtype, int32_t mode, int32_t degree, double cr, double ci,
+                        double re_min, double re_max, double im_min, double im_max,
+                        int32_t W, int32_t H, int32_t max_iter, int32_t *out)
+{
+    for (int32_t j = 0; j < H; j++)
+        for (int32_t i = 0; i < W; i++)
+            out[(int64_t)j * W + i] = pixel_count_general(dtype, mode, degree, cr, ci, re_min,
+                                                          re_max, im_min, im_max, W, H,
+                                                          max_iter, i, j);
+}
+
+void jro_render_pixels_general(int32_t dtype, int32_t mode, int32_t degree, double cr,
+                               double ci, double re_min, double re_max, double im_min,
+                               double im_max, int32_t W, int32_t H, int32_t max_iter,
+                               int64_t n, const int32_t *ii, const int32_t *jj, int32_t *out)
+{
+    for (int64_t k = 0; k < n; k++)
+        out[k] = pixel_count_general(dtype, mode, degree, cr, ci, re_min, re_max, im_min,
+                                     im_max, W, H, max_iter, ii[k], jj[k]);
+}
+
+/* ------------------------------------------------------------------------ */
 /* One orbit in the chosen formulation.                                      */
 /* ------------------------------------------------------------------------ */
 int32_t jro_count(int32_t dtype, double x0, double y0, double cr, double ci,

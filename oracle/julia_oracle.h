@@ -70,6 +70,25 @@ void jro_pixel_center(double re_min, double re_max, double im_min, double im_max
 int32_t jro_count(int32_t dtype, double x0, double y0, double cr, double ci,
                   int32_t max_iter);
 
+/* General maps (the paper's further functions, Section 4 and its closing
+ * future work): Z_{n+1} = Z_n^d + C for an integer degree d in 2..8, the
+ * same count, escape test and pixel mapping.  Z^d is formed by d - 1 complex
+ * products W <- W * Z from W = Z, each product (a + ib)(x + iy) taken as
+ * (a*x - b*y) + i (a*y + b*x) with every operation rounded; then C is added.
+ * FP64 and FP32 use that order in their own precision (no fused operations;
+ * the test is fl(fl(x*x) + fl(y*y)) > 4); float-float uses the double-word
+ * product and sum for every operation.  For d = 2 the FP64 result equals
+ * jro_count's except where x*y is subnormal. */
+int32_t jro_count_general(int32_t dtype, int32_t degree, double x0, double y0,
+                          double cr, double ci, int32_t max_iter);
+void jro_render_general(int32_t dtype, int32_t mode, int32_t degree, double cr, double ci,
+                        double re_min, double re_max, double im_min, double im_max,
+                        int32_t W, int32_t H, int32_t max_iter, int32_t *out);
+void jro_render_pixels_general(int32_t dtype, int32_t mode, int32_t degree, double cr,
+                               double ci, double re_min, double re_max, double im_min,
+                               double im_max, int32_t W, int32_t H, int32_t max_iter,
+                               int64_t n, const int32_t *ii, const int32_t *jj, int32_t *out);
+
 /* Colour levels from counts (Section 2: each pixel is given a colour level by
  * its iteration count): out[k] = palette[min(counts[k], palette_len - 1)],
  * for counts >= 0 and palette_len >= 1. */

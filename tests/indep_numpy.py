@@ -165,6 +165,67 @@ def counts_ff(x0, y0, cr, ci, max_iter):
         return _iterate((x, y), step, esc, max_iter)
 
 
+# ------------------------------------------------------ general maps Z^d + C
+def _power_add(x, y, d, mul, sub, add, cr, ci):
+    """Z^d by d - 1 products W <- W Z from W = Z, then + C."""
+    wr, wi = x, y
+    for _ in range(d - 1):
+        nr = sub(mul(wr, x), mul(wi, y))
+        ni = add(mul(wr, y), mul(wi, x))
+        wr, wi = nr, ni
+    return add(wr, cr), add(wi, ci)
+
+
+def counts_general(x0, y0, cr, ci, max_iter, degree, dtype):
+    if dtype == "ff":
+        shape = np.shape(x0)
+        x, y = split(x0), split(y0)
+        crs = tuple(np.broadcast_to(a, shape) for a in split(cr))
+        cis = tuple(np.broadcast_to(a, shape) for a in split(ci))
+        neg = lambda a: (-a[0], -a[1])
+
+        def esc(s):
+            xx, yy = s
+            m = dw_add(dw_mul(xx, xx), dw_mul(yy, yy))
+            return ~((m[0] < 4) | ((m[0] == 4) & (m[1] <= 0)))
+
+        def step(s, act):
+            xx, yy = s
+            xn, yn = _power_add(xx, yy, degree, dw_mul, lambda a, b: dw_add(a, neg(b)), dw_add,
+                                crs, cis)
+            pick = lambda new, old: (np.where(act, new[0], old[0]), np.where(act, new[1], old[1]))
+            return (pick(xn, xx), pick(yn, yy))
+
+        with np.errstate(over="ignore", invalid="ignore"):
+            return _iterate((x, y), step, esc, max_iter)
+    T = F32 if dtype == "fp32" else F64
+    x0 = np.asarray(x0, F64).astype(T)
+    y0 = np.asarray(y0, F64).astype(T)
+    cr = np.broadcast_to(np.asarray(cr, F64).astype(T), x0.shape)
+    ci = np.broadcast_to(np.asarray(ci, F64).astype(T), x0.shape)
+
+    def esc(s):
+        x, y = s
+        return (x * x + y * y) > T(4.0)
+
+    def step(s, act):
+        x, y = s
+        xn, yn = _power_add(x, y, degree, np.multiply, np.subtract, np.add, cr, ci)
+        return (np.where(act, xn, x), np.where(act, yn, y))
+
+    with np.errstate(over="ignore", invalid="ignore"):
+        return _iterate((x0, y0), step, esc, max_iter)
+
+
+def render_general(c, window, W, H, max_iter, dtype="fp64", mode="julia", degree=3):
+    x, y = pixel_grid(window, W, H)
+    c = complex(c)
+    if mode == "mandelbrot":
+        z = np.zeros_like(x)
+        return counts_general(z, z, x, y, max_iter, degree, dtype)
+    return counts_general(x, y, c.real, c.imag, max_iter, degree, dtype)
+
+
 COUNTS = {"fp64": counts_fp64, "fp32": counts_fp32, "ff": counts_ff}
 
 

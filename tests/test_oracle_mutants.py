@@ -18,7 +18,10 @@ from oracle import build_oracle
 SRC = os.path.join(os.path.dirname(oracle.__file__), "julia_oracle.c")
 
 MUTANTS = {
-    "non_strict_escape": ("if (m > 4.0)", "if (m >= 4.0)"),
+    "non_strict_escape": ("if (m > 4.0)\n            break;\n        double re",
+                          "if (m >= 4.0)\n            break;\n        double re"),
+    "general_non_strict": ("if (m > 4.0)\n            break;\n        double wr",
+                           "if (m >= 4.0)\n            break;\n        double wr"),
     "minus_cr": ("double xn = re + cr;", "double xn = re - cr;"),
     "plus_y2": ("double re = x2 - y2;", "double re = x2 + y2;"),
     "dropped_two": ("double tx = 2.0 * x;", "double tx = x;"),
@@ -28,8 +31,12 @@ MUTANTS = {
                      "double oi = (double)(2 * (int64_t)i - W);"),
     "hx_off_by_one": ("double hx = (re_max - re_min) / (2.0 * (double)W);",
                       "double hx = (re_max - re_min) / (2.0 * (double)W - 2.0);"),
-    "cap_plus_one": ("    while (n < max_iter) {\n        double x2",
-                     "    while (n <= max_iter) {\n        double x2"),
+    "cap_plus_one": ("    while (n < max_iter) {\n        double x2 = x * x;\n        double y2 = y * y;\n"
+                     "        double m = x2 + y2;\n        if (m > 4.0)\n            break;\n"
+                     "        double re",
+                     "    while (n <= max_iter) {\n        double x2 = x * x;\n        double y2 = y * y;\n"
+                     "        double m = x2 + y2;\n        if (m > 4.0)\n            break;\n"
+                     "        double re"),
     "fp32_unfused_norm": ("float m = fmaf(y, y, t);", "float m = y * y + t;"),
     "fp32_unshifted_limit": ("const float lim = 4.0f + cr;", "const float lim = 4.0f;"),
     "fp32_sign": ("float xn = fmaf(-y, y, t);", "float xn = fmaf(y, y, t);"),
@@ -40,6 +47,12 @@ MUTANTS = {
     "colour_level_shift": ("out[k] = palette[level];",
                            "out[k] = palette[level > 0 ? level - 1 : 0];"),
     "colour_clamp_to_first": ("            level = palette_len - 1;", "            level = 0;"),
+    "general_sign": ("double nr = p_rr - p_ii;", "double nr = p_rr + p_ii;"),
+    "general_cross": ("double ni = p_ri + p_ir;", "double ni = p_ri - p_ir;"),
+    "general_degree": ("for (int32_t k = 1; k < d; k++) {\n            double p_rr",
+                       "for (int32_t k = 2; k < d; k++) {\n            double p_rr"),
+    "general_fp32_sign": ("float nr = p_rr - p_ii;", "float nr = p_rr + p_ii;"),
+    "general_ff_cross": ("dw p_ir = dw_mul(wi, x);", "dw p_ir = dw_mul(wi, y);"),
     "mandel_z0_is_c": ("return jro_count(dtype, 0.0, 0.0, x, y, max_iter);",
                        "return jro_count(dtype, x, y, x, y, max_iter);"),
 }
@@ -58,6 +71,14 @@ def _battery():
                ("cap01_fp64", pins.test_cap_zero_and_one, ("fp64",)),
                ("eft", pins.test_error_free_transforms, ()),
                ("colour_table", pins.test_colorize_literal_table, ()),
+               ("general_orbits_fp64", pins.test_general_exact_small_orbits, ("fp64",)),
+               ("general_orbits_fp32", pins.test_general_exact_small_orbits, ("fp32",)),
+               ("general_orbits_ff", pins.test_general_exact_small_orbits, ("ff",)),
+               ("general_quadratic", pins.test_general_degree_two_is_the_quadratic_map_fp64, ()),
+               ("general_numpy_fp32_3", pins.test_general_matches_numpy_reimplementation,
+                ("fp32", 3)),
+               ("general_numpy_ff_3", pins.test_general_matches_numpy_reimplementation,
+                ("ff", 3)),
                ("dw_bounds", pins.test_double_word_error_bounds, ())]
     for name, fn, args in checks:
         try:

@@ -486,3 +486,131 @@ def test_colorize_two_levels_mark_the_bounded_set():
             assert abs(mu) < 0.95
     m = oracle.colorize(oracle.render(0j, mwin, 41, 33, cap, "fp64", "mandelbrot"), pal)
     assert (m == 0xFFFFFFFF).all()
+
+
+# ------------------------------------------- general maps Z^d + C (Section 4)
+# Orbits of small integers and units: every value is exact in every
+# precision, so the counts are those of exact arithmetic.
+GENERAL_ORBITS = [
+    # degree, Z_0, C, count (cap 100)
+    (3, 0, 1, 3),        # 0, 1, 2 (|2|^2 = 4 is not > 4), 9
+    (3, 0, -1, 3),       # 0, -1, -2, -9
+    (4, 0, 1j, 3),       # 0, i, 1 + i, -4 + i
+    (3, 2, 0, 1),        # 2 is not escaped, 8 is
+    (3, 0, -2, 2),       # 0, -2, -10
+    (5, 0, 2, 2),        # 0, 2, 34
+    (3, 3, 0, 0),
+    (4, 0, -1, 100),     # 0, -1, 0, -1, ...
+    (3, 1j, 0, 100),     # i, -i, i, ...
+    (6, -1, 0, 100),     # -1, 1, 1, ...
+    (8, 0, 0, 100),
+]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_general_exact_small_orbits(dtype):
+    for d, z0, c, want in GENERAL_ORBITS:
+        assert oracle.count(z0, c, 100, dtype, degree=d) == want, (d, z0, c)
+        assert oracle.count(z0, c, 1, dtype, degree=d) == min(want, 1)
+        assert oracle.count(z0, c, 0, dtype, degree=d) == 0
+
+
+def test_general_degree_two_is_the_quadratic_map_fp64():
+    """(a + ib)^2 by the general product is (a a - b b) + i (a b + b a), and
+    a b + b a = 2 fl(a b) = fl((2a) b) when a b is normal: the general FP64
+    formulation at d = 2 gives the quadratic FP64 counts bit for bit."""
+    for c, win, mode in ((C1, (-1.5, 1.5, -1.5, 1.5), "julia"),
+                         (complex(0.285, 0.01), (-1.2, 1.2, -0.9, 0.9), "julia"),
+                         (0j, (-2.0, 0.6, -1.1, 1.1), "mandelbrot")):
+        a = oracle.render_general(c, win, 64, 48, 300, "fp64", mode, 2)
+        b = oracle.render(c, win, 64, 48, 300, "fp64", mode)
+        np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("degree", [2, 3, 4, 5, 8])
+def test_general_matches_numpy_reimplementation(dtype, degree):
+    for c, win, mode in ((complex(0.4, 0.3), (-1.3, 1.3, -1.2, 1.2), "julia"),
+                         (0j, (-1.5, 1.5, -1.5, 1.5), "mandelbrot")):
+        a = oracle.render(c, win, 37, 29, 60, dtype, mode, degree) if degree > 2 else \
+            oracle.render_general(c, win, 37, 29, 60, dtype, mode, degree)
+        b = ind.render_general(c, win, 37, 29, 60, dtype, mode, degree)
+        np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("dtype,tol", [("fp64", 1e-12), ("fp32", 1e-4), ("ff", 1e-10)])
+@pytest.mark.parametrize("degree", [3, 4])
+def test_general_closed_form_c_zero(dtype, tol, degree):
+    """C = 0: Z_n = Z_0^(d^n), so the count is the cap when |Z_0| <= 1 and
+    otherwise the first n with |Z_0|^(2 d^n) > 4."""
+    W = H = 48
+    win = (-1.9, 1.9, -1.9, 1.9)
+    cap = 30
+    a = oracle.render(0j, win, W, H, cap, dtype, "julia", degree)
+    checked = 0
+    for j in range(H):
+        for i in range(W):
+            x, y = oracle.pixel_center(win, W, H, i, j)
+            r = abs(complex(x, y))
+            if abs(r - 1.0) < 1e-2:
+                continue
+            if r <= 1.0:
+                want = cap
+            else:
+                L = math.log2(r)
+                n = 0
+                while (degree ** n) * L <= 1.0:  # |Z_n| = r^(d^n) <= 2
+                    n += 1
+                if any(abs(degree ** k * L - 1.0) < degree ** k * tol for k in (n - 1, n) if k >= 0):
+                    continue
+                want = min(n, cap)
+            assert a[j, i] == want, (dtype, degree, i, j, r, a[j, i], want)
+            checked += 1
+    assert checked > 0.9 * W * H
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_general_symmetries(dtype):
+    """Conjugating C mirrors the image top to bottom (every operation is
+    sign-symmetric); for even d, (-Z)^d = Z^d bit for bit, so the centred
+    image is its own 180-degree rotation."""
+    W, H, cap = 60, 44, 80
+    win = (-1.4, 1.4, -1.1, 1.1)
+    c = complex(-0.35, 0.52)
+    for d in (3, 5):
+        a = oracle.render(c, win, W, H, cap, dtype, "julia", d)
+        b = oracle.render(c.conjugate(), win, W, H, cap, dtype, "julia", d)
+        np.testing.assert_array_equal(b, a[::-1, :])
+    for d in (4, 6):
+        a = oracle.render(c, win, W, H, cap, dtype, "julia", d)
+        np.testing.assert_array_equal(a, a[::-1, ::-1])
+
+
+def test_general_exact_rational_counts_small_cap():
+    """Brute force in exact rationals: Z^3 + C on an 8 x 8 grid with cap 5.
+    The FP64 count must agree wherever no exact |Z_n|^2 lies within 1e-9 of 4."""
+    win = (-1.3, 1.3, -1.3, 1.3)
+    cr, ci = Fraction(-1, 5), Fraction(3, 10)
+    cap, d = 5, 3
+    got = oracle.render(complex(float(cr), float(ci)), win, 8, 8, cap, "fp64", "julia", d)
+    compared = 0
+    for j in range(8):
+        for i in range(8):
+            x0, y0 = oracle.pixel_center(win, 8, 8, i, j)
+            x, y = Fraction(x0), Fraction(y0)
+            n, close = 0, False
+            while n < cap:
+                m = x * x + y * y
+                if abs(m - 4) < Fraction(1, 10 ** 9):
+                    close = True
+                if m > 4:
+                    break
+                wr, wi = x, y
+                for _ in range(d - 1):
+                    wr, wi = wr * x - wi * y, wr * y + wi * x
+                x, y = wr + cr, wi + ci
+                n += 1
+            if not close:
+                assert got[j, i] == n, (i, j, got[j, i], n)
+                compared += 1
+    assert compared >= 60
