@@ -77,6 +77,15 @@ typedef struct { double re_min, re_max, im_min, im_max; } jr_window;
  * Mandelbrot mode.  Limits: width, height >= 1, width*height < 2^31,
  * 0 <= max_iter < 2^31, out_offset >= 0, out_offset + width*height <=
  * out_capacity.
+ *
+ * degree selects the map (the paper's further functions, Section 4):
+ * 0 or 2 is Z^2 + C; 3..8 is the general map Z^degree + C, with Z^degree
+ * formed by degree - 1 complex products W <- W Z from W = Z, each product
+ * (a + ib)(x + iy) taken as (a x - b y) + i (a y + b x) and every operation
+ * rounded, then C added.  Its FP64 and FP32 forms use no fused operations
+ * and test fl(fl(x x) + fl(y y)) > 4; float-float uses its double-word
+ * operations throughout.  Count, escape radius and pixel mapping are those
+ * of Z^2 + C.
  */
 typedef struct {
     jr_complex c;
@@ -87,7 +96,7 @@ typedef struct {
     int32_t mode;       /* jr_mode  */
     int32_t row_begin;  /* first row computed (0 = top)        */
     int32_t row_end;    /* one past the last row; 0 = height   */
-    int32_t reserved;   /* must be 0                           */
+    int32_t degree;     /* 0 or 2: Z^2 + C; 3..8: Z^degree + C */
     int64_t out_offset; /* element offset of pixel (0, 0)      */
 } jr_frame;
 

@@ -44,7 +44,7 @@ class jr_frame(ctypes.Structure):
                 ("width", ctypes.c_int32), ("height", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("mode", ctypes.c_int32), ("row_begin", ctypes.c_int32),
-                ("row_end", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("row_end", ctypes.c_int32), ("degree", ctypes.c_int32),
                 ("out_offset", ctypes.c_int64)]
 
 
@@ -238,7 +238,7 @@ _TUNED_MEMO = {}
 
 def render(c, window, width: int, height: int, max_iter: int, dtype: str = "fp64",
            out=None, stream=None, mode: str = "julia", plain: bool = False,
-           schedule: Optional["Schedule"] = None, palette=None):
+           schedule: Optional["Schedule"] = None, palette=None, degree: int = 2):
     """Counts of one image as an int32 (height, width) CUDA tensor (row 0 = im_max).
 
     ``plain=True`` uses the one-thread-per-pixel comparator kernel.  Otherwise
@@ -247,24 +247,34 @@ def render(c, window, width: int, height: int, max_iter: int, dtype: str = "fp64
 
     With ``palette`` (see _palette_ptr) each pixel holds the 32 bits of
     palette[min(count, len - 1)] instead of its count, stored by the kernel
-    itself (julia_render_batch_colored).
+    itself (julia_render_batch_colored).  ``degree`` 3..8 iterates the
+    general map Z^degree + C (through julia_render_batch).
     """
     out = _out_tensor(out, (height, width))
     st = _stream_ptr(stream)
     dt = DTYPES[dtype]
+    if degree != 2 and palette is None:
+        if plain:
+            schedule = Schedule(kernel="plain")
+        f = _OneFrame(c, window, width, height, max_iter, dtype, mode, degree)
+        sched = ctypes.byref(schedule.to_c()) if schedule is not None else None
+        _check(lib.julia_render_batch(_frames_array([f], [0]), 1, ctypes.c_void_p(out.data_ptr()),
+                                      width * height, sched, st))
+        return out.view(-1)[: width * height].view(height, width)
     if palette is not None:
         pp, plen = _palette_ptr(palette)
         if plain:
             schedule = Schedule(kernel="plain")
         elif schedule is None:
             schedule = tuned_schedule(dtype, max_iter, width * height)
-        if schedule is None and mode == "julia":
+        if schedule is None and mode == "julia" and degree == 2:
             c = complex(c)
             _check(lib.julia_render_colored(jr_complex(c.real, c.imag), _window(window), width,
                                             height, max_iter, dt, pp, plen,
                                             ctypes.c_void_p(out.data_ptr()), st))
         else:
-            arr = _frames_array([_OneFrame(c, window, width, height, max_iter, dtype, mode)], [0])
+            arr = _frames_array([_OneFrame(c, window, width, height, max_iter, dtype, mode,
+                                           degree)], [0])
             sched = ctypes.byref(schedule.to_c()) if schedule is not None else None
             _check(lib.julia_render_batch_colored(arr, 1, pp, plen,
                                                   ctypes.c_void_p(out.data_ptr()),
@@ -304,6 +314,7 @@ class _OneFrame:
     max_iter: int
     dtype: str
     mode: str
+    degree: int = 2
 
 
 def _frames_array(frames, offsets, rows=None):
@@ -313,7 +324,7 @@ def _frames_array(frames, offsets, rows=None):
         rb, re_ = (0, 0) if rows is None else rows[k]
         arr[k] = jr_frame(jr_complex(c.real, c.imag), _window(f.window), f.width, f.height,
                           f.max_iter, DTYPES[f.dtype], MODES[getattr(f, "mode", "julia")],
-                          rb, re_, 0, int(offsets[k]))
+                          rb, re_, int(getattr(f, "degree", 2)), int(offsets[k]))
     return arr
 
 

@@ -26,7 +26,7 @@ struct alignas(16) DevFrame {
     int32_t row_begin, row_end;
     int32_t tiles_x;         // tiles per tile row of this frame
     int32_t tile_w, tile_h;
-    int32_t pad;
+    int32_t degree;          // map Z^degree + C (2: the quadratic map)
 };
 static_assert(sizeof(DevFrame) == 112, "DevFrame layout");
 
@@ -69,6 +69,8 @@ constexpr int kRowsWide = 4;
 // Kernel variants that store colours carry this bit beside the dtype bits
 // (compile-time, so the counting kernels hold no colour code).
 constexpr int kColorBit = 8;
+// Kernel variants that also hold the general maps Z^d + C (d = 3..8).
+constexpr int kGeneralBit = 16;
 
 struct PlainArgs {
     int32_t* out;

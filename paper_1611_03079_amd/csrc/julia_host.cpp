@@ -58,6 +58,7 @@ int hip_fail(hipError_t e, const char* what) {
 // > 4 - 1.9 > 2, with a margin far above rounding in every formulation.
 constexpr double kAbsorbingC = 1.9;
 constexpr int32_t kMaxFrames = 1 << 22;
+constexpr int32_t kMaxDegree = 8;
 
 // ------------------------------------------------------------- validation
 bool finite(double v) { return std::isfinite(v); }
@@ -138,7 +139,8 @@ int check_frames(const jr_frame* frames, int32_t n, int64_t capacity) {
         const int32_t rend = f.row_end == 0 ? f.height : f.row_end;
         if (f.row_begin < 0 || rend > f.height || f.row_begin >= rend)
             return fail(JR_EINVAL, "%s: rows [%d, %d) outside [0, %d)", who, f.row_begin, rend, f.height);
-        if (f.reserved != 0) return fail(JR_EINVAL, "%s: reserved must be 0", who);
+        if (f.degree != 0 && (f.degree < 2 || f.degree > kMaxDegree))
+            return fail(JR_EINVAL, "%s: degree %d not 0 or 2..%d", who, f.degree, kMaxDegree);
         if (f.out_offset < 0) return fail(JR_EINVAL, "%s: out_offset must be >= 0", who);
         const int64_t px = (int64_t)f.width * f.height;
         if (f.out_offset > capacity - px)
@@ -174,7 +176,9 @@ double dtype_cost(int dtype) {
 double frame_cost(const jr_frame& f) {
     const int32_t rend = f.row_end == 0 ? f.height : f.row_end;
     const double px = (double)f.width * (double)(rend - f.row_begin);
-    return px * (4.0 + std::min<double>(f.max_iter, 256.0)) * dtype_cost(f.dtype);
+    // a general map's iteration costs about degree - 1 complex products
+    const double deg = f.degree > 2 ? (double)(f.degree - 1) : 1.0;
+    return px * (4.0 + std::min<double>(f.max_iter, 256.0)) * dtype_cost(f.dtype) * deg;
 }
 
 bool absorbing(const jr_frame& f) {
@@ -259,6 +263,7 @@ void build_table(const jr_frame* frames, int32_t n, const jr_schedule& s, Table&
         d.dtype = f.dtype;
         d.mode = f.mode;
         d.defer = absorbing(f) ? 1 : 0;
+        d.degree = f.degree == 0 ? 2 : f.degree;
         d.row_begin = f.row_begin;
         d.row_end = f.row_end == 0 ? f.height : f.row_end;
         const int32_t tw = s.kernel == JR_KERNEL_PLAIN ? 16 : s.tile_w;
@@ -273,6 +278,7 @@ void build_table(const jr_frame* frames, int32_t n, const jr_schedule& s, Table&
         t.total_cost += frame_cost(f);
         t.max_tile_cost = std::max(t.max_tile_cost, tile_cost);
         t.dtmask |= 1 << f.dtype;
+        if (d.degree > 2) t.dtmask |= jr::kGeneralBit;
     }
 }
 

@@ -53,7 +53,7 @@ struct ArF64 {
     __device__ static V shfl(V v, int src) { return __shfl(v, src); }
     __device__ static Z make(V x, V y) { return Z{x, y}; }
     __device__ static C cmake(V r, V i) { return C{r, i}; }
-    __device__ static bool inside(const Z& z, const C&) {
+    __device__ static bool inside(const Z& z, const C&, int) {
         double x2 = z.x * z.x;
         double y2 = z.y * z.y;
         return x2 + y2 <= 4.0;
@@ -67,12 +67,12 @@ struct ArF64 {
         z.x = xn;
         z.y = yn;
     }
-    __device__ static void step(Z& z, const C& c) {
+    __device__ static void step(Z& z, const C& c, int) {
         double x2 = z.x * z.x;
         double y2 = z.y * z.y;
         advance(z, c, x2, y2);
     }
-    __device__ static bool check_step(Z& z, const C& c) {
+    __device__ static bool check_step(Z& z, const C& c, int) {
         double x2 = z.x * z.x;
         double y2 = z.y * z.y;
         bool ok = (x2 + y2 <= 4.0);
@@ -93,7 +93,7 @@ struct ArF32 {
     __device__ static V shfl(V v, int src) { return __shfl(v, src); }
     __device__ static Z make(V x, V y) { return Z{x, y}; }
     __device__ static C cmake(V r, V i) { return C{r, i, 4.0f + r}; }
-    __device__ static bool inside(const Z& z, const C& c) {
+    __device__ static bool inside(const Z& z, const C& c, int) {
         float t = __builtin_fmaf(z.x, z.x, c.r);
         return __builtin_fmaf(z.y, z.y, t) <= c.lim;
     }
@@ -104,10 +104,10 @@ struct ArF32 {
         z.x = xn;
         z.y = yn;
     }
-    __device__ static void step(Z& z, const C& c) {
+    __device__ static void step(Z& z, const C& c, int) {
         advance(z, c, __builtin_fmaf(z.x, z.x, c.r));
     }
-    __device__ static bool check_step(Z& z, const C& c) {
+    __device__ static bool check_step(Z& z, const C& c, int) {
         float t = __builtin_fmaf(z.x, z.x, c.r);
         bool ok = __builtin_fmaf(z.y, z.y, t) <= c.lim;
         advance(z, c, t);
@@ -169,7 +169,7 @@ struct ArFF {
     __device__ static Z make(V x, V y) { return Z{x, y}; }
     __device__ static C cmake(V r, V i) { return C{r, i}; }
     __device__ static bool le4(D m) { return (m.hi < 4.0f) || (m.hi == 4.0f && m.lo <= 0.0f); }
-    __device__ static bool inside(const Z& z, const C&) {
+    __device__ static bool inside(const Z& z, const C&, int) {
         return le4(add(mul(z.x, z.x), mul(z.y, z.y)));
     }
     __device__ static void advance(Z& z, const C& c, D x2, D y2) {
@@ -182,16 +182,104 @@ struct ArFF {
         z.x = xn;
         z.y = yn;
     }
-    __device__ static void step(Z& z, const C& c) {
+    __device__ static void step(Z& z, const C& c, int) {
         D x2 = mul(z.x, z.x);
         D y2 = mul(z.y, z.y);
         advance(z, c, x2, y2);
     }
-    __device__ static bool check_step(Z& z, const C& c) {
+    __device__ static bool check_step(Z& z, const C& c, int) {
         D x2 = mul(z.x, z.x);
         D y2 = mul(z.y, z.y);
         bool ok = le4(add(x2, y2));
         advance(z, c, x2, y2);
+        return ok;
+    }
+};
+
+// General maps Z^d + C (d = 2..8; the paper's further functions).  Z^d comes
+// from d - 1 complex products W <- W Z starting at W = Z, each
+// (a + ib)(x + iy) taken as (a x - b y) + i (a y + b x) with every operation
+// rounded, then C is added.  FP64 and FP32 round each operation in their own
+// precision (no fused operations; escape test fl(fl(x x) + fl(y y)) > 4);
+// float-float uses the double-word product and sum throughout.  The degree is
+// the same for every lane of a wave (it is part of the stream variant), so the
+// product loop does not diverge.
+struct ArF64G : ArF64 {
+    __device__ static void power_add(Z& z, const C& c, int d) {
+        double wr = z.x, wi = z.y;
+#pragma unroll 1
+        for (int k = 1; k < d; ++k) {
+            double p_rr = wr * z.x;
+            double p_ii = wi * z.y;
+            double p_ri = wr * z.y;
+            double p_ir = wi * z.x;
+            double nr = p_rr - p_ii;
+            double ni = p_ri + p_ir;
+            wr = nr;
+            wi = ni;
+        }
+        z.x = wr + c.r;
+        z.y = wi + c.i;
+    }
+    __device__ static void step(Z& z, const C& c, int d) { power_add(z, c, d); }
+    __device__ static bool check_step(Z& z, const C& c, int d) {
+        bool ok = inside(z, c, d);
+        power_add(z, c, d);
+        return ok;
+    }
+};
+
+struct ArF32G : ArF32 {
+    __device__ static bool inside(const Z& z, const C&, int) {
+        float x2 = z.x * z.x;
+        float y2 = z.y * z.y;
+        return x2 + y2 <= 4.0f;
+    }
+    __device__ static void power_add(Z& z, const C& c, int d) {
+        float wr = z.x, wi = z.y;
+#pragma unroll 1
+        for (int k = 1; k < d; ++k) {
+            float p_rr = wr * z.x;
+            float p_ii = wi * z.y;
+            float p_ri = wr * z.y;
+            float p_ir = wi * z.x;
+            float nr = p_rr - p_ii;
+            float ni = p_ri + p_ir;
+            wr = nr;
+            wi = ni;
+        }
+        z.x = wr + c.r;
+        z.y = wi + c.i;
+    }
+    __device__ static void step(Z& z, const C& c, int d) { power_add(z, c, d); }
+    __device__ static bool check_step(Z& z, const C& c, int d) {
+        bool ok = inside(z, c, d);
+        power_add(z, c, d);
+        return ok;
+    }
+};
+
+struct ArFFG : ArFF {
+    __device__ static void power_add(Z& z, const C& c, int d) {
+        D wr = z.x, wi = z.y;
+#pragma unroll 1
+        for (int k = 1; k < d; ++k) {
+            D p_rr = mul(wr, z.x);
+            D p_ii = mul(wi, z.y);
+            D p_ri = mul(wr, z.y);
+            D p_ir = mul(wi, z.x);
+            D nr = add(p_rr, D{-p_ii.hi, -p_ii.lo});
+            D ni = add(p_ri, p_ir);
+            wr = nr;
+            wi = ni;
+        }
+        z.x = add(wr, c.r);
+        z.y = add(wi, c.i);
+    }
+    __device__ static void step(Z& z, const C& c, int d) { power_add(z, c, d); }
+    __device__ static bool check_step(Z& z, const C& c, int d) {
+        bool ok = inside(z, c, d);
+        power_add(z, c, d);
         return ok;
     }
 };
@@ -255,9 +343,10 @@ __global__ __launch_bounds__(256) void jr_plain(PlainArgs p) {
             z = A::make(A::coord(px), A::coord(py));
             c = A::cmake(A::coord(p.cr), A::coord(p.ci));
         }
+        constexpr int deg = 2;
         int n = 0;
         while (n < p.max_iter) {
-            if (!A::check_step(z, c)) break;
+            if (!A::check_step(z, c, deg)) break;
             n++;
         }
         p.out[(int64_t)j * p.W + i] = n;
@@ -402,9 +491,12 @@ struct Src {
 
 // Which stream variant a frame needs: its dtype, and whether the blocked test
 // may be used (escape absorbing, |C| <= 1.9) or every iteration is tested.
-__device__ __forceinline__ int variant_of(int dtype, int absorbing) {
-    return dtype * 2 + (absorbing ? 1 : 0);
+__device__ __forceinline__ int variant_of(int dtype, int absorbing, int degree) {
+    return ((degree - 2) * 3 + dtype) * 2 + (absorbing ? 1 : 0);
 }
+
+// The map's degree of a stream variant.
+__device__ __forceinline__ int degree_of(int variant) { return variant / 6 + 2; }
 
 // Makes tile t the refill source.  Lane L receives the binary64 coordinate of
 // the tile's column L (xd) and row L (yd), and every lane the frame's C.
@@ -421,7 +513,7 @@ __device__ __forceinline__ void load_src(Src& s, const PersistentArgs& a, int64_
     const int col0 = tx * F.tile_w;
     const int row0 = F.row_begin + ty * F.tile_h;
     const int th = min(F.tile_h, F.row_end - row0);
-    s.variant = variant_of(F.dtype, F.defer);
+    s.variant = variant_of(F.dtype, F.defer, F.degree);
     s.W = F.width;
     s.max_iter = F.max_iter;
     s.mode = F.mode;
@@ -463,6 +555,7 @@ __device__ void run_stream(Src& s, Claimer& cl, const PersistentArgs& a, double&
                            double& crd, double& cid) {
     using V = typename A::V;
     const int my_variant = s.variant;
+    const int deg = degree_of(my_variant);
     const V zero = A::coord(0.0);
     V xcol = A::coord(xd), yrow = A::coord(yd);
     V cre = A::coord(crd), cim = A::coord(cid);
@@ -484,7 +577,7 @@ __device__ void run_stream(Src& s, Claimer& cl, const PersistentArgs& a, double&
                 typename A::Z zr = zs;
                 int lead = 0;
 #pragma unroll
-                for (int u = 0; u < K; ++u) lead += A::check_step(zr, c) ? 1 : 0;
+                for (int u = 0; u < K; ++u) lead += A::check_step(zr, c, deg) ? 1 : 0;
                 if (pe) {
                     cnt = min(n + lead, mi);
                     fi = true;
@@ -536,8 +629,8 @@ __device__ void run_stream(Src& s, Claimer& cl, const PersistentArgs& a, double&
         if (DEFER) {
             zs = pe ? zs : z;  // a lane waiting for its replay keeps its block start
 #pragma unroll
-            for (int u = 0; u < K; ++u) A::step(z, c);
-            const bool esc = !A::inside(z, c);
+            for (int u = 0; u < K; ++u) A::step(z, c, deg);
+            const bool esc = !A::inside(z, c, deg);
             const bool capped = n + K >= mi;  // no escape up to n + K >= cap: absorbing
             cnt = (it && !esc && capped) ? mi : cnt;
             fi = fi || (it && !esc && capped);
@@ -548,7 +641,7 @@ __device__ void run_stream(Src& s, Claimer& cl, const PersistentArgs& a, double&
         } else {
             int lead = 0;
 #pragma unroll
-            for (int u = 0; u < K; ++u) lead += A::check_step(z, c) ? 1 : 0;
+            for (int u = 0; u < K; ++u) lead += A::check_step(z, c, deg) ? 1 : 0;
             const bool stop = (lead < K) || (n + K >= mi);
             const int final_cnt = min(n + lead, mi);
             cnt = (it && stop) ? final_cnt : cnt;
@@ -609,6 +702,7 @@ __device__ void run_hybrid(Src& s, Claimer& cl, const PersistentArgs& a, double&
                            double& crd, double& cid, uint32_t* q) {
     using V = typename A::V;
     const int my_variant = s.variant;
+    const int deg = degree_of(my_variant);
     const V zero = A::coord(0.0);
     V xcol = A::coord(xd), yrow = A::coord(yd);
     V cre = A::coord(crd), cim = A::coord(cid);
@@ -662,7 +756,7 @@ __device__ void run_hybrid(Src& s, Claimer& cl, const PersistentArgs& a, double&
             }
             // the exact test on every iteration, until every lane is done
             for (int u = 0; u < a.bail; ++u) {
-                const bool ok = A::check_step(z, c);
+                const bool ok = A::check_step(z, c, deg);
                 const bool stop = it && (!ok || n >= mi);
                 cnt = stop ? n : cnt;
                 fi = fi || stop;
@@ -695,7 +789,7 @@ __device__ void run_hybrid(Src& s, Claimer& cl, const PersistentArgs& a, double&
                     typename A::Z zr = zs;
                     int lead = 0;
 #pragma unroll
-                    for (int u = 0; u < K; ++u) lead += A::check_step(zr, c) ? 1 : 0;
+                    for (int u = 0; u < K; ++u) lead += A::check_step(zr, c, deg) ? 1 : 0;
                     if (pe) {
                         cnt = min(n + lead, mi);
                         fi = true;
@@ -739,8 +833,8 @@ __device__ void run_hybrid(Src& s, Claimer& cl, const PersistentArgs& a, double&
             if (DEFER) {
                 zs = pe ? zs : z;
 #pragma unroll
-                for (int u = 0; u < K; ++u) A::step(z, c);
-                const bool esc = !A::inside(z, c);
+                for (int u = 0; u < K; ++u) A::step(z, c, deg);
+                const bool esc = !A::inside(z, c, deg);
                 const bool capped = n + K >= mi;
                 cnt = (it && !esc && capped) ? mi : cnt;
                 fi = fi || (it && !esc && capped);
@@ -751,7 +845,7 @@ __device__ void run_hybrid(Src& s, Claimer& cl, const PersistentArgs& a, double&
             } else {
                 int lead = 0;
 #pragma unroll
-                for (int u = 0; u < K; ++u) lead += A::check_step(z, c) ? 1 : 0;
+                for (int u = 0; u < K; ++u) lead += A::check_step(z, c, deg) ? 1 : 0;
                 const bool stop = (lead < K) || (n + K >= mi);
                 const int final_cnt = min(n + lead, mi);
                 cnt = (it && stop) ? final_cnt : cnt;
@@ -770,6 +864,7 @@ __device__ void run_hybrid(Src& s, Claimer& cl, const PersistentArgs& a, double&
 template <int K, int DEFER, int DTMASK, int HYB>
 __global__ __launch_bounds__(256) void jr_tiled(PersistentArgs a) {
     constexpr int COLOR = (DTMASK & kColorBit) ? 1 : 0;
+    constexpr bool GENERAL = (DTMASK & kGeneralBit) != 0;
     // per-wave survivor queues of the hybrid stream (unused otherwise)
     __shared__ uint32_t qmem[HYB ? 4 * kQWordsMax * kQ : 1];
     uint32_t* q = qmem + (HYB ? (threadIdx.x >> 6) * kQWordsMax * kQ : 0);
@@ -788,18 +883,32 @@ __global__ __launch_bounds__(256) void jr_tiled(PersistentArgs a) {
             run_stream<A_, K_, D_, COLOR>(s, cl, a, xd, yd, cr, ci); \
     } while (0)
     while (s.t >= 0) {
-        const int v = s.variant;
-        if ((DTMASK & (1 << kFP32)) && v == variant_of(kFP32, 1))
+        const int v = s.variant % 6;  // dtype * 2 + absorbing
+        const bool general = s.variant >= 6;
+        if (GENERAL && general) {
+            if (v == kFP32 * 2 + 1)
+                JR_STREAM(ArF32G, K, DEFER);
+            else if (v == kFP32 * 2)
+                JR_STREAM(ArF32G, 1, 0);
+            else if (v == kFP64 * 2 + 1)
+                JR_STREAM(ArF64G, K, DEFER);
+            else if (v == kFP64 * 2)
+                JR_STREAM(ArF64G, 1, 0);
+            else if (v == kFF * 2 + 1)
+                JR_STREAM(ArFFG, K, DEFER);
+            else
+                JR_STREAM(ArFFG, 1, 0);
+        } else if ((DTMASK & (1 << kFP32)) && v == kFP32 * 2 + 1)
             JR_STREAM(ArF32, K, DEFER);
-        else if ((DTMASK & (1 << kFP32)) && v == variant_of(kFP32, 0))
+        else if ((DTMASK & (1 << kFP32)) && v == kFP32 * 2)
             JR_STREAM(ArF32, 1, 0);
-        else if ((DTMASK & (1 << kFP64)) && v == variant_of(kFP64, 1))
+        else if ((DTMASK & (1 << kFP64)) && v == kFP64 * 2 + 1)
             JR_STREAM(ArF64, K, DEFER);
-        else if ((DTMASK & (1 << kFP64)) && v == variant_of(kFP64, 0))
+        else if ((DTMASK & (1 << kFP64)) && v == kFP64 * 2)
             JR_STREAM(ArF64, 1, 0);
-        else if ((DTMASK & (1 << kFF)) && v == variant_of(kFF, 1))
+        else if ((DTMASK & (1 << kFF)) && v == kFF * 2 + 1)
             JR_STREAM(ArFF, K, DEFER);
-        else if ((DTMASK & (1 << kFF)) && v == variant_of(kFF, 0))
+        else if ((DTMASK & (1 << kFF)) && v == kFF * 2)
             JR_STREAM(ArFF, 1, 0);
         else
             load_src(s, a, next_tile(cl, a), xd, yd, cr, ci);  // not reached
@@ -814,6 +923,7 @@ __global__ __launch_bounds__(256) void jr_tiled(PersistentArgs a) {
 template <class A, int COLOR>
 __device__ __forceinline__ void plain_pixel(const PersistentArgs& a, CFrame& F, int i, int j,
                                             int32_t* out) {
+    const int deg = F.degree;
     const double px = pixel_re(F.cx, F.hx, i, F.width);
     const double py = pixel_im(F.cy, F.hy, j, F.height);
     typename A::Z z;
@@ -827,7 +937,7 @@ __device__ __forceinline__ void plain_pixel(const PersistentArgs& a, CFrame& F, 
     }
     int n = 0;
     while (n < F.max_iter) {
-        if (!A::check_step(z, c)) break;
+        if (!A::check_step(z, c, deg)) break;
         n++;
     }
     out[(int64_t)j * F.width + i] = shade<COLOR>(a, n);
@@ -854,7 +964,14 @@ __global__ __launch_bounds__(256) void jr_plain_batch(PersistentArgs a) {
     const int j = F.row_begin + ty * F.tile_h + (int)(threadIdx.x >> 4);
     if (i >= F.width || j >= F.row_end) return;
     int32_t* out = a.out_base + F.out_offset;
-    if ((DTMASK & (1 << kFP32)) && F.dtype == kFP32)
+    if ((DTMASK & kGeneralBit) && F.degree > 2) {
+        if (F.dtype == kFP32)
+            plain_pixel<ArF32G, COLOR>(a, F, i, j, out);
+        else if (F.dtype == kFP64)
+            plain_pixel<ArF64G, COLOR>(a, F, i, j, out);
+        else
+            plain_pixel<ArFFG, COLOR>(a, F, i, j, out);
+    } else if ((DTMASK & (1 << kFP32)) && F.dtype == kFP32)
         plain_pixel<ArF32, COLOR>(a, F, i, j, out);
     else if ((DTMASK & (1 << kFP64)) && F.dtype == kFP64)
         plain_pixel<ArF64, COLOR>(a, F, i, j, out);
@@ -944,6 +1061,7 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
     const int th = min(min(F.tile_h, F.row_end - row0), rows_max);
     const int W = F.width;
     const int mi = F.max_iter;
+    const int deg = F.degree;
     const int lane = lane_id();
     const V zero = A::coord(0.0);
     const V xl = A::coord(pixel_re(F.cx, F.hx, col0 + min(lane, tw - 1), W));
@@ -970,10 +1088,10 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
         int u = 0;
 #pragma unroll 1
         for (; u + 2 <= P; u += 2) {
-            lead += A::check_step(z, c) ? 1 : 0;
-            lead += A::check_step(z, c) ? 1 : 0;
+            lead += A::check_step(z, c, deg) ? 1 : 0;
+            lead += A::check_step(z, c, deg) ? 1 : 0;
         }
-        if (u < P) lead += A::check_step(z, c) ? 1 : 0;
+        if (u < P) lead += A::check_step(z, c, deg) ? 1 : 0;
         const bool fin = col_ok && (lead < P || P >= mi);
         if (fin) tout[r * W + lane] = shade<COLOR>(a, min(lead, mi));
         const bool sv = col_ok && !fin;
@@ -1034,7 +1152,7 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
         }
         int lead = 0;
 #pragma unroll
-        for (int u = 0; u < K; ++u) lead += A::check_step(z, c) ? 1 : 0;
+        for (int u = 0; u < K; ++u) lead += A::check_step(z, c, deg) ? 1 : 0;
         const bool stop = (lead < K) || (n + K >= mi);
         cnt = (it && stop) ? min(n + lead, mi) : cnt;
         fi = fi || (it && stop);
@@ -1072,7 +1190,14 @@ __global__ __launch_bounds__(256) void jr_rows(PersistentArgs a) {
         else if (!mandel) rows_tile<A_, 1, 0, COLOR>(a, F, t, P, list, cap, S::rows);    \
         else rows_tile<A_, 1, 1, COLOR>(a, F, t, P, list, cap, S::rows);                 \
     } while (0)
-        if ((DTMASK & (1 << kFP32)) && F.dtype == kFP32)
+        if ((DTMASK & kGeneralBit) && F.degree > 2) {
+            if (F.dtype == kFP32)
+                JR_ROWS(ArF32G);
+            else if (F.dtype == kFP64)
+                JR_ROWS(ArF64G);
+            else
+                JR_ROWS(ArFFG);
+        } else if ((DTMASK & (1 << kFP32)) && F.dtype == kFP32)
             JR_ROWS(ArF32);
         else if ((DTMASK & (1 << kFP64)) && F.dtype == kFP64)
             JR_ROWS(ArF64);
@@ -1099,6 +1224,9 @@ using TiledFn = void (*)(PersistentArgs);
 
 template <int K, int DEFER, int HYB>
 static TiledFn pick_mask(int dtmask) {
+    if (dtmask & kGeneralBit)  // general maps: every dtype, refill stream
+        return (dtmask & kColorBit) ? jr_tiled<K, DEFER, 7 | kGeneralBit | kColorBit, 0>
+                                    : jr_tiled<K, DEFER, 7 | kGeneralBit, 0>;
     if (dtmask & kColorBit) {
         // one-dtype colour kernels for the common cases (the all-dtype
         // variant holds the float-float registers and runs fewer waves)
@@ -1137,6 +1265,9 @@ static TiledFn pick_block(int unroll, int defer, int dtmask) {
 
 template <int K>
 static TiledFn pick_rows_mask(int dtmask) {
+    if (dtmask & kGeneralBit)
+        return (dtmask & kColorBit) ? jr_rows<K, 7 | kGeneralBit | kColorBit>
+                                    : jr_rows<K, 7 | kGeneralBit>;
     switch (dtmask) {
         case 1 << kFP32: return jr_rows<K, 1 << kFP32>;
         case 1 << kFP64: return jr_rows<K, 1 << kFP64>;
@@ -1159,6 +1290,9 @@ static TiledFn pick(int unroll, int defer, int dtmask, int hybrid) {
 }
 
 static TiledFn pick_plain(int dtmask) {
+    if (dtmask & kGeneralBit)
+        return (dtmask & kColorBit) ? jr_plain_batch<7 | kGeneralBit | kColorBit>
+                                    : jr_plain_batch<7 | kGeneralBit>;
     if (dtmask == ((1 << kFP32) | kColorBit)) return jr_plain_batch<(1 << kFP32) | kColorBit>;
     if (dtmask == ((1 << kFP64) | kColorBit)) return jr_plain_batch<(1 << kFP64) | kColorBit>;
     if (dtmask & kColorBit) return jr_plain_batch<7 | kColorBit>;

@@ -92,9 +92,13 @@ def test_check_frames():
     assert jr.check_frames(fr, offs, cap, rows=[(47, 48), (16, 17)]) == jr.JR_OK
     bad = [Frame(complex(-0.8, 0.156), (-1.5, 1.5, -1.5, 1.5), 64, 48, 100, "fp32")]
     arr = jr._frames_array(bad, [0])
-    arr[0].reserved = 1
-    assert jr.lib.jr_check_frames(arr, 1, 10 ** 6) == jr.JR_EINVAL
-    arr[0].reserved = 0
+    for bad in (1, 9, -2):
+        arr[0].degree = bad
+        assert jr.lib.jr_check_frames(arr, 1, 10 ** 6) == jr.JR_EINVAL
+    for good in (0, 2, 3, 8):
+        arr[0].degree = good
+        assert jr.lib.jr_check_frames(arr, 1, 10 ** 6) == jr.JR_OK
+    arr[0].degree = 0
     arr[0].mode = 5
     assert jr.lib.jr_check_frames(arr, 1, 10 ** 6) == jr.JR_EINVAL
     assert jr.lib.jr_check_frames(arr, 0, 10 ** 6) == jr.JR_EINVAL

@@ -61,6 +61,7 @@ class Frame:
     max_iter: int
     dtype: str = "fp64"        # "fp64" | "fp32" | "ff"
     mode: str = "julia"        # "julia" | "mandelbrot"
+    degree: int = 2            # map Z^degree + C
 
     @property
     def pixels(self) -> int:
