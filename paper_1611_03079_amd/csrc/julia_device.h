@@ -83,6 +83,9 @@ struct PlainArgs {
 hipError_t launch_tiled(int unroll, int defer, int dtmask, int blocks, const PersistentArgs& args,
                         hipStream_t stream);
 hipError_t launch_plain(int dtype, const PlainArgs& args, hipStream_t stream);
+// Tile rows the rows kernel for a launch of this dtype mask (dtype bits and
+// kGeneralBit) can hold.
+int rows_capacity(int dtmask);
 // One thread per pixel over the frame table (tiles of 16 x 16, one workgroup each).
 hipError_t launch_plain_batch(int dtmask, const PersistentArgs& args, hipStream_t stream);
 

@@ -239,7 +239,6 @@ void build_table(const jr_frame* frames, int32_t n, const jr_schedule& s, Table&
     t.total_tiles = 0;
     t.dtmask = 0;
     // The rows kernel's per-wave list holds a fixed number of tile rows.
-    // It holds kRowsFP32 rows only in the kernel for quadratic FP32 frames.
     int32_t rows_cap = 64;
     if (s.kernel == JR_KERNEL_ROWS) {
         int mask = 0;
@@ -247,7 +246,7 @@ void build_table(const jr_frame* frames, int32_t n, const jr_schedule& s, Table&
             mask |= 1 << frames[k].dtype;
             if (frames[k].degree > 2) mask |= jr::kGeneralBit;
         }
-        rows_cap = mask == (1 << JR_FP32) ? jr::kRowsFP32 : jr::kRowsWide;
+        rows_cap = jr::rows_capacity(mask);
     }
     for (int32_t k = 0; k < n; ++k) {
         const jr_frame& f = frames[idx[k]];

@@ -1263,6 +1263,13 @@ static TiledFn pick_block(int unroll, int defer, int dtmask) {
     }
 }
 
+// Tile rows the list of the rows kernel picked for `dtmask` holds (the host
+// caps tile_h with it; the kernel never writes past its list).
+int rows_capacity(int dtmask) {
+    return (dtmask & ~kColorBit) == (1 << kFP32) ? RowsShape<1 << kFP32>::rows
+                                                 : RowsShape<7 | kGeneralBit>::rows;
+}
+
 template <int K>
 static TiledFn pick_rows_mask(int dtmask) {
     if (dtmask & kGeneralBit)
