@@ -18,7 +18,7 @@ sample of the same workload, and further legs in "extra": the plain
 one-thread-per-pixel kernel on the same frames, the persistent-queue mode, the
 single 4096x4096 images in FP32 and FP64, the 512x512 FP64 image's latency,
 an uneven batch (FP32 + float-float, one launch), the headline batch with
-the fused colour store, the serving loop's p50/p99 latency under Poisson
+the fused colour store, a batch of the general map Z^3 + C, the serving loop's p50/p99 latency under Poisson
 arrivals, and the FP32 / float-float pixel fractions that
 differ from FP64.
 """
@@ -223,6 +223,31 @@ def extra_legs(args, torch, jr, wl, frames, sched, ms_headline, iters):
         "gpixel_iter_s": round(it_u / (ms_u * 1e-3) / 1e9, 2), "ms": round(ms_u, 3),
         "plain_per_frame_ms": round(ms_up, 3), "vs_plain": round(ms_up / ms_u, 3),
         "pixels": sum(f.pixels for f in ub), "pixel_iters": it_u}
+    # general map Z^3 + C: 32 frames of 1920x1080, one launch, against the
+    # plain kernel launched per frame
+    gp = wl.general_path(32, 3)
+    gsched, _ = tuned_schedule(jr, "general_deg3_fp32", gp)
+    plan = jr.Plan(gp, gsched)
+    ms_g, _ = time_plan_steps(torch, plan, 5, 1, graph=False)
+    it_g = count_sum(torch, plan.views)
+    plan.close()
+    outs = [torch.empty((f.height, f.width), dtype=torch.int32, device="cuda") for f in gp]
+
+    def plain_general():
+        for f, o in zip(gp, outs):
+            jr.render(f.c, f.window, f.width, f.height, f.max_iter, f.dtype, out=o, plain=True,
+                      degree=3)
+    plain_general()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain_general()
+    torch.cuda.synchronize()
+    ms_gp = (time.perf_counter() - t0) * 1e3
+    del outs
+    ex["general_map_degree3_32_frames_fp32"] = {
+        "gpixel_iter_s": round(it_g / (ms_g * 1e-3) / 1e9, 2), "ms": round(ms_g, 3),
+        "plain_per_frame_ms": round(ms_gp, 3), "vs_plain": round(ms_gp / ms_g, 3),
+        "schedule": gsched.__dict__, "pixel_iters": it_g}
     # serving: Poisson arrivals at several rates, with the precision policy
     # as specified (float-float for mid widths) and with FP64 for every window
     # narrower than FP32 handles (on MI355X FP64 runs at the FP32 rate)

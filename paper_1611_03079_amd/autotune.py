@@ -218,6 +218,7 @@ def standard_workloads():
         "single_512_fp64": [wl.single_512("fp64")],
         "uneven_fp32_ff": wl.uneven_batch(0, n=16),
         "cardioid_path_fp32": wl.cardioid_path(64),
+        "general_deg3_fp32": wl.general_path(32, 3),
     }
 
 

@@ -116,6 +116,19 @@ def cardioid_path(n: int, a: float = 3.9, width: int = 1920, height: int = 1080,
 
 
 # --------------------------------------------------------------------------
+# General maps: a path of constants C_k = r exp(2 pi i k / n) for Z^d + C
+# (r = 0.6 for d = 3 runs from light frames, mean count about 3, to frames
+# with a mean near 45 at cap 100).
+# --------------------------------------------------------------------------
+def general_path(n: int = 32, degree: int = 3, radius: float = 0.6, width: int = 1920,
+                 height: int = 1080, max_iter: int = 100, dtype: str = "fp32",
+                 window=(-1.6, 1.6, -0.9, 0.9)) -> List[Frame]:
+    return [Frame(complex(radius * math.cos(2.0 * math.pi * k / n),
+                          radius * math.sin(2.0 * math.pi * k / n)),
+                  window, width, height, max_iter, dtype, "julia", degree) for k in range(n)]
+
+
+# --------------------------------------------------------------------------
 # Uneven batch: square side ~ U{256..4096}; C uniform on the unit disk,
 # accepted when its Mandelbrot orbit from 0 survives 20 steps; cap from
 # {100, 500, 2000}; FP32 or float-float with probability 1/2 each.
