@@ -313,7 +313,7 @@ template <int COLOR>
 __device__ __forceinline__ void stage_palette(const PersistentArgs& a) {
     if (!COLOR) return;
     uint32_t* pal = palette_lds();
-    for (int k = threadIdx.x; k < a.palette_len; k += blockDim.x) pal[k] = a.palette[k];
+    for (int k = threadIdx.x; k < a.palette_len; k += 256) pal[k] = a.palette[k];  // 256-thread blocks
     __syncthreads();
 }
 
@@ -395,8 +395,8 @@ struct Claimer {
 __device__ __forceinline__ void claimer_init(Claimer& cl, const PersistentArgs& a) {
     // threadIdx.x / 64 is the same for the whole wave; readfirstlane tells the
     // compiler so, which keeps the claimer and the tile state in SGPRs.
-    cl.wave = blockIdx.x * (blockDim.x / 64) +
-              (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    cl.wave = (int)__builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / 64) +
+                                                  (threadIdx.x >> 6));
     cl.cur = cl.end = 0;
     cl.started = false;
     cl.raw = 0;
@@ -1059,9 +1059,9 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
     const int row0 = F.row_begin + ty * F.tile_h;
     const int tw = min(F.tile_w, F.width - col0);
     const int th = min(min(F.tile_h, F.row_end - row0), rows_max);
-    const int W = F.width;
-    const int mi = F.max_iter;
-    const int deg = F.degree;
+    const int W = __builtin_amdgcn_readfirstlane(F.width);
+    const int mi = __builtin_amdgcn_readfirstlane(F.max_iter);
+    const int deg = __builtin_amdgcn_readfirstlane(F.degree);
     const int lane = lane_id();
     const V zero = A::coord(0.0);
     const V xl = A::coord(pixel_re(F.cx, F.hx, col0 + min(lane, tw - 1), W));
@@ -1181,7 +1181,9 @@ __global__ __launch_bounds__(256) void jr_rows(PersistentArgs a) {
         f = find_frame(frames, a.nframes, t, f);
         CFrame& F = frames[f];
         const bool abs = F.defer != 0;
-        const int P = abs ? a.bail : 1;
+        // wave-uniform; readfirstlane says so to the compiler, which otherwise
+        // may keep the first block's trip count in a vector register
+        const int P = __builtin_amdgcn_readfirstlane(abs ? a.bail : 1);
         const bool mandel = F.mode == kModeMandelbrot;
 #define JR_ROWS(A_)                                                                      \
     do {                                                                                 \
