@@ -17,7 +17,7 @@ launch on the stream it runs on), the single-threaded CPU oracle on a bounded
 sample of the same workload, and further legs in "extra": the plain
 one-thread-per-pixel kernel on the same frames, the persistent-queue mode, the
 single 4096x4096 images in FP32 and FP64, the 512x512 FP64 image's latency,
-an uneven batch (FP32 + float-float, one launch), the headline batch with
+the 1024-frame uneven batch (FP32 + float-float, one launch), the headline batch with
 the fused colour store, a batch of the general map Z^3 + C, the serving loop's p50/p99 latency under Poisson
 arrivals, and the FP32 / float-float pixel fractions that
 differ from FP64.
@@ -209,20 +209,23 @@ def extra_legs(args, torch, jr, wl, frames, sched, ms_headline, iters):
             torch.cuda.synchronize()
         ex["single_512_fp64_latency_us_" + ("plain" if plain else "tuned")] = round(
             (time.perf_counter() - t0) / 50 * 1e6, 1)
-    # uneven batch: FP32 + float-float frames of random sides and caps, one launch
-    ub = wl.uneven_batch(0, n=64)
+    # uneven batch: 1024 FP32 and float-float frames of random sides (256..4096)
+    # and caps, one launch into a 24.5 GB arena; the plain kernel then renders
+    # the same frames one launch each into the same arena
+    ub = wl.uneven_batch(0, n=1024)
     usched, _ = tuned_schedule(jr, "uneven_fp32_ff", ub)
     plan = jr.Plan(ub, usched)
-    ms_u, _ = time_plan_steps(torch, plan, 2, 1, graph=False)
+    ms_u, _ = time_plan_steps(torch, plan, 1, 1, graph=False)
     it_u = count_sum(torch, plan.views)
+    ms_up = time_renders(jr, torch, ub, plan.views, 1, plain=True)
     plan.close()
-    outs = [torch.empty((f.height, f.width), dtype=torch.int32, device="cuda") for f in ub]
-    ms_up = time_renders(jr, torch, ub, outs, 1, plain=True)
-    del outs
-    ex["uneven_batch_64_frames_fp32_ff"] = {
+    del plan
+    torch.cuda.empty_cache()
+    ex["uneven_batch_1024_frames_fp32_ff"] = {
         "gpixel_iter_s": round(it_u / (ms_u * 1e-3) / 1e9, 2), "ms": round(ms_u, 3),
         "plain_per_frame_ms": round(ms_up, 3), "vs_plain": round(ms_up / ms_u, 3),
-        "pixels": sum(f.pixels for f in ub), "pixel_iters": it_u}
+        "frames": len(ub), "pixels": sum(f.pixels for f in ub), "pixel_iters": it_u,
+        "schedule": usched.__dict__}
     # general map Z^3 + C: 32 frames of 1920x1080, one launch, against the
     # plain kernel launched per frame
     gp = wl.general_path(32, 3)

@@ -216,7 +216,7 @@ def standard_workloads():
         "single_4096_fp64_cap100": [wl.single_4096(s, 100, "fp64") for s in range(2)],
         "single_4096_fp64_cap1000": [wl.single_4096(s, 1000, "fp64") for s in range(2)],
         "single_512_fp64": [wl.single_512("fp64")],
-        "uneven_fp32_ff": wl.uneven_batch(0, n=16),
+        "uneven_fp32_ff": wl.uneven_batch(0, n=64),
         "cardioid_path_fp32": wl.cardioid_path(64),
         "general_deg3_fp32": wl.general_path(32, 3),
     }

@@ -332,3 +332,24 @@ def test_deep_zoom_windows(width):
         _, views = batch(fr)
         for f, v in zip(fr, views):
             np.testing.assert_array_equal(v, ref(f))
+
+
+def test_uneven_batch_full_sampled():
+    """The 1024-frame uneven batch (sides 256..4096, caps 100/500/2000, FP32
+    and float-float, 24.5 GB of counts) in one launch with the tuned schedule
+    the benchmark uses; 40 sampled pixels per frame against the oracle."""
+    from paper_1611_03079_amd import autotune as at
+    frames = wl.uneven_batch(0, n=1024)
+    e = at.load_cache().get("_workloads", {}).get("uneven_fp32_ff")
+    sched = jr.Schedule(**e["schedule"]) if e else None
+    arena, views = jr.render_batch(frames, sched)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(17)
+    for f, v in zip(frames, views):
+        ii = rng.integers(0, f.width, 40).astype(np.int32)
+        jj = rng.integers(0, f.height, 40).astype(np.int32)
+        got = v[torch.from_numpy(jj).long().cuda(), torch.from_numpy(ii).long().cuda()].cpu().numpy()
+        want = oracle.render_pixels(f.c, f.window, f.width, f.height, f.max_iter, ii, jj, f.dtype)
+        np.testing.assert_array_equal(got, want, err_msg=str(f))
+    del arena, views
+    torch.cuda.empty_cache()
