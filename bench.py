@@ -67,6 +67,10 @@ def parse():
     p.add_argument("--no-extra", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--serve-seconds", type=float, default=2.5)
+    p.add_argument("--schedule", choices=("tuned", "plain", "tiled"), default="tuned",
+                   help="headline schedule: the autotuned one (default), the batched "
+                        "one-thread-per-pixel kernel, or the refill stream (64x64 tiles, "
+                        "counted blocks of 8), for profiling comparisons")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run an elementwise device copy of 1 GiB (read 1 GiB, write 1 GiB) "
                         "whose FETCH_SIZE / WRITE_SIZE counters calibrate the traffic figures")
@@ -308,7 +312,12 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     frames = wl.parameter_path()
-    sched, sched_src = tuned_schedule(jr, "parameter_path_fp32", frames)
+    if args.schedule == "plain":
+        sched, sched_src = jr.Schedule(kernel="plain"), "--schedule plain"
+    elif args.schedule == "tiled":
+        sched, sched_src = jr.Schedule(64, 64, 8, 0, 32, 0, 16, "cost"), "--schedule tiled"
+    else:
+        sched, sched_src = tuned_schedule(jr, "parameter_path_fp32", frames)
     plan = jr.Plan(frames, sched)
     plan.capture()
     ms_step, kernel_ms = time_plan_steps(torch, plan, args.steps, args.warmup, graph=True)
