@@ -343,7 +343,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "parameter_path: 256 frames 1920x1080, C=0.7885exp(2 pi i k/256), "
                                "window Re[-1.78,1.78] x Im[-1,1], max_iter 100, FP32, one launch "
-                               "of the tiled kernel per step (hipGraph replay), autotuned schedule",
+                               "per step (hipGraph replay) with the schedule below",
                    "frames": len(frames), "pixels_per_step": pixels, "pixel_iters_per_step": iters,
                    "schedule": sched.__dict__, "schedule_source": sched_src,
                    "tiles": info["tiles"], "workgroups": info["workgroups"]},
