@@ -5,6 +5,8 @@ oracle's FP64 counts exactly; the FP32 and float-float kernels must equal the
 oracle's FP32 and float-float formulations exactly, and their difference from
 FP64 is reported as a pixel fraction.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -273,21 +275,46 @@ def test_single_4096_sampled(seed, it, dtype):
     np.testing.assert_array_equal(plain, got)
 
 
-def test_parameter_path_full_sampled():
-    """The 256-frame 1920x1080 FP32 batch in the benchmark's launch setup."""
-    frames = wl.parameter_path()
-    plan = jr.Plan(frames, jr.default_schedule("fp32"))
+def _golden_sums(name):
+    rows = []
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", name)):
+        if not line.startswith("#"):
+            rows.append([int(v) for v in line.split()[1:]])
+    return rows
+
+
+def _bench_schedule(name):
+    from paper_1611_03079_amd import autotune as at
+    e = at.load_cache().get("_workloads", {}).get(name)
+    return jr.Schedule(**e["schedule"]) if e else None
+
+
+@pytest.mark.parametrize("workload", ["parameter_path_fp32", "general_deg3_fp32"])
+def test_full_batch_sums_and_samples(workload):
+    """The benchmark's batches at full size, in its launch setup (autotuned
+    schedule, captured graph replayed): every frame's count sum, pixels at
+    the cap and pixels at zero equal the oracle's (tests/golden, written by
+    the oracle), and sampled pixels match one by one."""
+    if workload == "parameter_path_fp32":
+        frames, golden = wl.parameter_path(), "parameter_path_fp32_sums.txt"
+    else:
+        frames, golden = wl.general_path(32, 3), "general_path_deg3_fp32_sums.txt"
+    plan = jr.Plan(frames, _bench_schedule(workload))
     plan.arena.fill_(-1)
-    plan.launch()
+    plan.capture()
+    plan.replay()
     torch.cuda.synchronize()
-    arena = plan.arena.cpu().numpy()
-    assert (arena >= 0).all() and (arena <= 100).all()
-    for k in range(0, 256, 5):
+    want = _golden_sums(golden)
+    for f, v, (s, capped, zero) in zip(frames, plan.views, want):
+        assert int(v.sum(dtype=torch.int64)) == s
+        assert int((v == f.max_iter).sum()) == capped
+        assert int((v == 0).sum()) == zero
+    for k in range(0, len(frames), 5):
         f = frames[k]
-        v = arena[k * f.pixels:(k + 1) * f.pixels].reshape(f.height, f.width)
         ii, jj = _sample(f.width, f.height, 1500, k)
-        want = oracle.render_pixels(f.c, f.window, f.width, f.height, f.max_iter, ii, jj, "fp32")
-        np.testing.assert_array_equal(v[jj, ii], want)
+        got = plan.views[k].cpu().numpy()[jj, ii]
+        np.testing.assert_array_equal(got, oracle.render_pixels(
+            f.c, f.window, f.width, f.height, f.max_iter, ii, jj, f.dtype, "julia", f.degree))
     plan.close()
 
 
