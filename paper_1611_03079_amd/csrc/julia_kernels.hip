@@ -998,7 +998,9 @@ __global__ __launch_bounds__(256) void jr_plain_batch(PersistentArgs a) {
 //            entries straight from the list, and C is the frame's constant.
 // Counts: phase 1 counts the leading non-escaped iterates of Z_0..Z_{P-1}; with
 // escape absorbing (|C| <= 1.9) that is min(count, P), so a pixel with fewer
-// than P is final and the others continue from Z_P with n = P.  Frames where
+// than P is final and the others continue from Z_P with n = P.  A row whose
+// pixels have all escaped stops before P: the iterates it skips would count
+// nothing.  Frames where
 // escape may not be absorbing run P = 1 and K = 1, the exact test on every
 // iteration.
 template <int DTMASK>
@@ -1084,14 +1086,24 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
             z = A::make(xl, y);
             c = cj;
         }
+        // Two iterations per trip; the row stops early once every lane's
+        // pixel has escaped (absorbing: later iterates would count nothing).
+        // Lanes past the tile's width repeat its last column, so they never
+        // hold the row back on their own.
         int lead = 0;
         int u = 0;
+        bool more = true;
 #pragma unroll 1
         for (; u + 2 <= P; u += 2) {
             lead += A::check_step(z, c, deg) ? 1 : 0;
-            lead += A::check_step(z, c, deg) ? 1 : 0;
+            const bool in = A::check_step(z, c, deg);
+            lead += in ? 1 : 0;
+            if (__ballot(in) == 0) {
+                more = false;
+                break;
+            }
         }
-        if (u < P) lead += A::check_step(z, c, deg) ? 1 : 0;
+        if (more && u < P) lead += A::check_step(z, c, deg) ? 1 : 0;
         const bool fin = col_ok && (lead < P || P >= mi);
         if (fin) tout[r * W + lane] = shade<COLOR>(a, min(lead, mi));
         const bool sv = col_ok && !fin;
