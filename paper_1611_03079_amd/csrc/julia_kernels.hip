@@ -1025,6 +1025,13 @@ __device__ __forceinline__ typename A::V bcast(typename A::V v, int lane) {
     return r;
 }
 
+// base[off] = v for a wave-uniform base and a per-lane offset 0 <= off < 2^30:
+// an unsigned 32-bit byte offset lets the store take the base from scalar
+// registers (no 64-bit address arithmetic per lane).
+__device__ __forceinline__ void store_at(int32_t* base, int off, int32_t v) {
+    *(int32_t*)((char*)base + (uint32_t)off * 4u) = v;
+}
+
 template <class A>
 __device__ __forceinline__ void list_put(uint32_t* list, int cap, int e, const typename A::Z& z) {
     constexpr int W = (int)(sizeof(typename A::Z) / 4);
@@ -1105,7 +1112,7 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
         }
         if (more && u < P) lead += A::check_step(z, c, deg) ? 1 : 0;
         const bool fin = col_ok && (lead < P || P >= mi);
-        if (fin) tout[r * W + lane] = shade<COLOR>(a, min(lead, mi));
+        if (fin) store_at(tout + (int64_t)r * W, lane, shade<COLOR>(a, min(lead, mi)));
         const bool sv = col_ok && !fin;
         const uint64_t m = __ballot(sv);
         if (sv) {
@@ -1130,7 +1137,7 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
     for (;;) {
         if (__popcll(running) <= busy_max) {
             if (fi) {
-                tout[off] = shade<COLOR>(a, cnt);
+                store_at(tout, off, shade<COLOR>(a, cnt));
                 fi = false;
             }
             if (next < qn) {
