@@ -2,7 +2,7 @@
 
 Workload (one step): the batched parameter path -- 256 frames of 1920x1080,
 C_k = 0.7885 exp(2 pi i k / 256), window Re[-1.78, 1.78] x Im[-1, 1], cap 100,
-FP32 -- rendered in ONE launch of the tiled kernel with the autotuned schedule,
+FP32 -- rendered in ONE launch with the autotuned kernel and schedule,
 replayed from a captured hipGraph.  This is the batched form the throughput
 target is quoted on.  Inputs are synthetic and resident in HBM before the timed
 region; nothing leaves the device inside it.
@@ -14,13 +14,17 @@ nothing is read.
 
 The JSON line also carries the roofline of the kernel (HIP events around each
 launch on the stream it runs on), the single-threaded CPU oracle on a bounded
-sample of the same workload, and further legs in "extra": the plain
-one-thread-per-pixel kernel on the same frames, the persistent-queue mode, the
-single 4096x4096 images in FP32 and FP64, the 512x512 FP64 image's latency,
-the 1024-frame uneven batch (FP32 + float-float, one launch), the headline batch with
-the fused colour store, a batch of the general map Z^3 + C, the serving loop's p50/p99 latency under Poisson
-arrivals, and the FP32 / float-float pixel fractions that
-differ from FP64.
+sample of the same workload, and further legs in "extra":
+  - the plain one-thread-per-pixel kernel on the same frames, the
+    persistent-queue mode, and the fused colour store;
+  - the single 4096x4096 images in FP32 and FP64, and the 512x512 FP64
+    image's latency;
+  - the 1024-frame uneven batch (FP32 and float-float, one launch);
+  - a batch of the general map Z^3 + C;
+  - the square-image sweep of the paper's timing study, GPU beside the CPU
+    oracle;
+  - the serving loop's p50/p99 latency under Poisson arrivals;
+  - the FP32 and float-float pixel fractions that differ from FP64.
 """
 import argparse
 import json
@@ -278,6 +282,33 @@ def extra_legs(args, torch, jr, wl, frames, sched, ms_headline, iters):
             del srv
             torch.cuda.empty_cache()
     ex["serving"] = serve
+    # the paper's timing study (Figure 1): square images of side 10 .. 10000,
+    # C = -0.8 + 0.156i, window [-1.5, 1.5]^2, cap 100, FP64: GPU time per
+    # image (tuned and plain, synchronised, launch included) beside the
+    # single-threaded oracle on this host (sides up to 3162)
+    if not args.no_cpu:
+        import oracle
+    sweep = {}
+    for f in wl.square_sweep("fp64"):
+        o = torch.empty((f.height, f.width), dtype=torch.int32, device="cuda")
+        row = {}
+        for plain in (False, True):
+            jr.render(f.c, f.window, f.width, f.height, 100, "fp64", out=o, plain=plain)
+            torch.cuda.synchronize()
+            reps = 20 if f.width <= 1000 else 5
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                jr.render(f.c, f.window, f.width, f.height, 100, "fp64", out=o, plain=plain)
+            torch.cuda.synchronize()
+            row["gpu_plain_ms" if plain else "gpu_tuned_ms"] = round(
+                (time.perf_counter() - t0) * 1e3 / reps, 4)
+        if not args.no_cpu and f.width <= 3162:
+            t0 = time.perf_counter()
+            oracle.render(f.c, f.window, f.width, f.height, 100, "fp64")
+            row["cpu_oracle_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
+        sweep["side_%d" % f.width] = row
+        del o
+    ex["figure1_square_sweep_fp64"] = sweep
     # pixels whose FP32 / float-float count differs from FP64 (GPU vs GPU)
     mism = {}
     for dt in ("fp32", "ff"):
