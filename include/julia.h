@@ -261,6 +261,25 @@ void jr_plan_destroy(jr_plan *plan);
 int jr_get_default_schedule(int32_t dtype, int32_t max_iter, jr_schedule *out);
 int jr_set_default_schedule(int32_t dtype, const jr_schedule *sched);
 
+/*
+ * Schedules of one-image calls (julia_render, mandelbrot_render,
+ * julia_render_colored), chosen by the image's cap and size: a call takes the
+ * entry of its dtype with the smallest max_iter_limit >= max_iter and, among
+ * those, the smallest pixels_limit >= width*height, or when no entry's
+ * pixels_limit covers the image, the one with the largest pixels_limit; with
+ * no entry for its dtype and cap it takes the dtype's default.  An entry whose
+ * kernel is JR_KERNEL_PLAIN runs the 2-D kernel of julia_render_plain (the
+ * colored call runs the batched plain kernel).  An entry with the same
+ * (dtype, max_iter_limit, pixels_limit) is replaced; at most 64 entries
+ * (JR_EINVAL beyond).  The Python binding installs the autotuner's per-image
+ * winners here.
+ */
+int jr_set_image_schedule(int32_t dtype, int32_t max_iter_limit, int64_t pixels_limit,
+                          const jr_schedule *sched);
+/* The schedule a one-image call of this dtype, cap and pixel count takes. */
+int jr_get_image_schedule(int32_t dtype, int32_t max_iter, int64_t pixels, jr_schedule *out);
+void jr_clear_image_schedules(void);
+
 /* Validate a schedule or a frame table without touching the device. */
 int jr_check_schedule(const jr_schedule *sched);
 int jr_check_frames(const jr_frame *frames, int32_t n, int64_t out_capacity);

@@ -89,7 +89,8 @@ class Schedule:
 EXPORTS = (
     "julia_render", "julia_render_plain", "mandelbrot_render", "mandelbrot_render_plain",
     "julia_render_batch", "julia_render_batch_colored", "julia_render_colored",
-    "jr_plan_create", "jr_plan_set_palette", "jr_plan_launch", "jr_plan_capture",
+    "jr_plan_create", "jr_plan_set_palette", "jr_set_image_schedule", "jr_get_image_schedule",
+    "jr_clear_image_schedules", "jr_plan_launch", "jr_plan_capture",
     "jr_plan_replay", "jr_plan_info", "jr_plan_destroy", "jr_get_default_schedule",
     "jr_set_default_schedule", "jr_check_schedule", "jr_check_frames", "jr_strerror",
     "jr_last_error_message", "jr_device_info", "jr_shutdown",
@@ -133,6 +134,12 @@ def _load():
     lib.julia_render_colored.restype = ctypes.c_int
     lib.jr_plan_set_palette.argtypes = [vp, vp, i32]
     lib.jr_plan_set_palette.restype = ctypes.c_int
+    lib.jr_set_image_schedule.argtypes = [i32, i32, i64, P(jr_schedule)]
+    lib.jr_set_image_schedule.restype = ctypes.c_int
+    lib.jr_get_image_schedule.argtypes = [i32, i32, i64, P(jr_schedule)]
+    lib.jr_get_image_schedule.restype = ctypes.c_int
+    lib.jr_clear_image_schedules.argtypes = []
+    lib.jr_clear_image_schedules.restype = None
     lib.jr_plan_create.argtypes = [P(jr_frame), i32, vp, i64, P(jr_schedule), P(vp)]
     lib.jr_plan_create.restype = ctypes.c_int
     for name in ("jr_plan_launch", "jr_plan_capture", "jr_plan_replay"):
@@ -234,6 +241,35 @@ def tuned_schedule(dtype: str, max_iter: int, pixels: int) -> Optional["Schedule
 
 
 _TUNED_MEMO = {}
+_IMAGE_SCHEDULES_FOR = set()
+
+
+def _install_image_schedules():
+    """Hand the autotuner's single-image winners for this device to the
+    library (jr_set_image_schedule), once per device."""
+    from . import autotune
+    dev = autotune.device_name()
+    if dev in _IMAGE_SCHEDULES_FOR:
+        return
+    _IMAGE_SCHEDULES_FOR.add(dev)
+    try:
+        cache = autotune.load_cache()
+    except (OSError, ValueError):
+        return
+    autotune.install_image_schedules(cache, dev)
+
+
+def image_schedule(dtype: str, max_iter: int, pixels: int) -> Schedule:
+    """The schedule the library gives a one-image call of this size."""
+    out = jr_schedule()
+    _check(lib.jr_get_image_schedule(DTYPES[dtype], int(max_iter), int(pixels),
+                                     ctypes.byref(out)))
+    return Schedule.from_c(out)
+
+
+def set_image_schedule(dtype: str, max_iter_limit: int, pixels_limit: int, schedule: Schedule):
+    _check(lib.jr_set_image_schedule(DTYPES[dtype], int(max_iter_limit), int(pixels_limit),
+                                     ctypes.byref(schedule.to_c())))
 
 
 def render(c, window, width: int, height: int, max_iter: int, dtype: str = "fp64",
@@ -242,8 +278,9 @@ def render(c, window, width: int, height: int, max_iter: int, dtype: str = "fp64
     """Counts of one image as an int32 (height, width) CUDA tensor (row 0 = im_max).
 
     ``plain=True`` uses the one-thread-per-pixel comparator kernel.  Otherwise
-    the schedule is ``schedule``, else the autotuner's choice for the image's
-    bucket, else the library default (julia_render / mandelbrot_render).
+    the schedule is ``schedule``, else the library's choice by size
+    (julia_render / mandelbrot_render), which holds the autotuner's per-image
+    winners (installed on first use, see _install_image_schedules).
 
     With ``palette`` (see _palette_ptr) each pixel holds the 32 bits of
     palette[min(count, len - 1)] instead of its count, stored by the kernel
@@ -265,9 +302,10 @@ def render(c, window, width: int, height: int, max_iter: int, dtype: str = "fp64
         pp, plen = _palette_ptr(palette)
         if plain:
             schedule = Schedule(kernel="plain")
-        elif schedule is None:
+        elif schedule is None and (mode != "julia" or degree != 2):
             schedule = tuned_schedule(dtype, max_iter, width * height)
         if schedule is None and mode == "julia" and degree == 2:
+            _install_image_schedules()
             c = complex(c)
             _check(lib.julia_render_colored(jr_complex(c.real, c.imag), _window(window), width,
                                             height, max_iter, dt, pp, plen,
@@ -281,16 +319,14 @@ def render(c, window, width: int, height: int, max_iter: int, dtype: str = "fp64
                                                   width * height, sched, st))
         return out.view(-1)[: width * height].view(height, width)
     if not plain:
-        if schedule is None:
-            schedule = tuned_schedule(dtype, max_iter, width * height)
-            # one image with the one-thread-per-pixel kernel: its 2-D grid form
-            plain = schedule is not None and schedule.kernel == "plain"
-        if schedule is not None and not plain:
+        if schedule is not None:
             f = _OneFrame(c, window, width, height, max_iter, dtype, mode)
             arr = _frames_array([f], [0])
             _check(lib.julia_render_batch(arr, 1, ctypes.c_void_p(out.data_ptr()),
                                           width * height, ctypes.byref(schedule.to_c()), st))
             return out.view(-1)[: width * height].view(height, width)
+        # the library picks the schedule by size (jr_set_image_schedule)
+        _install_image_schedules()
     if mode == "julia":
         c = complex(c)
         fn = lib.julia_render_plain if plain else lib.julia_render

@@ -191,6 +191,25 @@ def lookup(cache: Dict[str, dict], dtype: str, max_iter: int, pixels: int) -> Op
     return jr.Schedule(**e["schedule"]) if e else None
 
 
+CAP_LIMITS = {"cap<=128": 128, "cap<=1024": 1024, "cap>1024": 2 ** 31 - 1}
+PIXEL_LIMITS = {"px<1M": (1 << 20) - 1, "px<64M": (64 << 20) - 1, "px>=64M": 2 ** 63 - 1}
+
+
+def install_image_schedules(cache: Dict[str, dict], device: str) -> int:
+    """Install the single-image buckets of `device` from the cache as the
+    library's per-size schedules (jr_set_image_schedule); returns how many."""
+    n = 0
+    for key, e in cache.items():
+        parts = key.split("|")
+        if len(parts) != 4 or parts[0] != device:
+            continue  # batch entries and other devices
+        _, dtype, cap, px = parts
+        jr.set_image_schedule(dtype, CAP_LIMITS[cap], PIXEL_LIMITS[px],
+                              jr.Schedule(**e["schedule"]))
+        n += 1
+    return n
+
+
 def apply_cache(cache: Dict[str, dict], max_iter: int = 100, pixels: int = 1 << 24):
     """Install cached schedules for (dtype, max_iter, pixels) as library defaults."""
     for dt in ("fp64", "fp32", "ff"):

@@ -167,6 +167,43 @@ jr_schedule default_schedule(int dtype) {
     return g_default[dtype];
 }
 
+// Schedules of one-image calls by size (jr_set_image_schedule).
+struct ImageSchedule {
+    int32_t dtype;
+    int32_t max_iter_limit;
+    int64_t pixels_limit;
+    jr_schedule s;
+};
+constexpr size_t kMaxImageSchedules = 64;
+std::vector<ImageSchedule> g_image;
+
+// The entry of this dtype with the smallest cap limit covering max_iter and,
+// among those, the smallest pixel limit covering px; when no pixel limit
+// covers px, the largest one below it; otherwise the dtype's default.
+jr_schedule image_schedule(int dtype, int32_t max_iter, int64_t px) {
+    std::lock_guard<std::mutex> g(g_sched_mu);
+    const ImageSchedule* best = nullptr;
+    for (const ImageSchedule& e : g_image) {
+        if (e.dtype != dtype || max_iter > e.max_iter_limit) continue;
+        if (!best) {
+            best = &e;
+            continue;
+        }
+        if (e.max_iter_limit != best->max_iter_limit) {
+            if (e.max_iter_limit < best->max_iter_limit) best = &e;
+            continue;
+        }
+        const bool e_covers = px <= e.pixels_limit, b_covers = px <= best->pixels_limit;
+        if (e_covers != b_covers) {
+            if (e_covers) best = &e;
+        } else if (e_covers ? e.pixels_limit < best->pixels_limit
+                            : e.pixels_limit > best->pixels_limit) {
+            best = &e;
+        }
+    }
+    return best ? best->s : g_default[dtype];
+}
+
 // ------------------------------------------------------------- frame table
 double dtype_cost(int dtype) {
     // Relative cost of one pixel-iteration (vector-ALU instructions).
@@ -489,13 +526,19 @@ jr_frame single_frame(jr_complex c, jr_window w, int32_t W, int32_t H, int32_t m
     return f;
 }
 
+int render_plain(jr_complex c, jr_window w, int32_t W, int32_t H, int32_t max_iter,
+                 int32_t dtype, int32_t mode, int32_t* out, void* stream, const char* who);
+
 int render_one(jr_complex c, jr_window w, int32_t W, int32_t H, int32_t max_iter, int32_t dtype,
                int32_t mode, int32_t* out, void* stream, const char* who) {
     int rc = check_image(W, H, max_iter, dtype, mode, c, w, who);
     if (rc) return rc;
     if ((rc = check_out(out, who))) return rc;
+    jr_schedule s = image_schedule(dtype, max_iter, (int64_t)W * H);
+    // one image on the one-thread-per-pixel kernel: its 2-D grid form
+    if (s.kernel == JR_KERNEL_PLAIN) return render_plain(c, w, W, H, max_iter, dtype, mode, out,
+                                                         stream, who);
     jr_frame f = single_frame(c, w, W, H, max_iter, dtype, mode);
-    jr_schedule s = default_schedule(dtype);
     return enqueue_batch(&f, 1, out, (int64_t)W * H, &s, (hipStream_t)stream);
 }
 
@@ -508,7 +551,7 @@ int render_one_colored(jr_complex c, jr_window w, int32_t W, int32_t H, int32_t 
     if ((rc = check_out(out, who))) return rc;
     if ((rc = check_palette(palette, palette_len, true, who))) return rc;
     jr_frame f = single_frame(c, w, W, H, max_iter, dtype, JR_JULIA);
-    jr_schedule s = default_schedule(dtype);
+    jr_schedule s = image_schedule(dtype, max_iter, (int64_t)W * H);
     return enqueue_batch(&f, 1, reinterpret_cast<int32_t*>(out), (int64_t)W * H, &s,
                          (hipStream_t)stream, palette, palette_len);
 }
@@ -584,6 +627,40 @@ int jr_get_default_schedule(int32_t dtype, int32_t max_iter, jr_schedule* out) {
     if (dtype < 0 || dtype > 2) return fail(JR_EINVAL, "unknown dtype %d", dtype);
     *out = default_schedule(dtype);
     return JR_OK;
+}
+
+int jr_set_image_schedule(int32_t dtype, int32_t max_iter_limit, int64_t pixels_limit,
+                          const jr_schedule* s) {
+    if (!s) return fail(JR_EINVAL, "schedule is null");
+    if (dtype < 0 || dtype > 2) return fail(JR_EINVAL, "unknown dtype %d", dtype);
+    if (max_iter_limit < 0 || pixels_limit < 1)
+        return fail(JR_EINVAL, "limits must be max_iter_limit >= 0, pixels_limit >= 1");
+    int rc = check_schedule(*s);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> g(g_sched_mu);
+    for (ImageSchedule& e : g_image) {
+        if (e.dtype == dtype && e.max_iter_limit == max_iter_limit &&
+            e.pixels_limit == pixels_limit) {
+            e.s = *s;
+            return JR_OK;
+        }
+    }
+    if (g_image.size() >= kMaxImageSchedules)
+        return fail(JR_EINVAL, "at most %d image schedules", (int)kMaxImageSchedules);
+    g_image.push_back(ImageSchedule{dtype, max_iter_limit, pixels_limit, *s});
+    return JR_OK;
+}
+
+int jr_get_image_schedule(int32_t dtype, int32_t max_iter, int64_t pixels, jr_schedule* out) {
+    if (!out) return fail(JR_EINVAL, "out is null");
+    if (dtype < 0 || dtype > 2) return fail(JR_EINVAL, "unknown dtype %d", dtype);
+    *out = image_schedule(dtype, max_iter, pixels);
+    return JR_OK;
+}
+
+void jr_clear_image_schedules(void) {
+    std::lock_guard<std::mutex> g(g_sched_mu);
+    g_image.clear();
 }
 
 int jr_set_default_schedule(int32_t dtype, const jr_schedule* s) {

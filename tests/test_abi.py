@@ -194,3 +194,38 @@ def test_colored_batch_validates_frames_and_plan_palette():
     assert jr.lib.jr_plan_set_palette(None, FAKE_PAL, 4) == jr.JR_EINVAL
     assert jr.PALETTE_MAX == 8192
     assert "#define JR_PALETTE_MAX 8192" in open(HEADER).read()
+
+
+def test_image_schedules_pick_by_cap_and_size():
+    """The per-size table of one-image calls (jr_set_image_schedule), queried
+    without a device."""
+    jr.lib.jr_clear_image_schedules()
+    try:
+        dflt = jr.default_schedule("fp32")
+        assert jr.image_schedule("fp32", 100, 10 ** 6) == dflt
+        small = jr.Schedule(64, 1, 8, 0, 64, 0, 16, "cost")
+        mid = jr.Schedule(64, 8, 8, 0, 32, 0, 16, "cost", "rows", 6)
+        deep = jr.Schedule(kernel="plain")
+        jr.set_image_schedule("fp32", 128, (1 << 20) - 1, small)
+        jr.set_image_schedule("fp32", 128, (64 << 20) - 1, mid)
+        jr.set_image_schedule("fp32", 1024, (64 << 20) - 1, deep)
+        assert jr.image_schedule("fp32", 100, 512 * 512) == small
+        assert jr.image_schedule("fp32", 100, 4096 * 4096) == mid
+        assert jr.image_schedule("fp32", 100, 10 ** 8) == mid      # largest below
+        assert jr.image_schedule("fp32", 1000, 512 * 512) == deep  # only cap-1024 entry
+        assert jr.image_schedule("fp32", 5000, 512 * 512) == dflt  # no cap covers it
+        assert jr.image_schedule("fp64", 100, 512 * 512) == jr.default_schedule("fp64")
+        jr.set_image_schedule("fp32", 128, (1 << 20) - 1, mid)      # replaces
+        assert jr.image_schedule("fp32", 100, 512 * 512) == mid
+        bad = jr.Schedule(tile_w=0).to_c()
+        assert jr.lib.jr_set_image_schedule(1, 128, 100, ctypes.byref(bad)) == jr.JR_EINVAL
+        ok = mid.to_c()
+        assert jr.lib.jr_set_image_schedule(3, 128, 100, ctypes.byref(ok)) == jr.JR_EINVAL
+        assert jr.lib.jr_set_image_schedule(1, -1, 100, ctypes.byref(ok)) == jr.JR_EINVAL
+        assert jr.lib.jr_set_image_schedule(1, 128, 0, ctypes.byref(ok)) == jr.JR_EINVAL
+        assert jr.lib.jr_set_image_schedule(1, 128, 100, None) == jr.JR_EINVAL
+        for k in range(64 - 3):
+            assert jr.lib.jr_set_image_schedule(2, k, 100, ctypes.byref(ok)) == jr.JR_OK
+        assert jr.lib.jr_set_image_schedule(2, 999, 100, ctypes.byref(ok)) == jr.JR_EINVAL
+    finally:
+        jr.lib.jr_clear_image_schedules()
