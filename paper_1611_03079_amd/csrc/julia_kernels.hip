@@ -1078,6 +1078,9 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
     const typename A::C cj = A::cmake(A::coord(F.cr), A::coord(F.ci));
     int32_t* tout = a.out_base + F.out_offset + ((int64_t)row0 * W + col0);
     const bool col_ok = lane < tw;
+    // survivors of phase 1 have lead >= p_lane; lanes past the tile and caps
+    // within P have none
+    const int p_lane = (col_ok && P < mi) ? P : 0x7fffffff;
     uint16_t* pos = (uint16_t*)(list + ZW * cap);
 
     // phase 1
@@ -1111,10 +1114,13 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
             }
         }
         if (more && u < P) lead += A::check_step(z, c, deg) ? 1 : 0;
-        const bool fin = col_ok && (lead < P || P >= mi);
-        if (fin) store_at(tout + (int64_t)r * W, lane, shade<COLOR>(a, min(lead, mi)));
-        const bool sv = col_ok && !fin;
+        // A pixel survives when it is inside for all P iterates (lead = P)
+        // and the cap lies beyond P; one compare against the lane's bound
+        // gives the survivors' mask directly.
+        const bool sv = lead >= p_lane;
+        const bool fin = col_ok && !sv;
         const uint64_t m = __ballot(sv);
+        if (fin) store_at(tout + (int64_t)r * W, lane, shade<COLOR>(a, min(lead, mi)));
         if (sv) {
             const int e = qn + lanes_below(m);
             list_put<A>(list, cap, e, z);
