@@ -134,9 +134,9 @@ typedef struct {
  *                   continue in refilled blocks (they wait in shared memory).
  *                   JR_KERNEL_ROWS: each wave takes a tile row by row (lane
  *                   = column); every pixel of a row first runs `bail` counted
- *                   iterations (rounded up to even; a row stops early once
- *                   all its pixels have escaped) with no exchange between
- *                   lanes, pixels that finish store at once, and the others wait in a per-wave
+ *                   iterations (rounded up to a multiple of 4; a row stops
+ *                   early once all its pixels have escaped) with no exchange
+ *                   between lanes, pixels that finish store at once, and the others wait in a per-wave
  *                   list in shared memory, which the wave then drains with
  *                   refilled counted blocks of `unroll` (4 or 8, defer 0).
  *                   tile_h is capped at 8 rows for batches of FP32 frames

@@ -35,7 +35,7 @@ TILES = [(64, 1), (64, 4), (64, 16), (32, 8), (16, 16), (64, 64)]
 REFILLS = [8, 16, 32, 64]
 WAVES = [8, 16, 24, 32]
 HYBRID_BAILS = [4, 8, 16, 32]
-ROWS_FIRST = [4, 6, 8, 12, 16]
+ROWS_FIRST = [4, 8, 12, 16, 20, 24]
 
 DEFAULT_CACHE = os.environ.get(
     "JR_AUTOTUNE_CACHE",

@@ -1100,12 +1100,15 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
         if (K == 1) {
             lead = A::check_step(z, c, deg) ? 1 : 0;  // P = 1: the exact test
         } else {
-            // Two iterations per trip (P is even here); the row stops early
-            // once every lane's pixel has escaped (absorbing: later iterates
-            // would count nothing).  Lanes past the tile's width repeat its
-            // last column, so they never hold the row back on their own.
+            // Four iterations per trip (P is a multiple of 4 here); the row
+            // stops early once every lane's pixel has escaped (absorbing:
+            // later iterates would count nothing).  Lanes past the tile's
+            // width repeat its last column, so they never hold the row back
+            // on their own.
 #pragma unroll 1
-            for (int u = 0; u < P; u += 2) {
+            for (int u = 0; u < P; u += 4) {
+                lead += A::check_step(z, c, deg) ? 1 : 0;
+                lead += A::check_step(z, c, deg) ? 1 : 0;
                 lead += A::check_step(z, c, deg) ? 1 : 0;
                 const bool in = A::check_step(z, c, deg);
                 lead += in ? 1 : 0;
@@ -1187,8 +1190,8 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
 
 // Waves of 64 lanes, one tile at a time (from the dispatcher or the work
 // queues), each tile in two phases (rows_tile).  P, the first block's length,
-// is the schedule's bail field rounded up to even; K is the second phase's
-// block length.
+// is the schedule's bail field rounded up to a multiple of 4; K is the second
+// phase's block length.
 template <int K, int DTMASK>
 __global__ __launch_bounds__(256) void jr_rows(PersistentArgs a) {
     constexpr int COLOR = (DTMASK & kColorBit) ? 1 : 0;
@@ -1205,11 +1208,12 @@ __global__ __launch_bounds__(256) void jr_rows(PersistentArgs a) {
         f = find_frame(frames, a.nframes, t, f);
         CFrame& F = frames[f];
         const bool abs = F.defer != 0;
-        // The first block's length: the schedule's, rounded up to even (two
-        // iterations per trip), or 1 where escape may not be absorbing.
+        // The first block's length: the schedule's, rounded up to a multiple
+        // of 4 (four iterations per trip), or 1 where escape may not be
+        // absorbing.
         // Wave-uniform; readfirstlane says so to the compiler, which otherwise
         // may keep the trip count in a vector register.
-        const int P = __builtin_amdgcn_readfirstlane(abs ? (a.bail + 1) & ~1 : 1);
+        const int P = __builtin_amdgcn_readfirstlane(abs ? (a.bail + 3) & ~3 : 1);
         const bool mandel = F.mode == kModeMandelbrot;
 #define JR_ROWS(A_)                                                                      \
     do {                                                                                 \
