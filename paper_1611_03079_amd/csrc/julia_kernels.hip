@@ -1085,10 +1085,8 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
 
     // phase 1
     int qn = 0;
-    for (int r = 0; r < th; ++r) {
+    auto start_row = [&](int r, typename A::Z& z, typename A::C& c) {
         const V y = bcast<A>(yl, r);
-        typename A::Z z;
-        typename A::C c;
         if (MANDEL) {
             z = A::make(zero, zero);
             c = A::cmake(xl, y);
@@ -1096,28 +1094,11 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
             z = A::make(xl, y);
             c = cj;
         }
-        int lead = 0;
-        if (K == 1) {
-            lead = A::check_step(z, c, deg) ? 1 : 0;  // P = 1: the exact test
-        } else {
-            // Four iterations per trip (P is a multiple of 4 here); the row
-            // stops early once every lane's pixel has escaped (absorbing:
-            // later iterates would count nothing).  Lanes past the tile's
-            // width repeat its last column, so they never hold the row back
-            // on their own.
-#pragma unroll 1
-            for (int u = 0; u < P; u += 4) {
-                lead += A::check_step(z, c, deg) ? 1 : 0;
-                lead += A::check_step(z, c, deg) ? 1 : 0;
-                lead += A::check_step(z, c, deg) ? 1 : 0;
-                const bool in = A::check_step(z, c, deg);
-                lead += in ? 1 : 0;
-                if (__ballot(in) == 0) break;
-            }
-        }
-        // A pixel survives when it is inside for all P iterates (lead = P)
-        // and the cap lies beyond P; one compare against the lane's bound
-        // gives the survivors' mask directly.
+    };
+    // A pixel survives when it is inside for all P iterates (lead = P) and the
+    // cap lies beyond P; one compare against the lane's bound gives the
+    // survivors' mask directly.  Finished pixels store, survivors append.
+    auto finish_row = [&](int r, int lead, const typename A::Z& z) {
         const bool sv = lead >= p_lane;
         const bool fin = col_ok && !sv;
         const uint64_t m = __ballot(sv);
@@ -1128,6 +1109,57 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
             pos[e] = (uint16_t)((r << 6) | lane);
         }
         qn += __popcll(m);
+    };
+    int r = 0;
+    if (K != 1) {
+        // Two rows at a time, four iterations per trip (P is a multiple of 4
+        // here): two independent orbits per lane keep the pipeline full.  The
+        // pair stops early once every lane's pixels in both rows have
+        // escaped (absorbing: later iterates would count nothing).  Lanes
+        // past the tile's width repeat its last column, so they never hold
+        // the rows back on their own.
+        for (; r + 2 <= th; r += 2) {
+            typename A::Z z0, z1;
+            typename A::C c0, c1;
+            start_row(r, z0, c0);
+            start_row(r + 1, z1, c1);
+            int l0 = 0, l1 = 0;
+#pragma unroll 1
+            for (int u = 0; u < P; u += 4) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    l0 += A::check_step(z0, c0, deg) ? 1 : 0;
+                    l1 += A::check_step(z1, c1, deg) ? 1 : 0;
+                }
+                const bool in0 = A::check_step(z0, c0, deg);
+                const bool in1 = A::check_step(z1, c1, deg);
+                l0 += in0 ? 1 : 0;
+                l1 += in1 ? 1 : 0;
+                if (__ballot(in0 || in1) == 0) break;
+            }
+            finish_row(r, l0, z0);
+            finish_row(r + 1, l1, z1);
+        }
+    }
+    for (; r < th; ++r) {  // the last row of an odd tile height, or P = 1
+        typename A::Z z;
+        typename A::C c;
+        start_row(r, z, c);
+        int lead = 0;
+        if (K == 1) {
+            lead = A::check_step(z, c, deg) ? 1 : 0;  // P = 1: the exact test
+        } else {
+#pragma unroll 1
+            for (int u = 0; u < P; u += 4) {
+                lead += A::check_step(z, c, deg) ? 1 : 0;
+                lead += A::check_step(z, c, deg) ? 1 : 0;
+                lead += A::check_step(z, c, deg) ? 1 : 0;
+                const bool in = A::check_step(z, c, deg);
+                lead += in ? 1 : 0;
+                if (__ballot(in) == 0) break;
+            }
+        }
+        finish_row(r, lead, z);
     }
     // Other lanes read the entries written above: keep the compiler from
     // moving LDS accesses across this point (one wave runs them in order).
