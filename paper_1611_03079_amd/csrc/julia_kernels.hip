@@ -36,6 +36,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "julia_device.h"
 
 namespace jr {
@@ -1111,7 +1113,10 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
         qn += __popcll(m);
     };
     int r = 0;
-    if (K != 1) {
+    // Pairs for the quadratic FP32 and FP64 maps; float-float and the general
+    // maps hold too much state per orbit (registers would cost resident waves).
+    constexpr bool kPairs = std::is_same<A, ArF32>::value || std::is_same<A, ArF64>::value;
+    if (K != 1 && kPairs) {
         // Two rows at a time, four iterations per trip (P is a multiple of 4
         // here): two independent orbits per lane keep the pipeline full.  The
         // pair stops early once every lane's pixels in both rows have
@@ -1141,7 +1146,7 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
             finish_row(r + 1, l1, z1);
         }
     }
-    for (; r < th; ++r) {  // the last row of an odd tile height, or P = 1
+    for (; r < th; ++r) {  // single rows: an odd tile height's last, P = 1, wide types
         typename A::Z z;
         typename A::C c;
         start_row(r, z, c);
