@@ -136,11 +136,11 @@ typedef struct {
  *                   = column); every pixel of a row first runs `bail` counted
  *                   iterations (rounded up to a multiple of 4; a row stops
  *                   early once all its pixels have escaped) with no exchange
- *                   between lanes, pixels that finish store at once, and the others wait in a per-wave
- *                   list in shared memory, which the wave then drains with
- *                   refilled counted blocks of `unroll` (4 or 8, defer 0).
- *                   tile_h is capped at 8 rows for batches of FP32 frames
- *                   only, 4 otherwise (the list's size).
+ *                   between lanes.  Pixels that finish store at once; the
+ *                   others wait in a per-wave list in shared memory, which
+ *                   the wave drains with refilled counted blocks of `unroll`
+ *                   (4 or 8, defer 0) whenever it could not take the next
+ *                   rows' survivors, and at the end of the tile.
  *   bail            JR_KERNEL_HYBRID: 1..4096; JR_KERNEL_ROWS: 1..64 (other
  *                   kernels ignore it).
  */

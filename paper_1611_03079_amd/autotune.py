@@ -135,7 +135,8 @@ def tune(frames: Sequence, base: Optional[jr.Schedule] = None, reps: int = 3,
                singles)
     r = _stage(frames, r, [dict(persistent=p, refill=rf, waves_per_cu=w, tile_w=tw, tile_h=th)
                            for p in (1, 0) for rf in (8, 16, 32) for w in (16, 32)
-                           for tw, th in ((64, 8), (64, 4), (32, 8))], reps, log, singles)
+                           for tw, th in ((64, 8), (64, 16), (64, 32), (64, 64), (32, 16))],
+               reps, log, singles)
     r = _stage(frames, r, [dict(bail=p) for p in ROWS_FIRST], reps, log, singles)
     t = min(tt for d, tt in log if jr.Schedule(**d) == r)
     if t < best_t:

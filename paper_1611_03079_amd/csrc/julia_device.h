@@ -60,10 +60,11 @@ struct PersistentArgs {
 
 // Largest colour table of the fused colour store; it is staged in LDS.
 constexpr int kPaletteMax = 8192;
-// Row-packet kernel: rows of a tile a wave's survivor list holds (64 pixels
-// each): 8 for FP32-only launches (20 KiB of LDS per 4-wave workgroup, so 8
-// workgroups fit a CU), 4 when FP64 or float-float frames are in (18 KiB).
-// Larger lists cost more in resident waves than they save in drains.
+// Row-packet kernel: a wave's survivor list holds this many rows' worth of
+// pixels (64 each): 8 for FP32-only launches (512 entries, 20 KiB of LDS per
+// 4-wave workgroup, so 8 workgroups fit a CU), 4 when FP64, float-float or
+// general-map frames are in (18 KiB).  The list is drained whenever it could
+// not take the next rows' survivors, so tiles may be taller than the list.
 constexpr int kRowsFP32 = 8;
 constexpr int kRowsWide = 4;
 // Kernel variants that store colours carry this bit beside the dtype bits
@@ -83,9 +84,7 @@ struct PlainArgs {
 hipError_t launch_tiled(int unroll, int defer, int dtmask, int blocks, const PersistentArgs& args,
                         hipStream_t stream);
 hipError_t launch_plain(int dtype, const PlainArgs& args, hipStream_t stream);
-// Tile rows the rows kernel for a launch of this dtype mask (dtype bits and
-// kGeneralBit) can hold.
-int rows_capacity(int dtmask);
+
 // One thread per pixel over the frame table (tiles of 16 x 16, one workgroup each).
 hipError_t launch_plain_batch(int dtmask, const PersistentArgs& args, hipStream_t stream);
 

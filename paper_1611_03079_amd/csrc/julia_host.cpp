@@ -275,16 +275,6 @@ void build_table(const jr_frame* frames, int32_t n, const jr_schedule& s, Table&
     t.rows.resize(n);
     t.total_tiles = 0;
     t.dtmask = 0;
-    // The rows kernel's per-wave list holds a fixed number of tile rows.
-    int32_t rows_cap = 64;
-    if (s.kernel == JR_KERNEL_ROWS) {
-        int mask = 0;
-        for (int32_t k = 0; k < n; ++k) {
-            mask |= 1 << frames[k].dtype;
-            if (frames[k].degree > 2) mask |= jr::kGeneralBit;
-        }
-        rows_cap = jr::rows_capacity(mask);
-    }
     for (int32_t k = 0; k < n; ++k) {
         const jr_frame& f = frames[idx[k]];
         DevFrame& d = t.rows[k];
@@ -307,7 +297,7 @@ void build_table(const jr_frame* frames, int32_t n, const jr_schedule& s, Table&
         d.row_begin = f.row_begin;
         d.row_end = f.row_end == 0 ? f.height : f.row_end;
         const int32_t tw = s.kernel == JR_KERNEL_PLAIN ? 16 : s.tile_w;
-        const int32_t th = s.kernel == JR_KERNEL_PLAIN ? 16 : std::min(s.tile_h, rows_cap);
+        const int32_t th = s.kernel == JR_KERNEL_PLAIN ? 16 : s.tile_h;
         d.tile_w = std::min(tw, f.width);
         d.tile_h = std::min(th, d.row_end - d.row_begin);
         d.tiles_x = (f.width + d.tile_w - 1) / d.tile_w;

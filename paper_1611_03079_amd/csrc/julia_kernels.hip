@@ -986,7 +986,7 @@ __global__ __launch_bounds__(256) void jr_plain_batch(PersistentArgs a) {
 // ---------------------------------------------------------------------------
 // Most pixels of a light image escape within a few iterations, and in the
 // refill stream each of them still costs a block of K iterations and a share of
-// a refill round.  Here a wave takes its tile (at most 64 columns, lane L =
+// a refill round.  Here a wave takes its tile (at most 64 x 64, lane L =
 // column L) row by row:
 //   phase 1  every lane runs its pixel of the row for P counted iterations,
 //            without branches; the row's coordinate is one value for the whole
@@ -995,16 +995,18 @@ __global__ __launch_bounds__(256) void jr_plain_batch(PersistentArgs a) {
 //            store their count at once, one coalesced row store;
 //   survivors append their iterate (Z_P) and position to the wave's list in
 //            LDS (stored one array per word, so lanes hit distinct banks);
-//   phase 2  once the tile's rows are done, the wave drains the list with the
-//            refill stream in counted blocks of K: idle lanes read the next
-//            entries straight from the list, and C is the frame's constant.
+//   phase 2  whenever the list could not take the next rows' survivors, and
+//            at the end of the tile, the wave drains it with the refill stream
+//            in counted blocks of K: idle lanes read the next entries straight
+//            from the list, and C is the frame's constant.  A drain usually
+//            holds several wave-loads of survivors, so the lanes left idle
+//            while its last orbits finish cost little.
 // Counts: phase 1 counts the leading non-escaped iterates of Z_0..Z_{P-1}; with
 // escape absorbing (|C| <= 1.9) that is min(count, P), so a pixel with fewer
 // than P is final and the others continue from Z_P with n = P.  A row whose
 // pixels have all escaped stops before P: the iterates it skips would count
-// nothing.  Frames where
-// escape may not be absorbing run P = 1 and K = 1, the exact test on every
-// iteration.
+// nothing.  Frames where escape may not be absorbing run P = 1 and K = 1, the
+// exact test on every iteration.
 template <int DTMASK>
 struct RowsShape {
     static constexpr int kMask = DTMASK & 7;
@@ -1060,7 +1062,7 @@ __device__ __forceinline__ typename A::Z list_get(const uint32_t* list, int cap,
 // follows the iterate words.
 template <class A, int K, int MANDEL, int COLOR>
 __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, uint32_t* list,
-                          int cap, int rows_max) {
+                          int cap) {
     using V = typename A::V;
     constexpr int ZW = (int)(sizeof(typename A::Z) / 4);
     const uint32_t local = (uint32_t)(t - F.tile_begin);
@@ -1069,7 +1071,7 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
     const int col0 = tx * F.tile_w;
     const int row0 = F.row_begin + ty * F.tile_h;
     const int tw = min(F.tile_w, F.width - col0);
-    const int th = min(min(F.tile_h, F.row_end - row0), rows_max);
+    const int th = min(F.tile_h, F.row_end - row0);  // at most 64 (one row per lane of yl)
     const int W = __builtin_amdgcn_readfirstlane(F.width);
     const int mi = __builtin_amdgcn_readfirstlane(F.max_iter);
     const int deg = __builtin_amdgcn_readfirstlane(F.degree);
@@ -1112,6 +1114,68 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
         }
         qn += __popcll(m);
     };
+    // Phase 2: the refill stream over the list's entries, in counted blocks of
+    // K; idle lanes read the next entries straight from the list, and C is
+    // the frame's constant.  It runs whenever the list could not take the
+    // next rows' survivors, and at the end of the tile, so a drain usually
+    // holds several wave-loads of survivors and its tail stays short.
+    auto drain = [&]() {
+        if (qn == 0) return;
+        // Other lanes read the entries written above, and the next rows
+        // overwrite them afterwards: keep the compiler from moving LDS
+        // accesses across either point (one wave runs them in order).
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        bool it = false, fi = false;
+        int n = 0, cnt = 0, off = 0;
+        typename A::Z z = A::make(zero, zero);
+        typename A::C c = cj;
+        int next = 0;
+        uint64_t running = 0;
+        const int busy_max = 64 - a.refill;
+        for (;;) {
+            if (__popcll(running) <= busy_max) {
+                if (fi) {
+                    store_at(tout, off, shade<COLOR>(a, cnt));
+                    fi = false;
+                }
+                if (next < qn) {
+                    const uint64_t idle = ~running;
+                    const int e = next + lanes_below(idle);
+                    const int ee = min(e, qn - 1);
+                    const typename A::Z zl = list_get<A>(list, cap, ee);
+                    const uint32_t id = pos[ee];
+                    const int r = (int)(id >> 6);
+                    const int col = (int)(id & 63u);
+                    V cx = zero, cy = zero;
+                    if (MANDEL) {
+                        cx = A::shfl(xl, col);
+                        cy = A::shfl(yl, r);
+                    }
+                    if (!it && e < qn) {
+                        z = zl;
+                        if (MANDEL) c = A::cmake(cx, cy);
+                        off = r * W + col;
+                        n = P;
+                        it = true;
+                    }
+                    next += __popcll(idle);
+                }
+                running = __ballot(it);
+                if (running == 0) break;
+            }
+            int lead = 0;
+#pragma unroll
+            for (int u = 0; u < K; ++u) lead += A::check_step(z, c, deg) ? 1 : 0;
+            const bool stop = (lead < K) || (n + K >= mi);
+            cnt = (it && stop) ? min(n + lead, mi) : cnt;
+            fi = fi || (it && stop);
+            it = it && !stop;
+            n += K;
+            running = __ballot(it);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        qn = 0;
+    };
     int r = 0;
     // Pairs for the quadratic FP32 and FP64 maps; float-float and the general
     // maps hold too much state per orbit (registers would cost resident waves).
@@ -1124,6 +1188,7 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
         // past the tile's width repeat its last column, so they never hold
         // the rows back on their own.
         for (; r + 2 <= th; r += 2) {
+            if (qn + 128 > cap) drain();  // room for two rows' survivors
             typename A::Z z0, z1;
             typename A::C c0, c1;
             start_row(r, z0, c0);
@@ -1147,6 +1212,7 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
         }
     }
     for (; r < th; ++r) {  // single rows: an odd tile height's last, P = 1, wide types
+        if (qn + 64 > cap) drain();  // room for one row's survivors
         typename A::Z z;
         typename A::C c;
         start_row(r, z, c);
@@ -1166,63 +1232,7 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
         }
         finish_row(r, lead, z);
     }
-    // Other lanes read the entries written above: keep the compiler from
-    // moving LDS accesses across this point (one wave runs them in order).
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-
-    // phase 2
-    bool it = false, fi = false;
-    int n = 0, cnt = 0, off = 0;
-    typename A::Z z = A::make(zero, zero);
-    typename A::C c = cj;
-    int next = 0;
-    uint64_t running = 0;
-    const int busy_max = 64 - a.refill;
-    for (;;) {
-        if (__popcll(running) <= busy_max) {
-            if (fi) {
-                store_at(tout, off, shade<COLOR>(a, cnt));
-                fi = false;
-            }
-            if (next < qn) {
-                const uint64_t idle = ~running;
-                const int e = next + lanes_below(idle);
-                const int ee = min(e, qn - 1);
-                const typename A::Z zl = list_get<A>(list, cap, ee);
-                const uint32_t id = pos[ee];
-                const int r = (int)(id >> 6);
-                const int col = (int)(id & 63u);
-                V cx = zero, cy = zero;
-                if (MANDEL) {
-                    cx = A::shfl(xl, col);
-                    cy = A::shfl(yl, r);
-                }
-                if (!it && e < qn) {
-                    z = zl;
-                    if (MANDEL) c = A::cmake(cx, cy);
-                    off = r * W + col;
-                    n = P;
-                    it = true;
-                }
-                next += __popcll(idle);
-            }
-            running = __ballot(it);
-            if (running == 0) {
-                // the next tile's first phase overwrites entries read here
-                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-                return;
-            }
-        }
-        int lead = 0;
-#pragma unroll
-        for (int u = 0; u < K; ++u) lead += A::check_step(z, c, deg) ? 1 : 0;
-        const bool stop = (lead < K) || (n + K >= mi);
-        cnt = (it && stop) ? min(n + lead, mi) : cnt;
-        fi = fi || (it && stop);
-        it = it && !stop;
-        n += K;
-        running = __ballot(it);
-    }
+    drain();
 }
 
 // Waves of 64 lanes, one tile at a time (from the dispatcher or the work
@@ -1254,10 +1264,10 @@ __global__ __launch_bounds__(256) void jr_rows(PersistentArgs a) {
         const bool mandel = F.mode == kModeMandelbrot;
 #define JR_ROWS(A_)                                                                      \
     do {                                                                                 \
-        if (abs && !mandel) rows_tile<A_, K, 0, COLOR>(a, F, t, P, list, cap, S::rows);  \
-        else if (abs) rows_tile<A_, K, 1, COLOR>(a, F, t, P, list, cap, S::rows);        \
-        else if (!mandel) rows_tile<A_, 1, 0, COLOR>(a, F, t, P, list, cap, S::rows);    \
-        else rows_tile<A_, 1, 1, COLOR>(a, F, t, P, list, cap, S::rows);                 \
+        if (abs && !mandel) rows_tile<A_, K, 0, COLOR>(a, F, t, P, list, cap);  \
+        else if (abs) rows_tile<A_, K, 1, COLOR>(a, F, t, P, list, cap);        \
+        else if (!mandel) rows_tile<A_, 1, 0, COLOR>(a, F, t, P, list, cap);    \
+        else rows_tile<A_, 1, 1, COLOR>(a, F, t, P, list, cap);                 \
     } while (0)
         if ((DTMASK & kGeneralBit) && F.degree > 2) {
             if (F.dtype == kFP32)
@@ -1330,13 +1340,6 @@ static TiledFn pick_block(int unroll, int defer, int dtmask) {
         case 8: return pick_mask<8, 0, HYB>(dtmask);
         default: return nullptr;
     }
-}
-
-// Tile rows the list of the rows kernel picked for `dtmask` holds (the host
-// caps tile_h with it; the kernel never writes past its list).
-int rows_capacity(int dtmask) {
-    return (dtmask & ~kColorBit) == (1 << kFP32) ? RowsShape<1 << kFP32>::rows
-                                                 : RowsShape<7 | kGeneralBit>::rows;
 }
 
 template <int K>

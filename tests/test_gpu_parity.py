@@ -40,6 +40,7 @@ SCHEDULES = [
     jr.Schedule(37, 5, 4, 0, 32, 1, 8, "table", "rows", 2),   # ragged tiles, work queues
     jr.Schedule(64, 64, 8, 0, 8, 0, 16, "cost", "rows", 1),   # tile height clamped
     jr.Schedule(1, 1, 4, 0, 1, 1, 4, "cost", "rows", 64),     # one-pixel tiles, long first block
+    jr.Schedule(64, 64, 4, 0, 8, 1, 8, "table", "rows", 8),   # several list drains per tile
 ]
 
 
