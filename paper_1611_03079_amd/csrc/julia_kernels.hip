@@ -1238,14 +1238,20 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
 // Waves of 64 lanes, one tile at a time (from the dispatcher or the work
 // queues), each tile in two phases (rows_tile).  P, the first block's length,
 // is the schedule's bail field rounded up to a multiple of 4; K is the second
-// phase's block length.
-template <int K, int DTMASK>
-__global__ __launch_bounds__(256) void jr_rows(PersistentArgs a) {
+// phase's block length.  WPB is the number of waves per workgroup: 4 for the
+// work queues and the colour store (whose palette the workgroup shares), 1
+// for dispatched tiles, so that a wave's LDS is released as soon as its own
+// tile is done instead of when the slowest of four tiles is.
+template <int K, int DTMASK, int WPB>
+__global__ __launch_bounds__(64 * WPB) void jr_rows(PersistentArgs a) {
     constexpr int COLOR = (DTMASK & kColorBit) ? 1 : 0;
+    static_assert(WPB == 4 || (WPB == 1 && !COLOR), "one-wave workgroups carry no palette");
     using S = RowsShape<DTMASK>;
     constexpr int cap = 64 * S::rows;
-    __shared__ uint32_t lmem[4 * S::wave_words];
-    uint32_t* list = lmem + (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * S::wave_words;
+    __shared__ uint32_t lmem[WPB * S::wave_words];
+    uint32_t* list =
+        WPB == 1 ? lmem
+                 : lmem + (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * S::wave_words;
     stage_palette<COLOR>(a);
     Claimer cl;
     claimer_init(cl, a);
@@ -1343,23 +1349,32 @@ static TiledFn pick_block(int unroll, int defer, int dtmask) {
 }
 
 template <int K>
-static TiledFn pick_rows_mask(int dtmask) {
+static TiledFn pick_rows_mask(int dtmask, bool one_wave) {
+    if (one_wave && !(dtmask & kColorBit)) {
+        if (dtmask & kGeneralBit) return jr_rows<K, 7 | kGeneralBit, 1>;
+        switch (dtmask) {
+            case 1 << kFP32: return jr_rows<K, 1 << kFP32, 1>;
+            case 1 << kFP64: return jr_rows<K, 1 << kFP64, 1>;
+            case 1 << kFF: return jr_rows<K, 1 << kFF, 1>;
+            default: return jr_rows<K, 7, 1>;
+        }
+    }
     if (dtmask & kGeneralBit)
-        return (dtmask & kColorBit) ? jr_rows<K, 7 | kGeneralBit | kColorBit>
-                                    : jr_rows<K, 7 | kGeneralBit>;
+        return (dtmask & kColorBit) ? jr_rows<K, 7 | kGeneralBit | kColorBit, 4>
+                                    : jr_rows<K, 7 | kGeneralBit, 4>;
     switch (dtmask) {
-        case 1 << kFP32: return jr_rows<K, 1 << kFP32>;
-        case 1 << kFP64: return jr_rows<K, 1 << kFP64>;
-        case 1 << kFF: return jr_rows<K, 1 << kFF>;
-        case (1 << kFP32) | kColorBit: return jr_rows<K, (1 << kFP32) | kColorBit>;
-        default: return (dtmask & kColorBit) ? jr_rows<K, 7 | kColorBit> : jr_rows<K, 7>;
+        case 1 << kFP32: return jr_rows<K, 1 << kFP32, 4>;
+        case 1 << kFP64: return jr_rows<K, 1 << kFP64, 4>;
+        case 1 << kFF: return jr_rows<K, 1 << kFF, 4>;
+        case (1 << kFP32) | kColorBit: return jr_rows<K, (1 << kFP32) | kColorBit, 4>;
+        default: return (dtmask & kColorBit) ? jr_rows<K, 7 | kColorBit, 4> : jr_rows<K, 7, 4>;
     }
 }
 
-static TiledFn pick_rows(int unroll, int dtmask) {
+static TiledFn pick_rows(int unroll, int dtmask, bool one_wave) {
     switch (unroll) {
-        case 4: return pick_rows_mask<4>(dtmask);
-        case 8: return pick_rows_mask<8>(dtmask);
+        case 4: return pick_rows_mask<4>(dtmask, one_wave);
+        case 8: return pick_rows_mask<8>(dtmask, one_wave);
         default: return nullptr;
     }
 }
@@ -1399,14 +1414,21 @@ hipError_t launch_plain_batch(int dtmask, const PersistentArgs& args, hipStream_
 hipError_t launch_tiled(int unroll, int defer, int dtmask, int blocks, const PersistentArgs& args,
                         hipStream_t stream) {
     if (args.palette_len > 0) dtmask |= kColorBit;
-    TiledFn fn = args.rows ? pick_rows(unroll, dtmask) : pick(unroll, defer, dtmask, args.hybrid);
+    // Dispatched rows tiles (one tile per wave, no palette) run in one-wave
+    // workgroups, one per tile.
+    const bool one_wave = args.rows && !args.persistent && !(dtmask & kColorBit) &&
+                          args.total_tiles <= 0x7fffffffLL;
+    if (one_wave) blocks = (int)args.total_tiles;
+    const unsigned threads = one_wave ? 64u : 256u;
+    TiledFn fn = args.rows ? pick_rows(unroll, dtmask, one_wave)
+                           : pick(unroll, defer, dtmask, args.hybrid);
     if (!fn || args.palette_len > kPaletteMax) return hipErrorInvalidValue;
     if (args.persistent) {
         hipLaunchKernelGGL(jr_reset_queues, dim3(1), dim3(kQueues), 0, stream, args.ctr);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), palette_bytes(args), stream, args);
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(threads), palette_bytes(args), stream, args);
     return hipGetLastError();
 }
 

@@ -38,7 +38,7 @@ SCHEDULES = [
     jr.Schedule(16, 16, 4, 0, 48, 0, 16, "cost", "hybrid", 1),
     jr.Schedule(64, 16, 8, 0, 16, 0, 16, "cost", "rows", 4),   # two phases per tile
     jr.Schedule(37, 5, 4, 0, 32, 1, 8, "table", "rows", 2),   # ragged tiles, work queues
-    jr.Schedule(64, 64, 8, 0, 8, 0, 16, "cost", "rows", 1),   # tile height clamped
+    jr.Schedule(64, 64, 8, 0, 8, 0, 16, "cost", "rows", 1),   # 64-row tiles, one-wave workgroups
     jr.Schedule(1, 1, 4, 0, 1, 1, 4, "cost", "rows", 64),     # one-pixel tiles, long first block
     jr.Schedule(64, 64, 4, 0, 8, 1, 8, "table", "rows", 8),   # several list drains per tile
 ]
