@@ -49,14 +49,14 @@ METRIC = "Gpixel-iters/s (FP64/FP32/float-float) vs plain kernel; p99 frame late
 # are in profiles/.  A kernel without an entry reports null.
 MEASURED_TRAFFIC_BYTES = {
     "jr_tiled<8, 0, 2, 0>": 2124197256,  # 662,559 B fetched + 2,123,534,697 B written
-    "jr_rows<8, 2>": 2165909152,  # 667,456 B fetched + 2,165,241,696 B written
 }
 
 # The kernel instance a schedule launches for an FP32-only batch that stores
 # counts (template arguments as rocprofv3 prints them).
 def kernel_instance(sched):
     if sched.kernel == "rows":
-        return "jr_rows<%d, 2>" % sched.unroll
+        # one-wave workgroups for dispatched tiles, four waves with the queues
+        return "jr_rows<%d, 2, %d>" % (sched.unroll, 4 if sched.persistent else 1)
     if sched.kernel == "plain":
         return "jr_plain_batch<2>"
     return "jr_tiled<%d, %d, 2, %d>" % (sched.unroll, sched.defer, int(sched.kernel == "hybrid"))

@@ -133,16 +133,23 @@ typedef struct {
  *                   only the pixels still running after `bail` iterations
  *                   continue in refilled blocks (they wait in shared memory).
  *                   JR_KERNEL_ROWS: each wave takes a tile row by row (lane
- *                   = column); every pixel of a row first runs `bail` counted
- *                   iterations (rounded up to a multiple of 4; a row stops
- *                   early once all its pixels have escaped) with no exchange
- *                   between lanes.  Pixels that finish store at once; the
- *                   others wait in a per-wave list in shared memory, which
- *                   the wave drains with refilled counted blocks of `unroll`
- *                   (4 or 8, defer 0) whenever it could not take the next
- *                   rows' survivors, and at the end of the tile.
+ *                   = column); every pixel of a row first runs up to `bail`
+ *                   counted iterations (rounded up to a multiple of 4), with
+ *                   no exchange between lanes.  Pixels that finish store at
+ *                   once; the others wait in a per-wave list in shared
+ *                   memory, which the wave drains with refilled counted
+ *                   blocks of `unroll` (4 or 8, defer 0) whenever it could
+ *                   not take the next rows' survivors, and at the end of the
+ *                   tile.
  *   bail            JR_KERNEL_HYBRID: 1..4096; JR_KERNEL_ROWS: 1..64 (other
  *                   kernels ignore it).
+ *   handoff         JR_KERNEL_ROWS, 0..128: rows run in pairs for FP32 and
+ *                   FP64 (quadratic maps), and a pair stops its first
+ *                   iterations, after a multiple of 4 of them, once at most
+ *                   `handoff` of its pixels are still inside the disc; those
+ *                   join the list with their count so far.  With 0 a pair
+ *                   stops once all its pixels have escaped.  Single rows
+ *                   always stop then.  Other kernels ignore it.
  */
 typedef enum {
     JR_KERNEL_TILED = 0,
@@ -160,6 +167,7 @@ typedef struct {
     int32_t order;
     int32_t kernel;
     int32_t bail;
+    int32_t handoff;
 } jr_schedule;
 
 /*

@@ -53,7 +53,8 @@ class jr_schedule(ctypes.Structure):
                 ("unroll", ctypes.c_int32), ("defer", ctypes.c_int32),
                 ("refill", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("waves_per_cu", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("kernel", ctypes.c_int32), ("bail", ctypes.c_int32)]
+                ("kernel", ctypes.c_int32), ("bail", ctypes.c_int32),
+                ("handoff", ctypes.c_int32)]
 
 
 assert ctypes.sizeof(jr_frame) == 88
@@ -72,18 +73,19 @@ class Schedule:
     order: str = "cost"
     kernel: str = "tiled"
     bail: int = 8
+    handoff: int = 0
 
     def to_c(self) -> jr_schedule:
         return jr_schedule(self.tile_w, self.tile_h, self.unroll, self.defer, self.refill,
                            self.persistent, self.waves_per_cu, ORDERS[self.order],
-                           KERNELS[self.kernel], self.bail)
+                           KERNELS[self.kernel], self.bail, self.handoff)
 
     @staticmethod
     def from_c(s: jr_schedule) -> "Schedule":
         inv = {v: k for k, v in ORDERS.items()}
         invk = {v: k for k, v in KERNELS.items()}
         return Schedule(s.tile_w, s.tile_h, s.unroll, s.defer, s.refill, s.persistent,
-                        s.waves_per_cu, inv[s.order], invk[s.kernel], s.bail)
+                        s.waves_per_cu, inv[s.order], invk[s.kernel], s.bail, s.handoff)
 
 
 EXPORTS = (

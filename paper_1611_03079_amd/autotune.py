@@ -35,7 +35,8 @@ TILES = [(64, 1), (64, 4), (64, 16), (32, 8), (16, 16), (64, 64)]
 REFILLS = [8, 16, 32, 64]
 WAVES = [8, 16, 24, 32]
 HYBRID_BAILS = [4, 8, 16, 32]
-ROWS_FIRST = [4, 8, 12, 16, 20, 24]
+ROWS_FIRST = [4, 8, 12, 16, 20, 24, 32, 48, 64]
+ROWS_HANDOFF = [0, 16, 32, 48]
 
 DEFAULT_CACHE = os.environ.get(
     "JR_AUTOTUNE_CACHE",
@@ -129,7 +130,8 @@ def tune(frames: Sequence, base: Optional[jr.Schedule] = None, reps: int = 3,
         if t < best_t:
             s, best_t = h, t
     # the two-phase row-packet kernel: first-block length x second block,
-    # then scheduling mode, refill and resident waves, then the first block again
+    # then scheduling mode, refill and resident waves, then the first block
+    # again with the pairs' handoff point
     r = jr.Schedule(64, 8, 8, 0, 16, 1, 32, s.order, "rows", 4)
     r = _stage(frames, r, [dict(bail=p, unroll=k) for p in ROWS_FIRST for k in (4, 8)], reps, log,
                singles)
@@ -137,7 +139,8 @@ def tune(frames: Sequence, base: Optional[jr.Schedule] = None, reps: int = 3,
                            for p in (1, 0) for rf in (8, 16, 32) for w in (16, 32)
                            for tw, th in ((64, 8), (64, 16), (64, 32), (64, 64), (32, 16))],
                reps, log, singles)
-    r = _stage(frames, r, [dict(bail=p) for p in ROWS_FIRST], reps, log, singles)
+    r = _stage(frames, r, [dict(bail=p, handoff=h) for p in ROWS_FIRST for h in ROWS_HANDOFF],
+               reps, log, singles)
     t = min(tt for d, tt in log if jr.Schedule(**d) == r)
     if t < best_t:
         s, best_t = r, t

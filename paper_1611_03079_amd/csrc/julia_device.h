@@ -53,7 +53,8 @@ struct PersistentArgs {
     int32_t bail;        // hybrid: iterations of a fresh packet before its survivors park;
                          // rows: length of the first counted block of every row
     int32_t rows;        // 1: two-phase row-packet kernel (jr_rows)
-    int32_t pad_;
+    int32_t handoff;     // rows: a row pair leaves its first block once at most
+                         // this many of its pixels are still inside
     int32_t palette_len; // > 0: a pixel stores palette[min(count, palette_len - 1)]
     const uint32_t* palette;
 };

@@ -122,6 +122,9 @@ int check_schedule(const jr_schedule& s) {
             return fail(JR_EINVAL, "schedule: the rows kernel takes defer 0 and unroll 4 or 8");
         if (s.bail < 1 || s.bail > 64)
             return fail(JR_EINVAL, "schedule: rows kernel bail must be in 1..64 (got %d)", s.bail);
+        if (s.handoff < 0 || s.handoff > 128)
+            return fail(JR_EINVAL, "schedule: rows kernel handoff must be in 0..128 (got %d)",
+                        s.handoff);
     }
     return JR_OK;
 }
@@ -156,10 +159,11 @@ std::mutex g_sched_mu;
 // two-phase rows kernel, which won every FP32 workload measured; one wave per
 // tile keeps one-image calls free of the work queues (and so capturable).
 jr_schedule g_default[3] = {
-    // tile_w, tile_h, unroll, defer, refill, persistent, waves_per_cu, order, kernel, bail
-    {16, 16, 8, 0, 16, 0, 16, JR_ORDER_COST, JR_KERNEL_TILED, 8},  // FP64
-    {64, 8, 8, 0, 32, 0, 16, JR_ORDER_COST, JR_KERNEL_ROWS, 6},    // FP32
-    {16, 16, 8, 1, 64, 0, 16, JR_ORDER_COST, JR_KERNEL_TILED, 8},  // FF
+    // tile_w, tile_h, unroll, defer, refill, persistent, waves_per_cu, order, kernel, bail,
+    // handoff
+    {16, 16, 8, 0, 16, 0, 16, JR_ORDER_COST, JR_KERNEL_TILED, 8, 0},  // FP64
+    {64, 8, 8, 0, 32, 0, 16, JR_ORDER_COST, JR_KERNEL_ROWS, 6, 0},    // FP32
+    {16, 16, 8, 1, 64, 0, 16, JR_ORDER_COST, JR_KERNEL_TILED, 8, 0},  // FF
 };
 
 jr_schedule default_schedule(int dtype) {
@@ -262,6 +266,7 @@ jr::PersistentArgs make_args(const Table& t, const DevFrame* d_table, int32_t* o
     a.hybrid = s.kernel == JR_KERNEL_HYBRID ? 1 : 0;
     a.rows = s.kernel == JR_KERNEL_ROWS ? 1 : 0;
     a.bail = s.bail;
+    a.handoff = s.kernel == JR_KERNEL_ROWS ? s.handoff : 0;
     return a;
 }
 

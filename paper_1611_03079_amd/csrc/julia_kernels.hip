@@ -1082,9 +1082,7 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
     const typename A::C cj = A::cmake(A::coord(F.cr), A::coord(F.ci));
     int32_t* tout = a.out_base + F.out_offset + ((int64_t)row0 * W + col0);
     const bool col_ok = lane < tw;
-    // survivors of phase 1 have lead >= p_lane; lanes past the tile and caps
-    // within P have none
-    const int p_lane = (col_ok && P < mi) ? P : 0x7fffffff;
+    const uint64_t cols = tw >= 64 ? ~0ull : ((1ull << tw) - 1ull);  // lanes inside the tile
     uint16_t* pos = (uint16_t*)(list + ZW * cap);
 
     // phase 1
@@ -1099,10 +1097,15 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
             c = cj;
         }
     };
-    // A pixel survives when it is inside for all P iterates (lead = P) and the
-    // cap lies beyond P; one compare against the lane's bound gives the
-    // survivors' mask directly.  Finished pixels store, survivors append.
-    auto finish_row = [&](int r, int lead, const typename A::Z& z) {
+    // A pixel survives when it is inside for all `done` iterates its row ran
+    // (lead = done) and the cap lies beyond them; one compare against the
+    // lane's bound gives the survivors' mask directly.  Finished pixels store,
+    // survivors append.  An entry's position word holds the row and column
+    // in the tile and, in its top four bits, done / 4 - 1 (done is a multiple
+    // of 4 from 4 to 64 where K > 1; where K = 1 it is P = 1 and the bits are
+    // unused).
+    auto finish_row = [&](int r, int lead, const typename A::Z& z, int done) {
+        const int p_lane = (col_ok && done < mi) ? done : 0x7fffffff;
         const bool sv = lead >= p_lane;
         const bool fin = col_ok && !sv;
         const uint64_t m = __ballot(sv);
@@ -1110,7 +1113,8 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
         if (sv) {
             const int e = qn + lanes_below(m);
             list_put<A>(list, cap, e, z);
-            pos[e] = (uint16_t)((r << 6) | lane);
+            const int k = K == 1 ? 0 : (done >> 2) - 1;
+            pos[e] = (uint16_t)((k << 12) | (r << 6) | lane);
         }
         qn += __popcll(m);
     };
@@ -1135,7 +1139,10 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
         for (;;) {
             if (__popcll(running) <= busy_max) {
                 if (fi) {
-                    store_at(tout, off, shade<COLOR>(a, cnt));
+                    // r * W + col fits an int (a frame holds < 2^31 pixels),
+                    // but four times it may not fit 32 bits: index, so that
+                    // the address is formed in 64 bits.
+                    tout[off] = shade<COLOR>(a, cnt);
                     fi = false;
                 }
                 if (next < qn) {
@@ -1144,8 +1151,9 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
                     const int ee = min(e, qn - 1);
                     const typename A::Z zl = list_get<A>(list, cap, ee);
                     const uint32_t id = pos[ee];
-                    const int r = (int)(id >> 6);
+                    const int r = (int)((id >> 6) & 63u);
                     const int col = (int)(id & 63u);
+                    const int done = K == 1 ? P : (int)((id >> 12) + 1u) * 4;
                     V cx = zero, cy = zero;
                     if (MANDEL) {
                         cx = A::shfl(xl, col);
@@ -1155,7 +1163,7 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
                         z = zl;
                         if (MANDEL) c = A::cmake(cx, cy);
                         off = r * W + col;
-                        n = P;
+                        n = done;
                         it = true;
                     }
                     next += __popcll(idle);
@@ -1183,10 +1191,13 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
     if (K != 1 && kPairs) {
         // Two rows at a time, four iterations per trip (P is a multiple of 4
         // here): two independent orbits per lane keep the pipeline full.  The
-        // pair stops early once every lane's pixels in both rows have
-        // escaped (absorbing: later iterates would count nothing).  Lanes
-        // past the tile's width repeat its last column, so they never hold
-        // the rows back on their own.
+        // pair leaves its first block early once at most `handoff` of its
+        // pixels inside the tile are still inside the disc: with 0, once all
+        // have escaped (absorbing: later iterates would count nothing);
+        // otherwise the few still running go to the list with the count so
+        // far instead of holding the wave.  Lanes past the tile's width
+        // repeat its last column and are not counted.
+        const int handoff = __builtin_amdgcn_readfirstlane(a.handoff);
         for (; r + 2 <= th; r += 2) {
             if (qn + 128 > cap) drain();  // room for two rows' survivors
             typename A::Z z0, z1;
@@ -1194,8 +1205,9 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
             start_row(r, z0, c0);
             start_row(r + 1, z1, c1);
             int l0 = 0, l1 = 0;
+            int done = 0;
 #pragma unroll 1
-            for (int u = 0; u < P; u += 4) {
+            while (done < P) {
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
                     l0 += A::check_step(z0, c0, deg) ? 1 : 0;
@@ -1205,10 +1217,12 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
                 const bool in1 = A::check_step(z1, c1, deg);
                 l0 += in0 ? 1 : 0;
                 l1 += in1 ? 1 : 0;
-                if (__ballot(in0 || in1) == 0) break;
+                done += 4;
+                const int still = __popcll(__ballot(in0) & cols) + __popcll(__ballot(in1) & cols);
+                if (still <= handoff) break;
             }
-            finish_row(r, l0, z0);
-            finish_row(r + 1, l1, z1);
+            finish_row(r, l0, z0, done);
+            finish_row(r + 1, l1, z1, done);
         }
     }
     for (; r < th; ++r) {  // single rows: an odd tile height's last, P = 1, wide types
@@ -1216,7 +1230,7 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
         typename A::Z z;
         typename A::C c;
         start_row(r, z, c);
-        int lead = 0;
+        int lead = 0, done = P;
         if (K == 1) {
             lead = A::check_step(z, c, deg) ? 1 : 0;  // P = 1: the exact test
         } else {
@@ -1227,10 +1241,11 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
                 lead += A::check_step(z, c, deg) ? 1 : 0;
                 const bool in = A::check_step(z, c, deg);
                 lead += in ? 1 : 0;
+                // all escaped: no survivors, whatever `done` says
                 if (__ballot(in) == 0) break;
             }
         }
-        finish_row(r, lead, z);
+        finish_row(r, lead, z, done);
     }
     drain();
 }

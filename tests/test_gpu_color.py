@@ -46,6 +46,7 @@ SCHEDS = [
     jr.Schedule(64, 16, 8, 0, 16, 0, 16, "cost", "hybrid", 8),
     jr.Schedule(32, 8, 8, 1, 32, 1, 16, "table", "hybrid", 3),
     jr.Schedule(64, 16, 8, 0, 16, 0, 16, "cost", "rows", 4),
+    jr.Schedule(64, 32, 8, 0, 16, 0, 16, "cost", "rows", 32, 32),
 ]
 
 

@@ -25,6 +25,7 @@ SCHEDS = [
     jr.Schedule(kernel="plain", order="table"),
     jr.Schedule(64, 16, 8, 0, 16, 0, 16, "cost", "hybrid", 8),
     jr.Schedule(64, 16, 8, 0, 16, 0, 16, "cost", "rows", 4),
+    jr.Schedule(64, 64, 8, 0, 16, 0, 16, "cost", "rows", 48, 32),
     jr.Schedule(37, 5, 4, 0, 32, 1, 8, "table", "rows", 2),
     jr.Schedule(64, 64, 8, 0, 16, 1, 8, "cost", "rows", 4),
 ]

@@ -41,6 +41,8 @@ SCHEDULES = [
     jr.Schedule(64, 64, 8, 0, 8, 0, 16, "cost", "rows", 1),   # 64-row tiles, one-wave workgroups
     jr.Schedule(1, 1, 4, 0, 1, 1, 4, "cost", "rows", 64),     # one-pixel tiles, long first block
     jr.Schedule(64, 64, 4, 0, 8, 1, 8, "table", "rows", 8),   # several list drains per tile
+    jr.Schedule(64, 64, 8, 0, 16, 0, 16, "cost", "rows", 64, 48),  # pairs hand off early
+    jr.Schedule(37, 5, 4, 0, 32, 1, 8, "table", "rows", 12, 128),  # every pair after one trip
 ]
 
 
@@ -380,4 +382,28 @@ def test_uneven_batch_full_sampled():
         want = oracle.render_pixels(f.c, f.window, f.width, f.height, f.max_iter, ii, jj, f.dtype)
         np.testing.assert_array_equal(got, want, err_msg=str(f))
     del arena, views
+    torch.cuda.empty_cache()
+
+
+def test_rows_wide_frame_offsets():
+    """A frame 2^25 pixels wide and 40 rows tall: pixels of rows 32 and below
+    lie more than 2^32 bytes past their tile's first pixel.  The rows kernel
+    writes them from its list drain; sampled survivors of those rows against
+    the oracle (a 32-bit byte offset would have wrapped onto other pixels)."""
+    W, H = 1 << 25, 40
+    win = (-1.6, 1.6, -0.05, 0.05)
+    c, cap = complex(-0.4, 0.6), 48
+    sched = jr.Schedule(64, 64, 8, 0, 16, 0, 16, "cost", "rows", 8)
+    out = torch.full((H, W), -1, dtype=torch.int32, device="cuda")
+    jr.render(c, win, W, H, cap, "fp32", out=out, schedule=sched)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(23)
+    jj = rng.integers(32, H, 4000).astype(np.int32)
+    ii = rng.integers(0, W, 4000).astype(np.int32)
+    want = oracle.render_pixels(c, win, W, H, cap, ii, jj, "fp32")
+    # the samples must include pixels that outlive the first block (P = 8)
+    assert (want > 8).sum() >= 100
+    got = out[torch.from_numpy(jj).long().cuda(), torch.from_numpy(ii).long().cuda()].cpu().numpy()
+    np.testing.assert_array_equal(got, want)
+    del out
     torch.cuda.empty_cache()
