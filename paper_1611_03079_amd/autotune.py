@@ -63,22 +63,34 @@ def time_singles(frames, schedule: jr.Schedule, reps: int = 3) -> float:
     return sum(time_plan([f], schedule, reps=reps) for f in frames)
 
 
-def time_plan(frames, schedule: jr.Schedule, reps: int = 3, warmup: int = 1) -> float:
-    """Median device time (ms) of one launch of `frames` under `schedule`."""
+def time_plan(frames, schedule: jr.Schedule, reps: int = 3, warmup: int = 1,
+              span_ms: float = 5.0) -> float:
+    """Device time (ms) per launch of `frames` under `schedule`, sustained:
+    the median over `reps` runs of back-to-back launches, each run at least
+    `span_ms` long.  The chip's clock under a steady load, not a lone
+    launch's, decides throughput, and the two can rank schedules
+    differently."""
     import torch
     plan = jr.Plan(frames, schedule)
     try:
         for _ in range(warmup):
             plan.launch()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        plan.launch()
+        b.record()
+        b.synchronize()
+        n = int(min(200, max(1, math.ceil(span_ms / max(a.elapsed_time(b), 1e-3)))))
         times = []
         for _ in range(reps):
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
             a.record()
-            plan.launch()
+            for _ in range(n):
+                plan.launch()
             b.record()
             b.synchronize()
-            times.append(a.elapsed_time(b))
+            times.append(a.elapsed_time(b) / n)
         times.sort()
         return times[len(times) // 2]
     finally:
