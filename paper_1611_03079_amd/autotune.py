@@ -59,8 +59,43 @@ def cache_key(device: str, dtype: str, max_iter: int, pixels: int, batch: bool =
 
 
 def time_singles(frames, schedule: jr.Schedule, reps: int = 3) -> float:
-    """Sum over the frames of the median time of each rendered on its own."""
+    """Sum over the frames of the time of each rendered on its own.  A single
+    image under a plain schedule runs the two-dimensional one-thread-per-pixel
+    kernel (julia_render_plain), which is what is timed for it."""
+    if schedule.kernel == "plain":
+        return sum(time_render_plain(f, reps=reps) for f in frames)
     return sum(time_plan([f], schedule, reps=reps) for f in frames)
+
+
+def time_render_plain(f, reps: int = 3, span_ms: float = 5.0) -> float:
+    """Sustained device time (ms) per render of one frame by the plain kernel,
+    timed like time_plan."""
+    import torch
+    out = torch.empty((f.height, f.width), dtype=torch.int32, device="cuda")
+
+    def one():
+        jr.render(f.c, f.window, f.width, f.height, f.max_iter, f.dtype, out=out,
+                  plain=True, mode=f.mode, degree=f.degree)
+
+    one()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    one()
+    b.record()
+    b.synchronize()
+    n = int(min(200, max(1, math.ceil(span_ms / max(a.elapsed_time(b), 1e-3)))))
+    times = []
+    for _ in range(reps):
+        a.record()
+        for _ in range(n):
+            one()
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b) / n)
+    times.sort()
+    return times[len(times) // 2]
 
 
 def time_plan(frames, schedule: jr.Schedule, reps: int = 3, warmup: int = 1,
