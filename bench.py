@@ -83,13 +83,15 @@ def parse():
 
 
 def tuned_schedule(jr, name, frames):
-    """Schedule from the committed autotune cache, else tuned here (seconds)."""
+    """Schedule from the committed autotune cache, else tuned here (minutes)."""
     from paper_1611_03079_amd import autotune as at
     cache = at.load_cache()
     e = cache.get("_workloads", {}).get(name)
     if e:
         return jr.Schedule(**e["schedule"]), "cache"
-    best, _, _ = at.tune(frames, reps=3)
+    print("bench: no autotune cache entry for %s; tuning it first (minutes)" % name,
+          file=sys.stderr, flush=True)
+    best, _, _ = at.tune(frames, reps=3, verbose=True)
     return best, "tuned at start"
 
 

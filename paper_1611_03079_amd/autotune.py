@@ -152,12 +152,31 @@ def _stage(frames, base: jr.Schedule, variants: List[dict], reps: int, log: list
     return best
 
 
+class _ProgressLog(list):
+    """A tuning log that reports every 16th candidate on stderr."""
+
+    def __init__(self, base):
+        super().__init__(base)
+
+    def append(self, item):
+        super().append(item)
+        if len(self) % 16 == 0:
+            import sys
+            d, t = item
+            print("autotune: %d candidates, last %s/%dx%d %.4f ms" % (
+                len(self), d["kernel"], d["tile_w"], d["tile_h"], t), file=sys.stderr, flush=True)
+
+
 def tune(frames: Sequence, base: Optional[jr.Schedule] = None, reps: int = 3,
-         log: Optional[list] = None, singles: bool = False) -> Tuple[jr.Schedule, float, list]:
+         log: Optional[list] = None, singles: bool = False,
+         verbose: bool = False) -> Tuple[jr.Schedule, float, list]:
     """Search schedules for `frames`; returns (best, its median ms, log).
     With ``singles`` each frame is timed as a launch of its own (the way
-    single images are rendered) and the times are summed."""
+    single images are rendered) and the times are summed.  ``verbose`` prints
+    a line to stderr after every stage."""
     log = [] if log is None else log
+    if verbose:
+        log = _ProgressLog(log)
     base = base or jr.Schedule()
     s = _stage(frames, base, [dict(unroll=u, defer=d) for u, d in BLOCKS], reps, log, singles)
     s = _stage(frames, s, [dict(tile_w=tw, tile_h=th, persistent=p, refill=r)
