@@ -143,11 +143,12 @@ typedef struct {
  *                   tile.
  *   bail            JR_KERNEL_HYBRID: 1..4096; JR_KERNEL_ROWS: 1..64 (other
  *                   kernels ignore it).
- *   handoff         JR_KERNEL_ROWS, 0..128: rows run in pairs for FP32 and
- *                   FP64 (quadratic maps), and a pair stops its first
+ *   handoff         JR_KERNEL_ROWS, 0..256: rows run in groups for FP32 and
+ *                   FP64 (quadratic maps): four rows at a time in batches of
+ *                   FP32 frames only, two otherwise.  A group stops its first
  *                   iterations, after a multiple of 4 of them, once at most
  *                   `handoff` of its pixels are still inside the disc; those
- *                   join the list with their count so far.  With 0 a pair
+ *                   join the list with their count so far.  With 0 a group
  *                   stops once all its pixels have escaped.  Single rows
  *                   always stop then.  Other kernels ignore it.
  */

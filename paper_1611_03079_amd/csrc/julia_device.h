@@ -53,7 +53,7 @@ struct PersistentArgs {
     int32_t bail;        // hybrid: iterations of a fresh packet before its survivors park;
                          // rows: length of the first counted block of every row
     int32_t rows;        // 1: two-phase row-packet kernel (jr_rows)
-    int32_t handoff;     // rows: a row pair leaves its first block once at most
+    int32_t handoff;     // rows: a row group leaves its first block once at most
                          // this many of its pixels are still inside
     int32_t palette_len; // > 0: a pixel stores palette[min(count, palette_len - 1)]
     const uint32_t* palette;
@@ -68,6 +68,8 @@ constexpr int kPaletteMax = 8192;
 // not take the next rows' survivors, so tiles may be taller than the list.
 constexpr int kRowsFP32 = 8;
 constexpr int kRowsWide = 4;
+// Rows per group in the rows kernel's first phase for FP32 (FP64 takes 2).
+constexpr int kGroupFP32 = 4;
 // Kernel variants that store colours carry this bit beside the dtype bits
 // (compile-time, so the counting kernels hold no colour code).
 constexpr int kColorBit = 8;

@@ -122,8 +122,8 @@ int check_schedule(const jr_schedule& s) {
             return fail(JR_EINVAL, "schedule: the rows kernel takes defer 0 and unroll 4 or 8");
         if (s.bail < 1 || s.bail > 64)
             return fail(JR_EINVAL, "schedule: rows kernel bail must be in 1..64 (got %d)", s.bail);
-        if (s.handoff < 0 || s.handoff > 128)
-            return fail(JR_EINVAL, "schedule: rows kernel handoff must be in 0..128 (got %d)",
+        if (s.handoff < 0 || s.handoff > 256)
+            return fail(JR_EINVAL, "schedule: rows kernel handoff must be in 0..256 (got %d)",
                         s.handoff);
     }
     return JR_OK;

@@ -1060,9 +1060,9 @@ __device__ __forceinline__ typename A::Z list_get(const uint32_t* list, int cap,
 // holds `cap` entries; word W of entry e's iterate is list[W * cap + e], and
 // its position (row << 6 | column) is the 16-bit element e of the array that
 // follows the iterate words.
-template <class A, int K, int MANDEL, int COLOR>
-__device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, uint32_t* list,
-                          int cap) {
+template <class A, int K, int MANDEL, int COLOR, int LROWS>
+__device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, uint32_t* list) {
+    constexpr int cap = 64 * LROWS;  // list entries
     using V = typename A::V;
     constexpr int ZW = (int)(sizeof(typename A::Z) / 4);
     const uint32_t local = (uint32_t)(t - F.tile_begin);
@@ -1185,44 +1185,54 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
         qn = 0;
     };
     int r = 0;
-    // Pairs for the quadratic FP32 and FP64 maps; float-float and the general
-    // maps hold too much state per orbit (registers would cost resident waves).
-    constexpr bool kPairs = std::is_same<A, ArF32>::value || std::is_same<A, ArF64>::value;
-    if (K != 1 && kPairs) {
-        // Two rows at a time, four iterations per trip (P is a multiple of 4
-        // here): two independent orbits per lane keep the pipeline full.  The
-        // pair leaves its first block early once at most `handoff` of its
+    // Row groups for the quadratic FP32 and FP64 maps; float-float and the
+    // general maps hold too much state per orbit (registers would cost
+    // resident waves).  FP32 takes four rows at a time where its list holds
+    // eight rows' survivors (FP32-only kernels), two otherwise, as FP64
+    // does: a drain should find several groups' survivors waiting.
+    constexpr bool kGroups = std::is_same<A, ArF32>::value || std::is_same<A, ArF64>::value;
+    constexpr int G = (std::is_same<A, ArF32>::value && LROWS >= 2 * kGroupFP32) ? kGroupFP32 : 2;
+    static_assert(2 * G <= LROWS, "the list holds at least two groups' survivors");
+    if (K != 1 && kGroups) {
+        // G rows at a time, four iterations per trip (P is a multiple of 4
+        // here): G independent orbits per lane keep the pipeline full.  The
+        // group leaves its first block early once at most `handoff` of its
         // pixels inside the tile are still inside the disc: with 0, once all
         // have escaped (absorbing: later iterates would count nothing);
         // otherwise the few still running go to the list with the count so
         // far instead of holding the wave.  Lanes past the tile's width
         // repeat its last column and are not counted.
         const int handoff = __builtin_amdgcn_readfirstlane(a.handoff);
-        for (; r + 2 <= th; r += 2) {
-            if (qn + 128 > cap) drain();  // room for two rows' survivors
-            typename A::Z z0, z1;
-            typename A::C c0, c1;
-            start_row(r, z0, c0);
-            start_row(r + 1, z1, c1);
-            int l0 = 0, l1 = 0;
+        for (; r + G <= th; r += G) {
+            if (qn + 64 * G > cap) drain();  // room for the group's survivors
+            typename A::Z z[G];
+            typename A::C c[G];
+            int l[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                start_row(r + g, z[g], c[g]);
+                l[g] = 0;
+            }
             int done = 0;
 #pragma unroll 1
             while (done < P) {
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    l0 += A::check_step(z0, c0, deg) ? 1 : 0;
-                    l1 += A::check_step(z1, c1, deg) ? 1 : 0;
+#pragma unroll
+                    for (int g = 0; g < G; ++g) l[g] += A::check_step(z[g], c[g], deg) ? 1 : 0;
                 }
-                const bool in0 = A::check_step(z0, c0, deg);
-                const bool in1 = A::check_step(z1, c1, deg);
-                l0 += in0 ? 1 : 0;
-                l1 += in1 ? 1 : 0;
+                int still = 0;
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const bool in = A::check_step(z[g], c[g], deg);
+                    l[g] += in ? 1 : 0;
+                    still += __popcll(__ballot(in) & cols);
+                }
                 done += 4;
-                const int still = __popcll(__ballot(in0) & cols) + __popcll(__ballot(in1) & cols);
                 if (still <= handoff) break;
             }
-            finish_row(r, l0, z0, done);
-            finish_row(r + 1, l1, z1, done);
+#pragma unroll
+            for (int g = 0; g < G; ++g) finish_row(r + g, l[g], z[g], done);
         }
     }
     for (; r < th; ++r) {  // single rows: an odd tile height's last, P = 1, wide types
@@ -1262,7 +1272,6 @@ __global__ __launch_bounds__(64 * WPB) void jr_rows(PersistentArgs a) {
     constexpr int COLOR = (DTMASK & kColorBit) ? 1 : 0;
     static_assert(WPB == 4 || (WPB == 1 && !COLOR), "one-wave workgroups carry no palette");
     using S = RowsShape<DTMASK>;
-    constexpr int cap = 64 * S::rows;
     __shared__ uint32_t lmem[WPB * S::wave_words];
     uint32_t* list =
         WPB == 1 ? lmem
@@ -1285,10 +1294,10 @@ __global__ __launch_bounds__(64 * WPB) void jr_rows(PersistentArgs a) {
         const bool mandel = F.mode == kModeMandelbrot;
 #define JR_ROWS(A_)                                                                      \
     do {                                                                                 \
-        if (abs && !mandel) rows_tile<A_, K, 0, COLOR>(a, F, t, P, list, cap);  \
-        else if (abs) rows_tile<A_, K, 1, COLOR>(a, F, t, P, list, cap);        \
-        else if (!mandel) rows_tile<A_, 1, 0, COLOR>(a, F, t, P, list, cap);    \
-        else rows_tile<A_, 1, 1, COLOR>(a, F, t, P, list, cap);                 \
+        if (abs && !mandel) rows_tile<A_, K, 0, COLOR, S::rows>(a, F, t, P, list);  \
+        else if (abs) rows_tile<A_, K, 1, COLOR, S::rows>(a, F, t, P, list);        \
+        else if (!mandel) rows_tile<A_, 1, 0, COLOR, S::rows>(a, F, t, P, list);    \
+        else rows_tile<A_, 1, 1, COLOR, S::rows>(a, F, t, P, list);                 \
     } while (0)
         if ((DTMASK & kGeneralBit) && F.degree > 2) {
             if (F.dtype == kFP32)

@@ -125,9 +125,9 @@ def test_check_schedule_rejects(field, value):
         rows = jr.Schedule(64, 16, 8, 0, 16, 0, 16, "cost", "rows", 4)
         assert jr.check_schedule(rows) == jr.JR_OK
         for bad in (dict(bail=0), dict(bail=65), dict(unroll=2), dict(unroll=8, defer=1),
-                    dict(handoff=-1), dict(handoff=129)):
+                    dict(handoff=-1), dict(handoff=257)):
             assert jr.check_schedule(jr.Schedule(**{**rows.__dict__, **bad})) == jr.JR_EINVAL
-        for good in (dict(handoff=0), dict(handoff=128), dict(bail=64, handoff=32)):
+        for good in (dict(handoff=0), dict(handoff=256), dict(bail=64, handoff=32)):
             assert jr.check_schedule(jr.Schedule(**{**rows.__dict__, **good})) == jr.JR_OK
         # other kernels ignore the field
         assert jr.check_schedule(jr.Schedule(kernel="tiled", handoff=500)) == jr.JR_OK
