@@ -47,8 +47,15 @@ def cap_bucket(max_iter: int) -> str:
     return "cap<=128" if max_iter <= 128 else "cap<=1024" if max_iter <= 1024 else "cap>1024"
 
 
+PIXEL_EDGES = [("px<64K", 1 << 16), ("px<512K", 1 << 19), ("px<4M", 1 << 22),
+               ("px<64M", 64 << 20)]
+
+
 def pixel_bucket(pixels: int) -> str:
-    return "px<1M" if pixels < (1 << 20) else "px<64M" if pixels < (64 << 20) else "px>=64M"
+    for name, edge in PIXEL_EDGES:
+        if pixels < edge:
+            return name
+    return "px>=64M"
 
 
 def cache_key(device: str, dtype: str, max_iter: int, pixels: int, batch: bool = False) -> str:
@@ -262,7 +269,7 @@ def lookup(cache: Dict[str, dict], dtype: str, max_iter: int, pixels: int) -> Op
 
 
 CAP_LIMITS = {"cap<=128": 128, "cap<=1024": 1024, "cap>1024": 2 ** 31 - 1}
-PIXEL_LIMITS = {"px<1M": (1 << 20) - 1, "px<64M": (64 << 20) - 1, "px>=64M": 2 ** 63 - 1}
+PIXEL_LIMITS = dict([(name, edge - 1) for name, edge in PIXEL_EDGES] + [("px>=64M", 2 ** 63 - 1)])
 
 
 def install_image_schedules(cache: Dict[str, dict], device: str) -> int:
@@ -274,6 +281,8 @@ def install_image_schedules(cache: Dict[str, dict], device: str) -> int:
         if len(parts) != 4 or parts[0] != device:
             continue  # batch entries and other devices
         _, dtype, cap, px = parts
+        if cap not in CAP_LIMITS or px not in PIXEL_LIMITS:
+            continue  # a bucket of an older layout
         jr.set_image_schedule(dtype, CAP_LIMITS[cap], PIXEL_LIMITS[px],
                               jr.Schedule(**e["schedule"]))
         n += 1
@@ -291,7 +300,8 @@ def apply_cache(cache: Dict[str, dict], max_iter: int = 100, pixels: int = 1 << 
 # ------------------------------------------------------------------ command line
 # workloads rendered one image per launch (tuned and filed per image)
 SINGLES = {"single_4096_fp32_cap100", "single_4096_fp32_cap1000", "single_4096_fp64_cap100",
-           "single_4096_fp64_cap1000", "single_512_fp64"}
+           "single_4096_fp64_cap1000", "single_512_fp64", "single_small_fp64",
+           "single_1000_fp64", "single_10000_fp64"}
 
 
 def standard_workloads():
@@ -305,6 +315,10 @@ def standard_workloads():
         "single_4096_fp64_cap100": [wl.single_4096(s, 100, "fp64") for s in range(2)],
         "single_4096_fp64_cap1000": [wl.single_4096(s, 1000, "fp64") for s in range(2)],
         "single_512_fp64": [wl.single_512("fp64")],
+        # the other sizes of the square sweep, one pixel bucket each
+        "single_small_fp64": wl.square_sweep("fp64", sides=(32, 100, 200)),
+        "single_1000_fp64": wl.square_sweep("fp64", sides=(1000, 2000)),
+        "single_10000_fp64": wl.square_sweep("fp64", sides=(10000,)),
         "uneven_fp32_ff": wl.uneven_batch(0, n=64),
         "cardioid_path_fp32": wl.cardioid_path(64),
         "general_deg3_fp32": wl.general_path(32, 3),
