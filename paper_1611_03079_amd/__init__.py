@@ -243,22 +243,24 @@ def tuned_schedule(dtype: str, max_iter: int, pixels: int) -> Optional["Schedule
 
 
 _TUNED_MEMO = {}
-_IMAGE_SCHEDULES_FOR = set()
+_IMAGE_SCHEDULES_DONE = False
 
 
 def _install_image_schedules():
-    """Hand the autotuner's single-image winners for this device to the
-    library (jr_set_image_schedule), once per device."""
-    from . import autotune
-    dev = autotune.device_name()
-    if dev in _IMAGE_SCHEDULES_FOR:
+    """Hand the autotuner's single-image winners to the library
+    (jr_set_image_schedule), once per process.  The library's table is
+    process-wide and the library runs on gfx950 only, so the entries of the
+    first device seen serve every device; later calls cost one test."""
+    global _IMAGE_SCHEDULES_DONE
+    if _IMAGE_SCHEDULES_DONE:
         return
-    _IMAGE_SCHEDULES_FOR.add(dev)
+    _IMAGE_SCHEDULES_DONE = True
+    from . import autotune
     try:
         cache = autotune.load_cache()
     except (OSError, ValueError):
         return
-    autotune.install_image_schedules(cache, dev)
+    autotune.install_image_schedules(cache, autotune.device_name())
 
 
 def image_schedule(dtype: str, max_iter: int, pixels: int) -> Schedule:
