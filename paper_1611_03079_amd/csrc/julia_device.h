@@ -70,6 +70,9 @@ constexpr int kRowsFP32 = 8;
 constexpr int kRowsWide = 4;
 // Rows per group in the rows kernel's first phase for FP32 (FP64 takes 2).
 constexpr int kGroupFP32 = 4;
+// Largest palette (entries) that one-wave workgroups of the rows kernel stage
+// each for themselves; larger palettes keep four-wave workgroups.
+constexpr int kOneWavePalette = 256;
 // Kernel variants that store colours carry this bit beside the dtype bits
 // (compile-time, so the counting kernels hold no colour code).
 constexpr int kColorBit = 8;

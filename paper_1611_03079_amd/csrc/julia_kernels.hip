@@ -315,7 +315,7 @@ template <int COLOR>
 __device__ __forceinline__ void stage_palette(const PersistentArgs& a) {
     if (!COLOR) return;
     uint32_t* pal = palette_lds();
-    for (int k = threadIdx.x; k < a.palette_len; k += 256) pal[k] = a.palette[k];  // 256-thread blocks
+    for (int k = threadIdx.x; k < a.palette_len; k += blockDim.x) pal[k] = a.palette[k];
     __syncthreads();
 }
 
@@ -1264,13 +1264,13 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
 // queues), each tile in two phases (rows_tile).  P, the first block's length,
 // is the schedule's bail field rounded up to a multiple of 4; K is the second
 // phase's block length.  WPB is the number of waves per workgroup: 4 for the
-// work queues and the colour store (whose palette the workgroup shares), 1
-// for dispatched tiles, so that a wave's LDS is released as soon as its own
-// tile is done instead of when the slowest of four tiles is.
+// work queues and for large palettes (which the workgroup stages once), 1 for
+// dispatched tiles, so that a wave's LDS is released as soon as its own tile
+// is done instead of when the slowest of four tiles is.
 template <int K, int DTMASK, int WPB>
 __global__ __launch_bounds__(64 * WPB) void jr_rows(PersistentArgs a) {
     constexpr int COLOR = (DTMASK & kColorBit) ? 1 : 0;
-    static_assert(WPB == 4 || (WPB == 1 && !COLOR), "one-wave workgroups carry no palette");
+    static_assert(WPB == 4 || WPB == 1, "one or four waves per workgroup");
     using S = RowsShape<DTMASK>;
     __shared__ uint32_t lmem[WPB * S::wave_words];
     uint32_t* list =
@@ -1374,6 +1374,8 @@ static TiledFn pick_block(int unroll, int defer, int dtmask) {
 
 template <int K>
 static TiledFn pick_rows_mask(int dtmask, bool one_wave) {
+    if (one_wave && dtmask == ((1 << kFP32) | kColorBit))
+        return jr_rows<K, (1 << kFP32) | kColorBit, 1>;
     if (one_wave && !(dtmask & kColorBit)) {
         if (dtmask & kGeneralBit) return jr_rows<K, 7 | kGeneralBit, 1>;
         switch (dtmask) {
@@ -1440,7 +1442,12 @@ hipError_t launch_tiled(int unroll, int defer, int dtmask, int blocks, const Per
     if (args.palette_len > 0) dtmask |= kColorBit;
     // Dispatched rows tiles (one tile per wave, no palette) run in one-wave
     // workgroups, one per tile.
-    const bool one_wave = args.rows && !args.persistent && !(dtmask & kColorBit) &&
+    // FP32 colour stores with a small palette too: each one-wave workgroup
+    // stages its own copy.
+    const bool small_palette = dtmask == ((1 << kFP32) | kColorBit) &&
+                               args.palette_len <= kOneWavePalette;
+    const bool one_wave = args.rows && !args.persistent &&
+                          (!(dtmask & kColorBit) || small_palette) &&
                           args.total_tiles <= 0x7fffffffLL;
     if (one_wave) blocks = (int)args.total_tiles;
     const unsigned threads = one_wave ? 64u : 256u;

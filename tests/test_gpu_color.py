@@ -146,3 +146,18 @@ def test_palette_validation_on_device():
     with pytest.raises(ValueError):
         jr.render(C1, UNIT, 8, 8, 10, "fp64", palette=torch.zeros(8193, dtype=torch.int32,
                                                                    device="cuda"))
+
+
+@pytest.mark.parametrize("plen", [256, 257])
+def test_fp32_batch_colours_both_workgroup_shapes(plen):
+    """An FP32-only batch on dispatched rows tiles: a palette of up to 256
+    entries runs in one-wave workgroups (each stages its own copy), a larger
+    one in four-wave workgroups.  Both against the oracle."""
+    frames = [Frame(C1, UNIT, 130, 67, 100, "fp32"),
+              Frame(complex(0.285, 0.01), (-1.2, 1.2, -0.9, 0.9), 97, 45, 300, "fp32"),
+              Frame(0j, (-2.0, 0.6, -1.1, 1.1), 64, 50, 150, "fp32", "mandelbrot")]
+    ph, pd = palette(plen, seed=19)
+    sched = jr.Schedule(64, 32, 8, 0, 16, 0, 16, "cost", "rows", 48, 96)
+    _, views = jr.render_batch(frames, sched, palette=pd)
+    for f, v in zip(frames, views):
+        np.testing.assert_array_equal(as_u32(v), expected(f, ph))
