@@ -37,6 +37,9 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32: 256 CU x 2.4 GHz x 256 flop/clk
 PEAK_FP64_TFLOPS = 78.6    # MI355X vector FP64: 256 CU x 2.4 GHz x 128 flop/clk
+# FP32 without packed instructions (the build leaves them off): one FMA per
+# lane per clock, 256 CU x 64 lanes x 2 flop x 2.4 GHz
+PEAK_FP32_UNPACKED_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 FLOP_PER_ITER = 8
 BYTES_PER_PIXEL = 4
@@ -388,6 +391,8 @@ def main():
                      "kernel_ms": round(kernel_ms, 4),
                      "alu": {"achieved": round(alu_tflops, 2), "peak": PEAK_FP32_TFLOPS,
                              "unit": "TFLOP/s", "frac": round(alu_tflops / PEAK_FP32_TFLOPS, 4),
+                             "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
+                             "frac_unpacked": round(alu_tflops / PEAK_FP32_UNPACKED_TFLOPS, 4),
                              "flops_per_launch": FLOP_PER_ITER * iters},
                      "kernel": kernel_instance(sched) + " (libjulia.so)"},
     }
