@@ -62,10 +62,10 @@ struct PersistentArgs {
 // Largest colour table of the fused colour store; it is staged in LDS.
 constexpr int kPaletteMax = 8192;
 // Row-packet kernel: a wave's survivor list holds this many rows' worth of
-// pixels (64 each): 8 for FP32-only launches (512 entries, 20 KiB of LDS per
-// 4-wave workgroup, so 8 workgroups fit a CU), 4 when FP64, float-float or
-// general-map frames are in (18 KiB).  The list is drained whenever it could
-// not take the next rows' survivors, so tiles may be taller than the list.
+// pixels (64 each): 8 for FP32-only launches (512 entries, 5 KiB of LDS per
+// wave, so 32 one-wave workgroups fit a CU), 4 when FP64, float-float or
+// general-map frames are in (4.5 KiB).  The list is drained whenever it could
+// not take the next group's survivors, so tiles may be taller than the list.
 constexpr int kRowsFP32 = 8;
 constexpr int kRowsWide = 4;
 // Rows per group in the rows kernel's first phase for FP32 (FP64 takes 2).

@@ -987,26 +987,30 @@ __global__ __launch_bounds__(256) void jr_plain_batch(PersistentArgs a) {
 // Most pixels of a light image escape within a few iterations, and in the
 // refill stream each of them still costs a block of K iterations and a share of
 // a refill round.  Here a wave takes its tile (at most 64 x 64, lane L =
-// column L) row by row:
-//   phase 1  every lane runs its pixel of the row for P counted iterations,
-//            without branches; the row's coordinate is one value for the whole
-//            wave and the column's is the lane's own, so nothing is exchanged
-//            between lanes.  Pixels that escape (or reach the cap) within P
-//            store their count at once, one coalesced row store;
-//   survivors append their iterate (Z_P) and position to the wave's list in
-//            LDS (stored one array per word, so lanes hit distinct banks);
-//   phase 2  whenever the list could not take the next rows' survivors, and
-//            at the end of the tile, the wave drains it with the refill stream
-//            in counted blocks of K: idle lanes read the next entries straight
-//            from the list, and C is the frame's constant.  A drain usually
-//            holds several wave-loads of survivors, so the lanes left idle
-//            while its last orbits finish cost little.
-// Counts: phase 1 counts the leading non-escaped iterates of Z_0..Z_{P-1}; with
-// escape absorbing (|C| <= 1.9) that is min(count, P), so a pixel with fewer
-// than P is final and the others continue from Z_P with n = P.  A row whose
-// pixels have all escaped stops before P: the iterates it skips would count
-// nothing.  Frames where escape may not be absorbing run P = 1 and K = 1, the
-// exact test on every iteration.
+// column L) a group of rows at a time:
+//   phase 1  every lane runs its pixel of each row of the group for up to P
+//            counted iterations, in branch-free trips of four; the row's
+//            coordinate is one value for the whole wave and the column's is
+//            the lane's own, so nothing is exchanged between lanes.  Pixels
+//            that escape (or reach the cap) store their count at once, one
+//            coalesced store per row;
+//   survivors append their iterate, their position and the number of
+//            iterations run to the wave's list in LDS (stored one array per
+//            word, so lanes hit distinct banks);
+//   phase 2  whenever the list could not take the next group's survivors,
+//            and at the end of the tile, the wave drains it with the refill
+//            stream in counted blocks of K: idle lanes read the next entries
+//            straight from the list, and C is the frame's constant.  A drain
+//            usually holds several wave-loads of survivors, so the lanes left
+//            idle while its last orbits finish cost little.
+// Counts: a group that ran `done` iterations counts, per pixel, the leading
+// non-escaped iterates of Z_0..Z_{done-1}; with escape absorbing (|C| <= 1.9)
+// that is min(count, done), so a pixel with fewer than `done` is final and the
+// others continue from Z_done with n = done.  A group stops before P once all
+// its pixels have escaped (the iterates it skips would count nothing), or
+// once at most the schedule's handoff of them are still inside.  Frames where
+// escape may not be absorbing run P = 1 and K = 1, the exact test on every
+// iteration.
 template <int DTMASK>
 struct RowsShape {
     static constexpr int kMask = DTMASK & 7;
