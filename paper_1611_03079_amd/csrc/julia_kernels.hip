@@ -1217,9 +1217,9 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
                 start_row(r + g, z[g], c[g]);
                 l[g] = 0;
             }
-            int done = 0;
-#pragma unroll 1
-            while (done < P) {
+            // one trip: four counted iterations of every row, then the number
+            // of the group's pixels still inside
+            auto trip = [&]() {
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
 #pragma unroll
@@ -1232,8 +1232,18 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
                     l[g] += in ? 1 : 0;
                     still += __popcll(__ballot(in) & cols);
                 }
-                done += 4;
-                if (still <= handoff) break;
+                return still;
+            };
+            // The first trip always runs (P >= 4) and is written out apart
+            // from the loop, so it reads the rows' starting values where they
+            // are instead of from copies made for the loop.
+            int done = 4;
+            if (trip() > handoff) {
+#pragma unroll 1
+                while (done < P) {
+                    done += 4;
+                    if (trip() <= handoff) break;
+                }
             }
 #pragma unroll
             for (int g = 0; g < G; ++g) finish_row(r + g, l[g], z[g], done);
