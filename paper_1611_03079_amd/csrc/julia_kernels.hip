@@ -1101,8 +1101,8 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
             c = cj;
         }
     };
-    // A pixel survives when it is inside for all `done` iterates its row ran
-    // (lead = done) and the cap lies beyond them; one compare against the
+    // A pixel survives when it is inside for all `done` iterates its group
+    // ran (lead = done) and the cap lies beyond them; one compare against the
     // lane's bound gives the survivors' mask directly.  Finished pixels store,
     // survivors append.  An entry's position word holds the row and column
     // in the tile and, in its top four bits, done / 4 - 1 (done is a multiple
@@ -1125,7 +1125,7 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
     // Phase 2: the refill stream over the list's entries, in counted blocks of
     // K; idle lanes read the next entries straight from the list, and C is
     // the frame's constant.  It runs whenever the list could not take the
-    // next rows' survivors, and at the end of the tile, so a drain usually
+    // next group's survivors, and at the end of the tile, so a drain usually
     // holds several wave-loads of survivors and its tail stays short.
     auto drain = [&]() {
         if (qn == 0) return;
