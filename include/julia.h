@@ -263,7 +263,8 @@ int jr_plan_replay(jr_plan *plan, void *stream);
  * valid while launches that use it are in flight.
  */
 int jr_plan_set_palette(jr_plan *plan, const uint32_t *palette, int32_t palette_len);
-/* Number of tiles of the plan and the grid it launches (for accounting). */
+/* Number of tiles of the plan and the workgroups it launches (for
+ * accounting): one per tile where the rows kernel runs one wave per tile. */
 int jr_plan_info(const jr_plan *plan, int64_t *tiles, int32_t *workgroups);
 void jr_plan_destroy(jr_plan *plan);
 

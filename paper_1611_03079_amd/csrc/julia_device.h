@@ -89,6 +89,8 @@ struct PlainArgs {
 // counters first (both may be captured into a hipGraph).
 hipError_t launch_tiled(int unroll, int defer, int dtmask, int blocks, const PersistentArgs& args,
                         hipStream_t stream);
+// Workgroups a launch_tiled call with this many `blocks` actually launches.
+int launch_workgroups(int dtmask, const PersistentArgs& args, int blocks);
 hipError_t launch_plain(int dtype, const PlainArgs& args, hipStream_t stream);
 
 // One thread per pixel over the frame table (tiles of 16 x 16, one workgroup each).

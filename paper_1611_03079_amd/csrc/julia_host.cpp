@@ -824,7 +824,10 @@ int jr_plan_set_palette(jr_plan* p, const uint32_t* palette, int32_t palette_len
 int jr_plan_info(const jr_plan* p, int64_t* tiles, int32_t* workgroups) {
     if (!p) return fail(JR_EINVAL, "plan is null");
     if (tiles) *tiles = p->total_tiles;
-    if (workgroups) *workgroups = p->blocks;
+    if (workgroups)
+        *workgroups = p->kernel == JR_KERNEL_PLAIN
+                          ? p->blocks
+                          : jr::launch_workgroups(p->dtmask, p->args, p->blocks);
     return JR_OK;
 }
 

@@ -1451,19 +1451,27 @@ hipError_t launch_plain_batch(int dtmask, const PersistentArgs& args, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_tiled(int unroll, int defer, int dtmask, int blocks, const PersistentArgs& args,
-                        hipStream_t stream) {
+// Dispatched rows tiles (one tile per wave) run in one-wave workgroups, one
+// per tile, unless they store colours from a palette larger than
+// kOneWavePalette or of a batch that is not FP32 only (such workgroups of
+// four waves stage the palette once).
+static bool one_wave_launch(int dtmask, const PersistentArgs& args) {
     if (args.palette_len > 0) dtmask |= kColorBit;
-    // Dispatched rows tiles (one tile per wave, no palette) run in one-wave
-    // workgroups, one per tile.
-    // FP32 colour stores with a small palette too: each one-wave workgroup
-    // stages its own copy.
     const bool small_palette = dtmask == ((1 << kFP32) | kColorBit) &&
                                args.palette_len <= kOneWavePalette;
-    const bool one_wave = args.rows && !args.persistent &&
-                          (!(dtmask & kColorBit) || small_palette) &&
-                          args.total_tiles <= 0x7fffffffLL;
-    if (one_wave) blocks = (int)args.total_tiles;
+    return args.rows && !args.persistent && (!(dtmask & kColorBit) || small_palette) &&
+           args.total_tiles <= 0x7fffffffLL;
+}
+
+int launch_workgroups(int dtmask, const PersistentArgs& args, int blocks) {
+    return one_wave_launch(dtmask, args) ? (int)args.total_tiles : blocks;
+}
+
+hipError_t launch_tiled(int unroll, int defer, int dtmask, int blocks, const PersistentArgs& args,
+                        hipStream_t stream) {
+    const bool one_wave = one_wave_launch(dtmask, args);
+    blocks = launch_workgroups(dtmask, args, blocks);
+    if (args.palette_len > 0) dtmask |= kColorBit;
     const unsigned threads = one_wave ? 64u : 256u;
     TiledFn fn = args.rows ? pick_rows(unroll, dtmask, one_wave)
                            : pick(unroll, defer, dtmask, args.hybrid);

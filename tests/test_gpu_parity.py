@@ -407,3 +407,27 @@ def test_rows_wide_frame_offsets():
     np.testing.assert_array_equal(got, want)
     del out
     torch.cuda.empty_cache()
+
+
+def test_plan_info_reports_the_launched_grid():
+    """jr_plan_info counts the workgroups actually launched: one per tile for
+    dispatched rows tiles (counts, or colours from a small FP32 palette), one
+    per four tiles otherwise."""
+    frames = [Frame(complex(-0.8, 0.156), (-1.5, 1.5, -1.5, 1.5), 200, 130, 100, "fp32")]
+    rows = jr.Schedule(64, 16, 8, 0, 16, 0, 16, "cost", "rows", 16, 32)
+    tiled = jr.Schedule(64, 16, 8, 0, 16, 0, 16, "cost")
+    small = torch.arange(100, dtype=torch.int32, device="cuda")
+    large = torch.arange(300, dtype=torch.int32, device="cuda")
+    for sched, pal, one_per_tile in ((rows, None, True), (rows, small, True),
+                                     (rows, large, False), (tiled, None, False)):
+        plan = jr.Plan(frames, sched)
+        try:
+            if pal is not None:
+                plan.set_palette(pal)
+            info = plan.info()
+            want = info["tiles"] if one_per_tile else (info["tiles"] + 3) // 4
+            assert info["tiles"] == 4 * 9 and info["workgroups"] == want, (sched, info)
+            plan.launch()
+            torch.cuda.synchronize()
+        finally:
+            plan.close()
