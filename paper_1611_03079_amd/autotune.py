@@ -36,7 +36,7 @@ REFILLS = [8, 16, 32, 64]
 WAVES = [8, 16, 24, 32]
 HYBRID_BAILS = [4, 8, 16, 32]
 ROWS_FIRST = [4, 8, 12, 16, 20, 24, 32, 48, 64]
-ROWS_HANDOFF = [0, 16, 32, 64, 96, 128]
+ROWS_HANDOFF = [0, 16, 32, 64, 96, 128, 160, 192]
 
 DEFAULT_CACHE = os.environ.get(
     "JR_AUTOTUNE_CACHE",
