@@ -41,8 +41,8 @@ SCHEDULES = [
     jr.Schedule(64, 64, 8, 0, 8, 0, 16, "cost", "rows", 1),   # 64-row tiles, one-wave workgroups
     jr.Schedule(1, 1, 4, 0, 1, 1, 4, "cost", "rows", 64),     # one-pixel tiles, long first block
     jr.Schedule(64, 64, 4, 0, 8, 1, 8, "table", "rows", 8),   # several list drains per tile
-    jr.Schedule(64, 64, 8, 0, 16, 0, 16, "cost", "rows", 64, 48),  # pairs hand off early
-    jr.Schedule(37, 5, 4, 0, 32, 1, 8, "table", "rows", 12, 128),  # every pair after one trip
+    jr.Schedule(64, 64, 8, 0, 16, 0, 16, "cost", "rows", 64, 48),  # groups hand off early
+    jr.Schedule(37, 5, 4, 0, 32, 1, 8, "table", "rows", 12, 128),  # often after one trip
 ]
 
 
@@ -128,6 +128,20 @@ def test_cap_edge_cases(dtype):
             np.testing.assert_array_equal(views[0], ref(f))
     assert not gpu(C1, UNIT, 40, 30, 0, dtype).any()
     assert not gpu(C1, UNIT, 40, 30, 0, dtype, plain=True).any()
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_cap_edge_cases_rows(dtype):
+    """Caps around the rows kernel's first-block boundaries (multiples of 4,
+    P itself, one either side) with and without early handoff."""
+    scheds = [jr.Schedule(64, 16, 8, 0, 16, 0, 16, "cost", "rows", 8, 0),
+              jr.Schedule(64, 32, 8, 0, 16, 0, 16, "cost", "rows", 48, 96),
+              jr.Schedule(64, 64, 4, 0, 8, 0, 16, "cost", "rows", 12, 256)]
+    for it in (0, 1, 3, 4, 5, 7, 8, 9, 11, 12, 13, 47, 48, 49, 60):
+        f = Frame(C1, UNIT, 70, 37, it, dtype)
+        for s in scheds:
+            _, views = batch([f], s)
+            np.testing.assert_array_equal(views[0], ref(f), err_msg="cap %d %s" % (it, s))
 
 
 # ------------------------------------------------------------------ batches
