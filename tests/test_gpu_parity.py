@@ -445,3 +445,40 @@ def test_plan_info_reports_the_launched_grid():
             torch.cuda.synchronize()
         finally:
             plan.close()
+
+
+def test_point_symmetry_of_the_full_parameter_path():
+    """Z -> -Z maps every orbit of Z^2 + C onto one with the same |Z|, and the
+    three formulations commute with that sign change exactly (squares and the
+    (2x)y product see both signs flipped; round-to-nearest is odd).  On a
+    window centred on 0 the binary64 pixel centres of (i, j) and
+    (W-1-i, H-1-j) are exact negatives, so every image equals itself turned
+    by 180 degrees.  Checked on all 256 frames at full size (530 M pixels)
+    with the tuned schedule of the benchmark, and on FP64 and float-float
+    frames of the path."""
+    from paper_1611_03079_amd import autotune as at
+    frames = wl.parameter_path()
+    e = at.load_cache().get("_workloads", {}).get("parameter_path_fp32")
+    sched = jr.Schedule(**e["schedule"]) if e else None
+    arena, views = jr.render_batch(frames, sched)
+    for k, v in enumerate(views):
+        assert torch.equal(v, v.flip(0).flip(1)), "frame %d" % k
+    del arena, views
+    others = [Frame(f.c, f.window, 640, 360, f.max_iter, dt)
+              for f in frames[::37] for dt in ("fp64", "ff")]
+    _, views = batch(others, None)
+    for f, v in zip(others, views):
+        assert (v == v[::-1, ::-1]).all(), str(f)
+    torch.cuda.empty_cache()
+
+
+def test_mirror_symmetry_of_mandelbrot_frames():
+    """With Z_0 = 0 the orbit of conj(C) is the conjugate orbit, and the
+    formulations commute with conjugation exactly; on a window symmetric in
+    Im the image equals its top-bottom mirror."""
+    frames = [Frame(0j, (-2.1, 0.7, -1.2, 1.2), 700, 601, 300, dt, "mandelbrot")
+              for dt in ("fp64", "fp32", "ff")]
+    for sched in (None, jr.Schedule(64, 32, 8, 0, 16, 0, 16, "cost", "rows", 48, 96)):
+        _, views = batch(frames, sched)
+        for f, v in zip(frames, views):
+            assert (v == v[::-1, :]).all(), str(f)
