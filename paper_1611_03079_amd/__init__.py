@@ -2,7 +2,7 @@
 
 Argument marshalling only: every step of the computation runs in the HIP
 kernels of ``csrc/``; torch supplies device memory and streams.  The library
-must be built (``python -m paper_1611_03079_amd.build``); importing this module
+must be built (``python paper_1611_03079_amd/build.py``); importing this module
 without it raises, and nothing here falls back to a CPU path.
 
 Method: Mayfield et al., Section 2 (iterate Z^2 + C from pixels scaled onto a
@@ -106,7 +106,7 @@ def _load():
     # the process holds one HIP runtime, not two.
     import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
-        raise ImportError("libjulia.so is not built (%s); run python -m paper_1611_03079_amd.build"
+        raise ImportError("libjulia.so is not built (%s); run python paper_1611_03079_amd/build.py"
                           % LIB_PATH)
     lib = ctypes.CDLL(LIB_PATH)
     runtimes = set()

@@ -12,7 +12,13 @@ HEADER = os.path.join(ROOT, "include", "julia.h")
 
 
 def _ensure_built():
-    from paper_1611_03079_amd import build as b
+    # the build module is loaded by path: importing the package itself needs
+    # the library that is about to be built
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "_jr_build", os.path.join(ROOT, "paper_1611_03079_amd", "build.py"))
+    b = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(b)
     if not os.path.exists(b.LIB):
         b.build()
 

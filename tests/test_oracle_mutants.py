@@ -55,6 +55,18 @@ MUTANTS = {
     "general_ff_cross": ("dw p_ir = dw_mul(wi, x);", "dw p_ir = dw_mul(wi, y);"),
     "mandel_z0_is_c": ("return jro_count(dtype, 0.0, 0.0, x, y, max_iter);",
                        "return jro_count(dtype, x, y, x, y, max_iter);"),
+    # the per-pixel entry points: column and row swapped, width and height
+    # swapped, the list index shifted by one, the mode dropped
+    "pixels_ij_swap": ("                             W, H, max_iter, ii[k], jj[k]);",
+                       "                             W, H, max_iter, jj[k], ii[k]);"),
+    "pixels_general_ij_swap": ("im_max, W, H, max_iter, ii[k], jj[k]);",
+                               "im_max, W, H, max_iter, jj[k], ii[k]);"),
+    "pixels_general_wh_swap": ("im_max, W, H, max_iter, ii[k], jj[k]);",
+                               "im_max, H, W, max_iter, ii[k], jj[k]);"),
+    "pixels_index_shift": ("                             W, H, max_iter, ii[k], jj[k]);",
+                           "                             W, H, max_iter, ii[k], jj[k > 0 ? k - 1 : 0]);"),
+    "pixels_mode_dropped": ("        out[k] = pixel_count(dtype, mode, cr, ci,",
+                            "        out[k] = pixel_count(dtype, JRO_JULIA, cr, ci,"),
 }
 
 
@@ -80,6 +92,9 @@ def _battery():
                ("general_numpy_ff_3", pins.test_general_matches_numpy_reimplementation,
                 ("ff", 3)),
                ("dw_bounds", pins.test_double_word_error_bounds, ())]
+    checks += [("pixels_%s_%d_%d" % (d, case, deg), pins.test_render_pixels_matches_whole_images,
+                (d, case, deg))
+               for d, case, deg in (("fp64", 0, 2), ("fp32", 1, 2), ("ff", 0, 3), ("fp64", 1, 5))]
     for name, fn, args in checks:
         try:
             fn(*args)

@@ -614,3 +614,47 @@ def test_general_exact_rational_counts_small_cap():
                 assert got[j, i] == n, (i, j, got[j, i], n)
                 compared += 1
     assert compared >= 60
+
+
+# ------------------------------------------- per-pixel entry points
+# jro_render_pixels and jro_render_pixels_general check every sampled and
+# full-size GPU test, and time the CPU baseline.  They must give, at any list
+# of (column, row) pairs, the counts that the independent numpy
+# implementation gives at those pixels of the whole image (and that the
+# oracle's own whole-image loop gives).  The grid is not square and the list
+# holds every pixel in a shuffled order, repeats and the four corners, so a
+# swapped column/row, a swapped width/height, a shifted list index or a lost
+# mode fails here.
+PIXEL_CASES = [
+    # c, window, W, H, cap, mode
+    (complex(0.285, 0.01), (-1.3, 1.1, -0.7, 0.95), 29, 23, 80, "julia"),
+    (0j, (-2.0, 0.7, -1.1, 1.2), 31, 19, 60, "mandelbrot"),
+]
+
+
+def _pixel_list(W, H, seed):
+    rng = np.random.default_rng(seed)
+    k = rng.permutation(W * H)
+    ii, jj = (k % W), (k // W)
+    extra = rng.integers(0, W * H, 40)
+    ii = np.concatenate([ii, extra % W, [0, W - 1, 0, W - 1]])
+    jj = np.concatenate([jj, extra // W, [0, 0, H - 1, H - 1]])
+    return ii.astype(np.int32), jj.astype(np.int32)
+
+
+@pytest.mark.parametrize("degree", [2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("case", range(len(PIXEL_CASES)))
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_render_pixels_matches_whole_images(dtype, case, degree):
+    c, win, W, H, cap, mode = PIXEL_CASES[case]
+    ii, jj = _pixel_list(W, H, 7 * case + degree)
+    got = oracle.render_pixels(c, win, W, H, cap, ii, jj, dtype, mode, degree)
+    if degree == 2:
+        twin = ind.render(c, win, W, H, cap, dtype, mode)
+    else:
+        twin = ind.render_general(c, win, W, H, cap, dtype, mode, degree)
+    np.testing.assert_array_equal(got, twin[jj, ii])
+    whole = oracle.render(c, win, W, H, cap, dtype, mode, degree)
+    np.testing.assert_array_equal(got, whole[jj, ii])
+    # the images must not be trivial: several distinct counts, some capped
+    assert len(np.unique(got)) >= 5 and (got == cap).any()
