@@ -61,6 +61,15 @@ enum {
     JR_EINTERNAL = -5  /* broken invariant inside the library              */
 };
 
+/*
+ * Largest iteration cap of any call (2^30).  The kernels keep iteration
+ * counters in 32-bit integers and test a block's end as n + K >= max_iter;
+ * a lane whose pixel is done keeps advancing its counter until the wave's
+ * last orbit ends, by up to max_iter more.  With max_iter <= 2^30 no counter
+ * passes 2^31 - 1.  Larger caps are rejected with JR_EINVAL.
+ */
+#define JR_MAX_ITER (1 << 30)
+
 typedef enum { JR_FP64 = 0, JR_FP32 = 1, JR_FF = 2 } jr_dtype;
 typedef enum { JR_JULIA = 0, JR_MANDELBROT = 1 } jr_mode;
 typedef enum { JR_ORDER_TABLE = 0, JR_ORDER_COST = 1 } jr_order;
@@ -75,7 +84,7 @@ typedef struct { double re_min, re_max, im_min, im_max; } jr_window;
  * [row_begin, row_end) are computed by this call (row_end = 0 means height),
  * so a large frame can be split over several calls.  `c` is ignored in
  * Mandelbrot mode.  Limits: width, height >= 1, width*height < 2^31,
- * 0 <= max_iter < 2^31, out_offset >= 0, out_offset + width*height <=
+ * 0 <= max_iter <= JR_MAX_ITER, out_offset >= 0, out_offset + width*height <=
  * out_capacity.
  *
  * degree selects the map (the paper's further functions, Section 4):

@@ -204,6 +204,26 @@ def _out_tensor(out, shape):
     return out
 
 
+def _arena_tensor(arena, need: int, colours: bool = False):
+    """Check a caller's output arena before its pointer and element count go
+    to the library: a contiguous CUDA tensor of 32-bit elements (int32, or
+    uint32 for colours) on the current device, holding at least `need`
+    elements.  Anything else would hand the kernel a host address, a range
+    shorter in bytes than its element count, or a strided view."""
+    import torch
+    ok = (torch.int32, torch.uint32) if colours else (torch.int32,)
+    if not isinstance(arena, torch.Tensor) or arena.dtype not in ok:
+        raise ValueError("arena must be an %s CUDA tensor" % "/".join(str(d) for d in ok))
+    if not arena.is_cuda or not arena.is_contiguous():
+        raise ValueError("arena must be a contiguous CUDA tensor")
+    if arena.device.index != torch.cuda.current_device():
+        raise ValueError("arena is on cuda:%d, the current device is cuda:%d"
+                         % (arena.device.index, torch.cuda.current_device()))
+    if arena.numel() < need:
+        raise ValueError("arena holds %d elements, the frames need %d" % (arena.numel(), need))
+    return arena
+
+
 PALETTE_MAX = 8192  # JR_PALETTE_MAX
 
 
@@ -390,6 +410,7 @@ def render_batch(frames: Sequence, schedule: Optional[Schedule] = None, arena=No
         total = max(int(o) + f.width * f.height for o, f in zip(offsets, frames))
     if arena is None:
         arena = torch.empty(total, dtype=torch.int32, device="cuda")
+    _arena_tensor(arena, total, colours=palette is not None)
     arr = _frames_array(frames, offsets, rows)
     sched = ctypes.byref(schedule.to_c()) if schedule is not None else None
     if palette is not None:
@@ -412,12 +433,14 @@ class Plan:
     def __init__(self, frames: Sequence, schedule: Optional[Schedule] = None, arena=None,
                  offsets=None):
         import torch
+        self._h = None
         if offsets is None:
             offsets, total = arena_layout(frames)
         else:
             total = max(int(o) + f.width * f.height for o, f in zip(offsets, frames))
         self.arena = arena if arena is not None else torch.empty(total, dtype=torch.int32,
                                                                  device="cuda")
+        _arena_tensor(self.arena, total)
         self.frames = list(frames)
         self.offsets = list(offsets)
         arr = _frames_array(frames, offsets)

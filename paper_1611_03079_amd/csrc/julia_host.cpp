@@ -27,17 +27,17 @@ using jr::DevFrame;
 
 namespace {
 
-thread_local std::string g_last_msg;
+// The last failure's message on this thread (a fixed buffer: recording an
+// error allocates nothing).
+thread_local char g_last_msg[512];
 
 static_assert(jr::kPaletteMax == JR_PALETTE_MAX, "one palette limit");
 
 int fail(int code, const char* fmt, ...) {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vsnprintf(g_last_msg, sizeof g_last_msg, fmt, ap);
     va_end(ap);
-    g_last_msg = buf;
     return code;
 }
 
@@ -79,7 +79,8 @@ int check_image(int32_t W, int32_t H, int32_t max_iter, int32_t dtype, int32_t m
         return fail(JR_EINVAL, "%s: width and height must be >= 1 (got %d x %d)", who, W, H);
     if ((int64_t)W * (int64_t)H > (int64_t)INT32_MAX)
         return fail(JR_EINVAL, "%s: width*height must be < 2^31", who);
-    if (max_iter < 0) return fail(JR_EINVAL, "%s: max_iter must be >= 0", who);
+    if (max_iter < 0 || max_iter > JR_MAX_ITER)
+        return fail(JR_EINVAL, "%s: max_iter %d outside 0..%d", who, max_iter, JR_MAX_ITER);
     if (dtype != JR_FP64 && dtype != JR_FP32 && dtype != JR_FF)
         return fail(JR_EINVAL, "%s: unknown dtype %d", who, dtype);
     if (mode != JR_JULIA && mode != JR_MANDELBROT)
@@ -270,50 +271,68 @@ jr::PersistentArgs make_args(const Table& t, const DevFrame* d_table, int32_t* o
     return a;
 }
 
+// The device record of frame f whose first tile is global tile `tile_begin`;
+// returns its tile count.
+int64_t fill_frame(const jr_frame& f, const jr_schedule& s, int64_t tile_begin, DevFrame& d) {
+    std::memset(&d, 0, sizeof d);
+    const double W = (double)f.width, H = (double)f.height;
+    d.hx = (f.w.re_max - f.w.re_min) / (2.0 * W);
+    d.hy = (f.w.im_max - f.w.im_min) / (2.0 * H);
+    d.cx = 0.5 * (f.w.re_min + f.w.re_max);
+    d.cy = 0.5 * (f.w.im_min + f.w.im_max);
+    d.cr = f.mode == JR_JULIA ? f.c.re : 0.0;
+    d.ci = f.mode == JR_JULIA ? f.c.im : 0.0;
+    d.out_offset = f.out_offset;
+    d.width = f.width;
+    d.height = f.height;
+    d.max_iter = f.max_iter;
+    d.dtype = f.dtype;
+    d.mode = f.mode;
+    d.defer = absorbing(f) ? 1 : 0;
+    d.degree = f.degree == 0 ? 2 : f.degree;
+    d.row_begin = f.row_begin;
+    d.row_end = f.row_end == 0 ? f.height : f.row_end;
+    const int32_t tw = s.kernel == JR_KERNEL_PLAIN ? 16 : s.tile_w;
+    const int32_t th = s.kernel == JR_KERNEL_PLAIN ? 16 : s.tile_h;
+    d.tile_w = std::min(tw, f.width);
+    d.tile_h = std::min(th, d.row_end - d.row_begin);
+    d.tiles_x = (f.width + d.tile_w - 1) / d.tile_w;
+    const int64_t tiles_y = (d.row_end - d.row_begin + d.tile_h - 1) / d.tile_h;
+    d.tile_begin = tile_begin;
+    return (int64_t)d.tiles_x * tiles_y;
+}
+
+// The order frames go into the table: as given, or (JR_ORDER_COST) most
+// expensive first, equal costs in the order given.  std::sort with the index
+// as tie-break needs no scratch memory, unlike a stable sort.
+void order_frames(const jr_frame* frames, int32_t n, const jr_schedule& s, int32_t* idx) {
+    std::iota(idx, idx + n, 0);
+    if (s.order == JR_ORDER_COST)
+        std::sort(idx, idx + n, [&](int32_t a, int32_t b) {
+            const double ca = frame_cost(frames[a]), cb = frame_cost(frames[b]);
+            return ca > cb || (ca == cb && a < b);
+        });
+}
+
+// Adds a frame's tiles to the table totals.
+void account(Table& t, const jr_frame& f, const DevFrame& d, int64_t tiles) {
+    t.total_tiles += tiles;
+    t.total_cost += frame_cost(f);
+    t.max_tile_cost = std::max(t.max_tile_cost, frame_cost(f) / (double)tiles);
+    t.dtmask |= 1 << f.dtype;
+    if (d.degree > 2) t.dtmask |= jr::kGeneralBit;
+}
+
 void build_table(const jr_frame* frames, int32_t n, const jr_schedule& s, Table& t) {
     std::vector<int32_t> idx(n);
-    std::iota(idx.begin(), idx.end(), 0);
-    if (s.order == JR_ORDER_COST)
-        std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) {
-            return frame_cost(frames[a]) > frame_cost(frames[b]);
-        });
+    order_frames(frames, n, s, idx.data());
     t.rows.resize(n);
     t.total_tiles = 0;
     t.dtmask = 0;
     for (int32_t k = 0; k < n; ++k) {
         const jr_frame& f = frames[idx[k]];
-        DevFrame& d = t.rows[k];
-        std::memset(&d, 0, sizeof d);
-        const double W = (double)f.width, H = (double)f.height;
-        d.hx = (f.w.re_max - f.w.re_min) / (2.0 * W);
-        d.hy = (f.w.im_max - f.w.im_min) / (2.0 * H);
-        d.cx = 0.5 * (f.w.re_min + f.w.re_max);
-        d.cy = 0.5 * (f.w.im_min + f.w.im_max);
-        d.cr = f.mode == JR_JULIA ? f.c.re : 0.0;
-        d.ci = f.mode == JR_JULIA ? f.c.im : 0.0;
-        d.out_offset = f.out_offset;
-        d.width = f.width;
-        d.height = f.height;
-        d.max_iter = f.max_iter;
-        d.dtype = f.dtype;
-        d.mode = f.mode;
-        d.defer = absorbing(f) ? 1 : 0;
-        d.degree = f.degree == 0 ? 2 : f.degree;
-        d.row_begin = f.row_begin;
-        d.row_end = f.row_end == 0 ? f.height : f.row_end;
-        const int32_t tw = s.kernel == JR_KERNEL_PLAIN ? 16 : s.tile_w;
-        const int32_t th = s.kernel == JR_KERNEL_PLAIN ? 16 : s.tile_h;
-        d.tile_w = std::min(tw, f.width);
-        d.tile_h = std::min(th, d.row_end - d.row_begin);
-        d.tiles_x = (f.width + d.tile_w - 1) / d.tile_w;
-        const int64_t tiles_y = (d.row_end - d.row_begin + d.tile_h - 1) / d.tile_h;
-        d.tile_begin = t.total_tiles;
-        t.total_tiles += (int64_t)d.tiles_x * tiles_y;
-        const double tile_cost = frame_cost(f) / (double)((int64_t)d.tiles_x * tiles_y);
-        t.total_cost += frame_cost(f);
-        t.max_tile_cost = std::max(t.max_tile_cost, tile_cost);
-        t.dtmask |= 1 << f.dtype;
-        if (d.degree > 2) t.dtmask |= jr::kGeneralBit;
+        const int64_t tiles = fill_frame(f, s, t.total_tiles, t.rows[k]);
+        account(t, f, t.rows[k], tiles);
     }
 }
 
@@ -325,11 +344,14 @@ struct DeviceInfo {
     int64_t hbm = 0;
 };
 std::mutex g_dev_mu;
-std::map<int, DeviceInfo> g_dev;
+constexpr int kMaxDevices = 64;
+DeviceInfo g_dev[kMaxDevices];
 
 int current_device(int* dev, DeviceInfo* info) {
     hipError_t e = hipGetDevice(dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (*dev < 0 || *dev >= kMaxDevices)
+        return fail(JR_ENODEV, "device %d beyond the library's %d", *dev, kMaxDevices);
     std::lock_guard<std::mutex> g(g_dev_mu);
     DeviceInfo& d = g_dev[*dev];
     if (!d.probed) {
@@ -605,7 +627,7 @@ const char* jr_strerror(int code) {
     }
 }
 
-const char* jr_last_error_message(void) { return g_last_msg.c_str(); }
+const char* jr_last_error_message(void) { return g_last_msg; }
 
 int jr_check_schedule(const jr_schedule* s) {
     if (!s) return fail(JR_EINVAL, "schedule is null");

@@ -94,17 +94,34 @@ class _Req:
 
 @dataclass
 class Stats:
+    """Latency and throughput of a run.  `latencies` holds the completed
+    requests' latencies; `unfinished` the requests still pending when the run
+    was cut off, each at the time it had waited by then (a lower bound of its
+    latency).  Percentiles count both, so a loop that falls behind cannot
+    report only the requests it managed to finish."""
     latencies: List[float] = field(default_factory=list)
+    unfinished: List[float] = field(default_factory=list)
     completed: int = 0
     pixels: int = 0
     steps: int = 0
     t_first: float = math.inf
     t_last: float = 0.0
 
-    def percentile(self, q: float) -> float:
-        if not self.latencies:
+    @property
+    def offered(self) -> int:
+        return self.completed + len(self.unfinished)
+
+    @property
+    def saturated(self) -> bool:
+        """Requests were left pending: the offered rate exceeded what the
+        loop sustained, and the percentiles are lower bounds."""
+        return len(self.unfinished) > 0
+
+    def percentile(self, q: float, completed_only: bool = False) -> float:
+        xs = self.latencies if completed_only else self.latencies + self.unfinished
+        if not xs:
             return math.nan
-        xs = sorted(self.latencies)
+        xs = sorted(xs)
         k = min(len(xs) - 1, max(0, int(math.ceil(q / 100.0 * len(xs))) - 1))
         return xs[k]
 
@@ -183,6 +200,15 @@ class Server:
     def pending(self) -> int:
         with self.lock:
             return len(self.queue) + len(self.active) + len(self.fetching)
+
+    def censor(self, t: float):
+        """Record every request still pending at time t as unfinished, with
+        the latency it has accumulated by t (the run is over)."""
+        with self.lock:
+            waiting = list(self.queue) + list(self.active)
+        for r in waiting:
+            self.stats.unfinished.append(t - r.arrival)
+            self.stats.t_first = min(self.stats.t_first, r.arrival)
 
     # ------------------------------------------------------------- scheduler
     def _admit(self):
@@ -301,4 +327,5 @@ def run_open_loop(server: Server, requests, drain_timeout: float = 60.0) -> Stat
     while server.pending() and time.perf_counter() < t_end:
         time.sleep(0.001)
     server.stop()
+    server.censor(time.perf_counter())
     return server.stats

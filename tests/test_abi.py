@@ -63,6 +63,7 @@ def _render(**kw):
 
 @pytest.mark.parametrize("kw", [
     dict(W=0), dict(H=0), dict(W=-3), dict(W=65536, H=65536), dict(it=-1), dict(dt=3),
+    dict(it=2 ** 30 + 1), dict(it=2 ** 31 - 1), dict(it=2 ** 31 - 65),
     dict(dt=-1), dict(out=ctypes.c_void_p(0)), dict(out=ctypes.c_void_p(0x10002)),
     dict(c=jr.jr_complex(math.nan, 0.0)), dict(c=jr.jr_complex(0.0, math.inf)),
     dict(w=jr.jr_window(1.0, 1.0, -1.0, 1.0)), dict(w=jr.jr_window(-1.0, 1.0, 2.0, 1.0)),
@@ -71,6 +72,20 @@ def _render(**kw):
 def test_render_rejects_invalid_arguments(kw):
     assert _render(**kw) == jr.JR_EINVAL
     assert jr.last_error()
+
+
+def test_cap_limit_is_accepted_and_one_past_it_rejected():
+    """JR_MAX_ITER = 2^30 is the largest cap (the kernels' counters stay in
+    int32).  The cap's validation comes before any device call: with a null
+    output the limit itself fails on the output, one past it on the cap."""
+    assert _render(it=2 ** 30, out=ctypes.c_void_p(0)) == jr.JR_EINVAL
+    assert "output" in jr.last_error()
+    assert _render(it=2 ** 30 + 1) == jr.JR_EINVAL
+    assert "max_iter" in jr.last_error()
+    fr = [Frame(complex(-0.8, 0.156), (-1.5, 1.5, -1.5, 1.5), 8, 8, 2 ** 30, "fp32")]
+    assert jr.check_frames(fr, [0], 64) == jr.JR_OK
+    fr[0].max_iter = 2 ** 30 + 1
+    assert jr.check_frames(fr, [0], 64) == jr.JR_EINVAL
 
 
 def test_plain_and_mandelbrot_validate_too():
@@ -256,3 +271,21 @@ def test_autotune_buckets():
     assert at.cap_bucket(100) == "cap<=128" and at.cap_bucket(129) == "cap<=1024"
     assert at.cache_key("gfx950", "fp64", 100, 512 * 512) == "gfx950|fp64|cap<=128|px<512K"
     assert at.cache_key("gfx950", "fp32", 100, 1 << 29, batch=True).endswith("|batch")
+
+
+@pytest.mark.parametrize("make", ["cpu_int32", "cpu_int16", "cpu_float32"])
+def test_batch_arena_is_checked_before_any_launch(make):
+    """render_batch and Plan pass the arena's address and element count to
+    the library, so an arena that is not a contiguous int32 CUDA tensor is
+    refused in Python first: a host tensor would give the kernel a host
+    address, and a 16-bit one fewer bytes than its element count."""
+    import torch
+    fr = _frames()
+    n = sum(f.pixels for f in fr)
+    arena = {"cpu_int32": lambda: torch.zeros(n, dtype=torch.int32),
+             "cpu_int16": lambda: torch.zeros(2 * n, dtype=torch.int16),
+             "cpu_float32": lambda: torch.zeros(n, dtype=torch.float32)}[make]()
+    with pytest.raises(ValueError):
+        jr.render_batch(fr, arena=arena)
+    with pytest.raises(ValueError):
+        jr.Plan(fr, arena=arena)

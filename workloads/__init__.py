@@ -217,3 +217,42 @@ FIG1_SIDES = (10, 32, 100, 316, 1000, 3162, 10000)
 def square_sweep(dtype: str = "fp64", sides=FIG1_SIDES) -> List[Frame]:
     base = single_512(dtype)
     return [Frame(base.c, base.window, s, s, 100, dtype) for s in sides]
+
+
+# --------------------------------------------------------------------------
+# Precision windows: the serving stream's windows at one fixed width.  Each
+# window has a constant from the uneven-batch sampler and a centre uniform in
+# [-1.5, 1.5]^2, is `width` wide with the 640x480 aspect, and is probed at
+# `pixels` pixel positions drawn uniformly from its 640x480 grid.
+# --------------------------------------------------------------------------
+PRECISION_WIDTHS = (3.0, 1e-1, 1e-3, 1e-5, 1e-7, 1e-9)
+PRECISION_CAPS = (100, 1000, 5000)
+
+
+@dataclass
+class ProbeWindow:
+    frame: Frame          # 640 x 480, dtype left to the caller
+    ii: List[int]         # probed columns
+    jj: List[int]         # probed rows
+
+
+def precision_windows(seed: int, width: float, max_iter: int, n: int = 32,
+                      pixels: int = 1024, size=(640, 480)) -> List[ProbeWindow]:
+    rng = SplitMix64(seed)
+    W, H = size
+    out = []
+    for _ in range(n):
+        c = sample_c_disk(rng)
+        cre = -1.5 + 3.0 * rng.uniform()
+        cim = -1.5 + 3.0 * rng.uniform()
+        height = width * H / W
+        win = (cre - 0.5 * width, cre + 0.5 * width, cim - 0.5 * height, cim + 0.5 * height)
+        ii = [rng.randint(0, W - 1) for _ in range(pixels)]
+        jj = [rng.randint(0, H - 1) for _ in range(pixels)]
+        out.append(ProbeWindow(Frame(c, win, W, H, max_iter, "fp64"), ii, jj))
+    return out
+
+
+def precision_seed(width: float, max_iter: int) -> int:
+    """The seed of a (width, cap) cell of the precision table."""
+    return 1000 + 10 * PRECISION_WIDTHS.index(width) + PRECISION_CAPS.index(max_iter)
