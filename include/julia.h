@@ -219,6 +219,28 @@ int julia_render_batch(const jr_frame *frames, int32_t n, int32_t *out_base,
                        int64_t out_capacity, const jr_schedule *sched, void *stream);
 
 /*
+ * Allocation-free form of julia_render_batch, for callers that cannot allocate
+ * memory: code under hipGraph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, frames, schedules, kernels and counts as
+ * julia_render_batch, but the call allocates nothing, on the device or the
+ * host: the frame table and the work-queue counters live in one fixed device
+ * array of the library (JR_NOALLOC_SCRATCH_BYTES, one copy per GPU, held until
+ * the process ends), and the table reaches it through kernel arguments, in
+ * stream order, so `frames` may be reused once the call returns.  The queue
+ * counters are zeroed by a kernel before each launch that uses them.
+ *   n            1 .. JR_NOALLOC_MAX_FRAMES; more frames are rejected with
+ *                JR_EINVAL before anything reaches the device.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents: calls that overlap on one GPU (on different streams, or from
+ * several threads without ordering) race and may render wrong images.  Order
+ * them, on one stream or with events.  Other errors are julia_render_batch's.
+ */
+#define JR_NOALLOC_MAX_FRAMES 1024
+#define JR_NOALLOC_SCRATCH_BYTES (64 * 4096 + JR_NOALLOC_MAX_FRAMES * 112)
+int julia_render_batch_noalloc(const jr_frame *frames, int32_t n, int32_t *out_base,
+                               int64_t out_capacity, const jr_schedule *sched, void *stream);
+
+/*
  * Fused count -> colour store (Section 2: every pixel is given a colour level
  * by its iteration count).  The frames, schedules and kernels are those of
  * julia_render_batch; only the stored value changes: each pixel stores the

@@ -90,7 +90,8 @@ class Schedule:
 
 EXPORTS = (
     "julia_render", "julia_render_plain", "mandelbrot_render", "mandelbrot_render_plain",
-    "julia_render_batch", "julia_render_batch_colored", "julia_render_colored",
+    "julia_render_batch", "julia_render_batch_noalloc", "julia_render_batch_colored",
+    "julia_render_colored",
     "jr_plan_create", "jr_plan_set_palette", "jr_set_image_schedule", "jr_get_image_schedule",
     "jr_clear_image_schedules", "jr_plan_launch", "jr_plan_capture",
     "jr_plan_replay", "jr_plan_info", "jr_plan_destroy", "jr_get_default_schedule",
@@ -128,6 +129,8 @@ def _load():
         getattr(lib, name).restype = ctypes.c_int
     lib.julia_render_batch.argtypes = [P(jr_frame), i32, vp, i64, P(jr_schedule), vp]
     lib.julia_render_batch.restype = ctypes.c_int
+    lib.julia_render_batch_noalloc.argtypes = [P(jr_frame), i32, vp, i64, P(jr_schedule), vp]
+    lib.julia_render_batch_noalloc.restype = ctypes.c_int
     lib.julia_render_batch_colored.argtypes = [P(jr_frame), i32, vp, i32, vp, i64,
                                                P(jr_schedule), vp]
     lib.julia_render_batch_colored.restype = ctypes.c_int
@@ -425,6 +428,29 @@ def render_batch(frames: Sequence, schedule: Optional[Schedule] = None, arena=No
     views = [arena[o: o + f.width * f.height].view(f.height, f.width)
              for o, f in zip(offsets, frames)]
     return arena, views
+
+
+NOALLOC_MAX_FRAMES = 1024  # JR_NOALLOC_MAX_FRAMES
+
+
+def render_batch_noalloc(frames: Sequence, arena, schedule: Optional[Schedule] = None,
+                         offsets=None, stream=None):
+    """render_batch through julia_render_batch_noalloc: the library allocates
+    nothing for the call (its frame table and queue counters sit in a fixed
+    device array, at most NOALLOC_MAX_FRAMES frames).  The caller provides the
+    int32 arena; returns the frames' views into it.  Calls that overlap on one
+    GPU share that array and race: keep them on one stream."""
+    if offsets is None:
+        offsets, total = arena_layout(frames)
+    else:
+        total = max(int(o) + f.width * f.height for o, f in zip(offsets, frames))
+    _arena_tensor(arena, total)
+    arr = _frames_array(frames, offsets)
+    sched = ctypes.byref(schedule.to_c()) if schedule is not None else None
+    _check(lib.julia_render_batch_noalloc(arr, len(frames), ctypes.c_void_p(arena.data_ptr()),
+                                          arena.numel(), sched, _stream_ptr(stream)))
+    return [arena[o: o + f.width * f.height].view(f.height, f.width)
+            for o, f in zip(offsets, frames)]
 
 
 class Plan:

@@ -85,6 +85,19 @@ struct PlainArgs {
     int32_t W, H, max_iter, mode;
 };
 
+// Allocation-free batch launches (julia_render_batch_noalloc) keep the queue
+// counters and the frame table in one fixed device array of the library, the
+// counters first (kCounterBytes), then room for kNoAllocMaxFrames frames.
+constexpr int kNoAllocMaxFrames = 1024;
+constexpr int kPutFrames = 32;  // frame records per jr_put_frames launch
+constexpr size_t kNoAllocScratchBytes = kCounterBytes + (size_t)kNoAllocMaxFrames * sizeof(DevFrame);
+// Device address of that array on the current device (looked up once per
+// device; `dev` is the current device's index, 0 <= dev < 64).
+hipError_t noalloc_scratch(int dev, void** ptr);
+// Writes rows[0, n) to the device table dst in stream order through kernel
+// arguments (no copy call, no staging memory): ceil(n / kPutFrames) launches.
+hipError_t put_frames(const DevFrame* rows, int n, DevFrame* dst, hipStream_t stream);
+
 // Runs the tiled kernel; in persistent mode a small kernel zeroes the queue
 // counters first (both may be captured into a hipGraph).
 hipError_t launch_tiled(int unroll, int defer, int dtmask, int blocks, const PersistentArgs& args,

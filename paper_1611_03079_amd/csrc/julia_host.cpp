@@ -233,25 +233,29 @@ bool absorbing(const jr_frame& f) {
     return m <= kAbsorbingC;
 }
 
-struct Table {
-    std::vector<DevFrame> rows;
+// Totals of a frame table, for the launch shape and the kernel variant.
+struct TableStats {
     int64_t total_tiles = 0;
     double total_cost = 0.0;     // estimated, arbitrary units
     double max_tile_cost = 0.0;  // estimated cost of the most expensive tile
     int dtmask = 0;
 };
 
+struct Table : TableStats {
+    std::vector<DevFrame> rows;
+};
+
 // Tiles per granule (one atomic claim): aim at ~16 granules per wave for the
 // most expensive tiles, so that claims stay rare on cheap work and a single
 // claim never holds a large share of a wave's work on expensive frames.
-int32_t granule_size(const Table& t, int blocks) {
+int32_t granule_size(const TableStats& t, int blocks) {
     const double waves = 4.0 * blocks;
     const double target = t.total_cost / (waves * 16.0);
     const double g = std::floor(target / std::max(t.max_tile_cost, 1.0));
     return (int32_t)std::max(1.0, std::min(32.0, g));
 }
 
-jr::PersistentArgs make_args(const Table& t, const DevFrame* d_table, int32_t* out,
+jr::PersistentArgs make_args(const TableStats& t, const DevFrame* d_table, int32_t* out,
                              unsigned long long* ctr, int32_t n, int blocks, const jr_schedule& s) {
     jr::PersistentArgs a;
     std::memset(&a, 0, sizeof a);
@@ -315,7 +319,7 @@ void order_frames(const jr_frame* frames, int32_t n, const jr_schedule& s, int32
 }
 
 // Adds a frame's tiles to the table totals.
-void account(Table& t, const jr_frame& f, const DevFrame& d, int64_t tiles) {
+void account(TableStats& t, const jr_frame& f, const DevFrame& d, int64_t tiles) {
     t.total_tiles += tiles;
     t.total_cost += frame_cost(f);
     t.max_tile_cost = std::max(t.max_tile_cost, frame_cost(f) / (double)tiles);
@@ -323,17 +327,36 @@ void account(Table& t, const jr_frame& f, const DevFrame& d, int64_t tiles) {
     if (d.degree > 2) t.dtmask |= jr::kGeneralBit;
 }
 
-void build_table(const jr_frame* frames, int32_t n, const jr_schedule& s, Table& t) {
-    std::vector<int32_t> idx(n);
-    order_frames(frames, n, s, idx.data());
-    t.rows.resize(n);
-    t.total_tiles = 0;
-    t.dtmask = 0;
+// Fills rows[0, n) in launch order and returns the table's totals; idx is
+// room for n frame indices.  Allocates nothing.
+void build_rows(const jr_frame* frames, int32_t n, const jr_schedule& s, DevFrame* rows,
+                int32_t* idx, TableStats& t) {
+    order_frames(frames, n, s, idx);
+    t = TableStats();
     for (int32_t k = 0; k < n; ++k) {
         const jr_frame& f = frames[idx[k]];
-        const int64_t tiles = fill_frame(f, s, t.total_tiles, t.rows[k]);
-        account(t, f, t.rows[k], tiles);
+        const int64_t tiles = fill_frame(f, s, t.total_tiles, rows[k]);
+        account(t, f, rows[k], tiles);
     }
+}
+
+void build_table(const jr_frame* frames, int32_t n, const jr_schedule& s, Table& t) {
+    std::vector<int32_t> idx(n);
+    t.rows.resize(n);
+    build_rows(frames, n, s, t.rows.data(), idx.data(), t);
+}
+
+// The schedule of a batch call: the caller's, checked, or the default of the
+// dtype with the most estimated work.
+int batch_schedule(const jr_frame* frames, int32_t n, const jr_schedule* sched, jr_schedule& s) {
+    if (sched) {
+        s = *sched;
+        return check_schedule(s);
+    }
+    double w[3] = {0, 0, 0};
+    for (int32_t k = 0; k < n; ++k) w[frames[k].dtype] += frame_cost(frames[k]);
+    s = default_schedule((int)(std::max_element(w, w + 3) - w));
+    return JR_OK;
 }
 
 // ------------------------------------------------------------- devices
@@ -444,15 +467,7 @@ int enqueue_batch(const jr_frame* frames, int32_t n, int32_t* out_base, int64_t 
     if (rc) return rc;
     if ((rc = check_out(out_base, "batch"))) return rc;
     jr_schedule s;
-    if (sched) {
-        s = *sched;
-        if ((rc = check_schedule(s))) return rc;
-    } else {
-        // default of the dtype with the most estimated work
-        double w[3] = {0, 0, 0};
-        for (int32_t k = 0; k < n; ++k) w[frames[k].dtype] += frame_cost(frames[k]);
-        s = default_schedule((int)(std::max_element(w, w + 3) - w));
-    }
+    if ((rc = batch_schedule(frames, n, sched, s))) return rc;
     int dev;
     DeviceInfo info;
     if ((rc = current_device(&dev, &info))) return rc;
@@ -526,6 +541,50 @@ int enqueue_batch(const jr_frame* frames, int32_t n, int32_t* out_base, int64_t 
                        ? jr::launch_plain_batch(t.dtmask, args, stream)
                        : jr::launch_tiled(s.unroll, s.defer, t.dtmask, blocks, args, stream);
     if (e != hipSuccess) return hip_fail(e, "persistent kernel launch");
+    return JR_OK;
+}
+
+// Allocation-free batches: the table is built in these fixed host arrays
+// (under g_na_mu) and written to the device array of jr::noalloc_scratch by
+// kernel arguments, which the runtime copies when a launch is enqueued.
+static_assert(jr::kNoAllocMaxFrames == JR_NOALLOC_MAX_FRAMES, "one frame limit");
+static_assert(jr::kNoAllocScratchBytes == JR_NOALLOC_SCRATCH_BYTES, "one scratch size");
+std::mutex g_na_mu;
+DevFrame g_na_rows[jr::kNoAllocMaxFrames];
+int32_t g_na_idx[jr::kNoAllocMaxFrames];
+
+int enqueue_batch_noalloc(const jr_frame* frames, int32_t n, int32_t* out_base, int64_t capacity,
+                          const jr_schedule* sched, hipStream_t stream) {
+    const char* who = "julia_render_batch_noalloc";
+    if (frames != nullptr && n > JR_NOALLOC_MAX_FRAMES)
+        return fail(JR_EINVAL, "%s: %d frames exceed the allocation-free limit of %d (split the "
+                    "batch, or use julia_render_batch)", who, n, JR_NOALLOC_MAX_FRAMES);
+    int rc = check_frames(frames, n, capacity);
+    if (rc) return rc;
+    if ((rc = check_out(out_base, who))) return rc;
+    jr_schedule s;
+    if ((rc = batch_schedule(frames, n, sched, s))) return rc;
+    int dev;
+    DeviceInfo info;
+    if ((rc = current_device(&dev, &info))) return rc;
+    void* base = nullptr;
+    HIP_TRY(jr::noalloc_scratch(dev, &base), "hipGetSymbolAddress of the scratch array");
+    unsigned long long* ctr = static_cast<unsigned long long*>(base);
+    DevFrame* table = reinterpret_cast<DevFrame*>(static_cast<char*>(base) + jr::kCounterBytes);
+    std::lock_guard<std::mutex> g(g_na_mu);
+    TableStats t;
+    build_rows(frames, n, s, g_na_rows, g_na_idx, t);
+    const int blocks = grid_blocks(info, s, t.total_tiles);
+    jr::PersistentArgs args = make_args(t, n == 1 ? nullptr : table, out_base, ctr, n, blocks, s);
+    if (n == 1) {
+        args.frame0 = g_na_rows[0];
+    } else {
+        HIP_TRY(jr::put_frames(g_na_rows, n, table, stream), "frame table launch");
+    }
+    hipError_t e = s.kernel == JR_KERNEL_PLAIN
+                       ? jr::launch_plain_batch(t.dtmask, args, stream)
+                       : jr::launch_tiled(s.unroll, s.defer, t.dtmask, blocks, args, stream);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return JR_OK;
 }
 
@@ -718,6 +777,11 @@ int julia_render_batch(const jr_frame* frames, int32_t n, int32_t* out_base,
     return enqueue_batch(frames, n, out_base, out_capacity, sched, (hipStream_t)stream);
 }
 
+int julia_render_batch_noalloc(const jr_frame* frames, int32_t n, int32_t* out_base,
+                               int64_t out_capacity, const jr_schedule* sched, void* stream) {
+    return enqueue_batch_noalloc(frames, n, out_base, out_capacity, sched, (hipStream_t)stream);
+}
+
 int julia_render_batch_colored(const jr_frame* frames, int32_t n, const uint32_t* palette,
                                int32_t palette_len, uint32_t* out_base, int64_t out_capacity,
                                const jr_schedule* sched, void* stream) {
@@ -742,14 +806,7 @@ int jr_plan_create(const jr_frame* frames, int32_t n, int32_t* out_base, int64_t
     if (rc) return rc;
     if ((rc = check_out(out_base, "plan"))) return rc;
     jr_schedule s;
-    if (sched) {
-        s = *sched;
-        if ((rc = check_schedule(s))) return rc;
-    } else {
-        double w[3] = {0, 0, 0};
-        for (int32_t k = 0; k < n; ++k) w[frames[k].dtype] += frame_cost(frames[k]);
-        s = default_schedule((int)(std::max_element(w, w + 3) - w));
-    }
+    if ((rc = batch_schedule(frames, n, sched, s))) return rc;
     int dev;
     DeviceInfo info;
     if ((rc = current_device(&dev, &info))) return rc;

@@ -36,6 +36,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "julia_device.h"
@@ -1336,6 +1337,36 @@ __global__ void jr_reset_queues(unsigned long long* ctr) {
     if (threadIdx.x < kQueues) ctr[(size_t)threadIdx.x * kQueueStride] = 0ull;
 }
 
+// Up to kPutFrames frame records travel inside the kernel arguments of
+// jr_put_frames, which writes them to a device frame table: the table of an
+// allocation-free launch needs neither a copy call nor staging memory, and the
+// caller's host array may be reused as soon as the launch call returns.
+struct FrameChunk {
+    DevFrame f[kPutFrames];
+    DevFrame* dst;
+    int32_t count;
+};
+static_assert(sizeof(FrameChunk) <= 4096, "kernel arguments are at most 4 KiB");
+
+__global__ __launch_bounds__(256) void jr_put_frames(FrameChunk c) {
+    // Read the records straight from the kernel-argument segment (the single
+    // by-value argument sits at offset 0): indexing the by-value array with
+    // the thread index would copy it to per-lane stack memory first.
+    constexpr int kWords = (int)(sizeof(DevFrame) / 8);
+    typedef const __attribute__((address_space(4))) uint64_t CWord;
+    CWord* src = (CWord*)__builtin_amdgcn_kernarg_segment_ptr();
+    uint64_t* dst = reinterpret_cast<uint64_t*>(c.dst);
+    for (int k = (int)threadIdx.x; k < c.count * kWords; k += (int)blockDim.x) dst[k] = src[k];
+}
+static_assert(sizeof(DevFrame) % 8 == 0 && offsetof(FrameChunk, f) == 0,
+              "frame records are whole 8-byte words at the start of the arguments");
+
+// The fixed device array of allocation-free launches (see julia_device.h).
+// Every process holds one copy per GPU until it ends.  In host code the name
+// stands for a host-side shadow, not a device address: host code uses the
+// address noalloc_scratch() looks up for the current device.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 }  // namespace jr
 
 // ---------------------------------------------------------------------------
@@ -1483,6 +1514,38 @@ hipError_t launch_tiled(int unroll, int defer, int dtmask, int blocks, const Per
     }
     hipLaunchKernelGGL(fn, dim3(blocks), dim3(threads), palette_bytes(args), stream, args);
     return hipGetLastError();
+}
+
+hipError_t noalloc_scratch(int dev, void** ptr) {
+    constexpr int kDevices = 64;
+    static std::mutex mu;
+    static void* addr[kDevices] = {};
+    if (dev < 0 || dev >= kDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(mu);
+    if (!addr[dev]) {
+        // Each GPU holds its own copy of the array at its own address; the
+        // caller has made `dev` the current device.
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (p == nullptr) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
+
+hipError_t put_frames(const DevFrame* rows, int n, DevFrame* dst, hipStream_t stream) {
+    for (int k0 = 0; k0 < n; k0 += kPutFrames) {
+        FrameChunk c;
+        c.count = n - k0 < kPutFrames ? n - k0 : kPutFrames;
+        c.dst = dst + k0;
+        for (int k = 0; k < c.count; ++k) c.f[k] = rows[k0 + k];
+        hipLaunchKernelGGL(jr_put_frames, dim3(1), dim3(256), 0, stream, c);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_plain(int dtype, const PlainArgs& args, hipStream_t stream) {

@@ -184,6 +184,25 @@ def test_batch_rejects_before_device():
     assert jr.lib.jr_plan_replay(None, None) == jr.JR_EINVAL
 
 
+def test_noalloc_batch_rejects_before_device():
+    """The allocation-free batch call checks its frame limit, frames, output
+    and schedule before any device call."""
+    from workloads import Frame
+    lim = jr.NOALLOC_MAX_FRAMES
+    assert lim == 1024
+    fr = [Frame(0.3 + 0.2j, (-1.5, 1.5, -1.5, 1.5), 4, 4, 50, "fp32")] * (lim + 1)
+    arr = jr._frames_array(fr, [16 * k for k in range(lim + 1)])
+    call = jr.lib.julia_render_batch_noalloc
+    assert call(arr, lim + 1, FAKE_OUT, 16 * (lim + 1), None, None) == jr.JR_EINVAL
+    assert "allocation-free limit" in jr.last_error()
+    assert call(None, 1, FAKE_OUT, 16, None, None) == jr.JR_EINVAL
+    assert call(arr, 0, FAKE_OUT, 16, None, None) == jr.JR_EINVAL
+    assert call(arr, 2, FAKE_OUT, 31, None, None) == jr.JR_EINVAL  # capacity too small
+    assert call(arr, 2, ctypes.c_void_p(0), 32, None, None) == jr.JR_EINVAL
+    bad = jr.Schedule(tile_w=0).to_c()
+    assert call(arr, 2, FAKE_OUT, 32, ctypes.byref(bad), None) == jr.JR_EINVAL
+
+
 def test_valid_call_without_gpu_reports_no_device():
     import torch
     if torch.cuda.is_available():
