@@ -45,15 +45,42 @@ FLOP_PER_ITER = 8
 BYTES_PER_PIXEL = 4
 METRIC = "Gpixel-iters/s (FP64/FP32/float-float) vs plain kernel; p99 frame latency"
 
-# HBM bytes per launch of the headline kernel from rocprofv3 --pmc FETCH_SIZE
-# and WRITE_SIZE (KiB summed over a dispatch), scaled by what the same
-# counters read for a device copy of 1 GiB (fetch x2.0, write x1.0), keyed by
-# the kernel instance they were taken on.  The summaries with their commands
-# are in profiles/.  A kernel without an entry reports null.
-MEASURED_TRAFFIC_BYTES = {
-    "jr_rows<8, 2, 1>": 2199092400,  # 620,544 B fetched + 2,198,471,856 B written
-    "jr_tiled<8, 0, 2, 0>": 2124197256,  # 662,559 B fetched + 2,123,534,697 B written
-}
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1611_03079_amd", "csrc", "julia_kernels.hip")
+
+
+def kernel_source_sha256():
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the rocprofv3
+    FETCH_SIZE / WRITE_SIZE summaries in profiles/: a summary states
+        traffic_bytes_per_launch: <workload> | <kernel> | <bytes>
+        kernel_source_sha256: <hash of julia_kernels.hip the counters ran on>
+    Returns (bytes, file) when a summary matches the kernel, the workload and
+    the current kernel source; (None, reason) otherwise, so that a kernel
+    changed since its counters were taken reports no traffic."""
+    if not os.path.isdir(PROFILES):
+        return None, "no profiles/ folder"
+    now = kernel_source_sha256()
+    stale = None
+    for name in sorted(os.listdir(PROFILES)):
+        entries, sha = [], None
+        with open(os.path.join(PROFILES, name), errors="replace") as f:
+            for line in f:
+                if line.startswith("traffic_bytes_per_launch:"):
+                    entries.append([x.strip() for x in line.split(":", 1)[1].split("|")])
+                elif line.startswith("kernel_source_sha256:"):
+                    sha = line.split(":", 1)[1].strip()
+        for wl_name, kern, nbytes in entries:
+            if wl_name == workload and kern == kernel:
+                if sha == now:
+                    return int(nbytes), "profiles/" + name
+                stale = "profiles/%s was taken on another kernel source" % name
+    return None, stale or "no counters for %s on %s in profiles/" % (kernel, workload)
 
 # The kernel instance a schedule launches for an FP32-only batch that stores
 # counts (template arguments as rocprofv3 prints them).
@@ -74,7 +101,10 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--no-extra", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
-    p.add_argument("--serve-seconds", type=float, default=2.5)
+    p.add_argument("--serve-seconds", type=float, default=20.0,
+                   help="longest arrival window per serving rate (s); a rate also stops "
+                        "after --serve-requests requests")
+    p.add_argument("--serve-requests", type=int, default=5000)
     p.add_argument("--schedule", choices=("tuned", "plain", "tiled"), default="tuned",
                    help="headline schedule: the autotuned one (default), the batched "
                         "one-thread-per-pixel kernel, or the refill stream (64x64 tiles, "
@@ -96,6 +126,56 @@ def tuned_schedule(jr, name, frames):
           file=sys.stderr, flush=True)
     best, _, _ = at.tune(frames, reps=3, verbose=True)
     return best, "tuned at start"
+
+
+def tuned_schedule_or_default(jr, name):
+    """Schedule from the committed autotune cache, else None (the library's
+    default for the batch's dtype)."""
+    from paper_1611_03079_amd import autotune as at
+    e = at.load_cache().get("_workloads", {}).get(name)
+    if e:
+        return jr.Schedule(**e["schedule"]), "cache"
+    return None, "library default"
+
+
+def serving_sweep(args, torch, wl):
+    from paper_1611_03079_amd.serve import GpuBackend, PrecisionPolicy, Server, run_open_loop
+    out = {}
+    policies = (("calibrated", PrecisionPolicy(), (50, 100, 200, 500, 1000, 2000, 4000)),
+                ("three_way_ff", PrecisionPolicy.specified(), (50, 200, 1000)))
+    for pname, pol, rates in policies:
+        sat = None
+        for rate in rates:
+            n = max(20, min(args.serve_requests, int(rate * args.serve_seconds)))
+            reqs = wl.serving_stream(11, float(rate), n)
+            cap = 8 * 1920 * 1080
+            srv = Server(GpuBackend(cap), cap, copy_out=False, policy=pol)
+            st = run_open_loop(srv, reqs, drain_timeout=5.0)
+            torch.cuda.synchronize()
+            span = max(st.t_last - st.t_first, 1e-9)
+            dts = {}
+            for r in reqs:
+                dts[r.frame.dtype] = dts.get(r.frame.dtype, 0) + 1
+            kept_up = (not st.saturated) and st.completed / span >= 0.9 * rate
+            if kept_up:
+                sat = rate
+            out["%s_rate_%d" % (pname, rate)] = {
+                "offered": n, "completed": st.completed, "unfinished": len(st.unfinished),
+                "seconds": round(reqs[-1].arrival_s, 2),
+                "p50_ms": round(st.percentile(50) * 1e3, 2),
+                "p99_ms": round(st.percentile(99) * 1e3, 2),
+                "completed_req_s": round(st.completed / span, 1), "steps": st.steps,
+                "kept_up": kept_up, "dtypes": dts,
+                "learnt_rate_units_per_s": float("%.3g" % srv.rate.rate)}
+            del srv
+            torch.cuda.empty_cache()
+            print("bench: serving %s at %d req/s: p99 %.1f ms, %s" % (
+                pname, rate, st.percentile(99) * 1e3, "kept up" if kept_up else "saturated"),
+                file=sys.stderr, flush=True)
+            if not kept_up:
+                break   # higher rates only queue longer
+        out["%s_highest_rate_kept_up" % pname] = sat
+    return out
 
 
 def time_plan_steps(torch, plan, steps, warmup, graph=True):
@@ -135,38 +215,88 @@ def count_sum(torch, views):
     return sum(int(v.sum(dtype=torch.int64).item()) for v in views)
 
 
-def cpu_baseline(frames, seconds):
-    """The oracle, single-threaded, on whole rows taken in a fixed interleaved
-    order (row j of every frame, rows stepping by 7 through the image), until
-    `seconds` of CPU work."""
+ROWS_PER_CALL = 8
+
+
+def _row_picks(frames):
+    """Whole rows in a fixed interleaved order: rows step by 7 through the
+    image (7 and 1080 are coprime, so every row comes once), taken
+    ROWS_PER_CALL at a time, each group from every frame in turn."""
+    H = frames[0].height
+    rows = [(3 + 7 * m) % H for m in range(H)]
+    groups = [rows[k: k + ROWS_PER_CALL] for k in range(0, H, ROWS_PER_CALL)]
+    return [(fi, g) for g in groups for fi in range(len(frames))]
+
+
+def _oracle_rows(job):
+    """Worker: the oracle on the row groups picks[start::step] (one oracle
+    call per group) until `seconds` pass; returns (pixel-iterations, pixels,
+    rows, seconds spent)."""
     import numpy as np
     import oracle
-    H = frames[0].height
-    rows = [(3 + 7 * m) % H for m in range(H)]  # 7 and 1080 are coprime: every row once
-    picks = [(fi, j) for j in rows for fi in range(len(frames))]
-    iters = px = 0
-    spent = 0.0
-    done = 0
-    for fi, j in picks:
-        if spent >= seconds:
+    frames, picks, start, step, seconds = job
+    iters = px = done = 0
+    t0 = time.perf_counter()
+    for fi, rows in picks[start::step]:
+        if time.perf_counter() - t0 >= seconds:
             break
         f = frames[fi]
-        ii = np.arange(f.width, dtype=np.int32)
-        jj = np.full(f.width, j, dtype=np.int32)
-        t0 = time.perf_counter()
+        ii = np.tile(np.arange(f.width, dtype=np.int32), len(rows))
+        jj = np.repeat(np.asarray(rows, dtype=np.int32), f.width)
         c = oracle.render_pixels(f.c, f.window, f.width, f.height, f.max_iter, ii, jj, f.dtype)
-        spent += time.perf_counter() - t0
         iters += int(c.sum(dtype=np.int64))
-        px += f.width
-        done += 1
-    sample = ("%d whole 1920-pixel rows (%d pixels): rows j = 3, 10, 17, ... (step 7 mod "
-              "1080) of all 256 frames in turn, oracle FP32 formulation, %.1f s "
-              "single-threaded" % (done, px, spent))
-    return iters / spent, sample
+        px += ii.size
+        done += len(rows)
+    return iters, px, done, time.perf_counter() - t0
+
+
+def host_cpu():
+    """The host's CPU model (lscpu / /proc/cpuinfo), its logical CPUs and the
+    CPUs this process may run on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    allowed = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return model, os.cpu_count(), allowed
+
+
+def cpu_baseline(frames, seconds):
+    """The oracle on whole rows of the headline workload (FP32 formulation):
+    single-threaded for `seconds`, then one host thread per core (at most 16,
+    the host share of one GPU), each calling the same single-threaded oracle
+    on every n-th row of the same order, for `seconds` of wall time.  The
+    oracle library releases the interpreter lock while it runs, so the
+    threads run in parallel."""
+    from concurrent.futures import ThreadPoolExecutor
+    picks = _row_picks(frames)
+    it1, px1, rows1, s1 = _oracle_rows((frames, picks, 0, 1, seconds))
+    model, ncpu, allowed = host_cpu()
+    n = max(1, min(16, allowed))
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(n) as pool:
+        res = list(pool.map(_oracle_rows, [(frames, picks, k, n, seconds) for k in range(n)]))
+    wall = time.perf_counter() - t0
+    busy = max(r[3] for r in res)
+    itn = sum(r[0] for r in res)
+    return {
+        "single": (it1 / s1, "%d whole 1920-pixel rows (%d pixels): rows j = 3, 10, 17, ... "
+                   "(step 7 mod 1080) in groups of %d, each group from all 256 frames in "
+                   "turn, one oracle call per group, oracle FP32 formulation, %.1f s on one "
+                   "core" % (rows1, px1, ROWS_PER_CALL, s1)),
+        "all": (itn / busy, n, "the same row order dealt round-robin to %d threads, each "
+                "calling the single-threaded oracle, %d rows (%d pixels), %.1f s of wall time "
+                "(%.1f s with start-up)" % (n, sum(r[2] for r in res), sum(r[1] for r in res),
+                                             busy, wall)),
+        "cpu_model": model, "nproc": ncpu, "cpus_allowed": allowed,
+    }
 
 
 def extra_legs(args, torch, jr, wl, frames, sched, ms_headline, iters):
-    from paper_1611_03079_amd.serve import GpuBackend, Server, run_open_loop
     ex = {}
     reps = 3
     # plain kernel: one launch per frame, same frames
@@ -176,6 +306,28 @@ def extra_legs(args, torch, jr, wl, frames, sched, ms_headline, iters):
         "gpixel_iter_s": round(iters / (ms_plain * 1e-3) / 1e9, 2), "ms_per_step": round(ms_plain, 4)}
     ex["tuned_batch_vs_plain"] = round(ms_plain / ms_headline, 3)
     del outs
+    # the same frames in FP64 and in float-float, one launch each (library
+    # default schedule of the dtype), beside the plain kernel per frame
+    for dt in ("fp64", "ff"):
+        fr = wl.parameter_path(dtype=dt)
+        dsched, dsrc = tuned_schedule_or_default(jr, "parameter_path_" + dt)
+        plan = jr.Plan(fr, dsched)
+        ms_d, kms_d = time_plan_steps(torch, plan, 5, 1, graph=False)
+        it_d = count_sum(torch, plan.views)
+        info_d = plan.info()
+        plan.close()
+        outs = [torch.empty((f.height, f.width), dtype=torch.int32, device="cuda") for f in fr]
+        ms_dp = time_renders(jr, torch, fr, outs, 1, plain=True)
+        del outs
+        peak = PEAK_FP64_TFLOPS if dt == "fp64" else PEAK_FP32_UNPACKED_TFLOPS
+        ex["parameter_path_%s" % dt] = {
+            "gpixel_iter_s": round(it_d / (ms_d * 1e-3) / 1e9, 2), "ms_per_step": round(ms_d, 4),
+            "kernel_ms": round(kms_d, 4), "pixel_iters": it_d,
+            "plain_per_frame_ms": round(ms_dp, 4), "vs_plain": round(ms_dp / ms_d, 3),
+            "useful_flop_frac_of_peak": round(FLOP_PER_ITER * it_d / (kms_d * 1e-3) / 1e12 / peak,
+                                              4),
+            "peak_tflops": peak, "schedule": (dsched.__dict__ if dsched else dsrc),
+            "workgroups": info_d["workgroups"]}
     # persistent work-queue mode of the same batch
     from dataclasses import replace
     pers = replace(sched, persistent=1, waves_per_cu=32)
@@ -270,33 +422,18 @@ def extra_legs(args, torch, jr, wl, frames, sched, ms_headline, iters):
         "gpixel_iter_s": round(it_g / (ms_g * 1e-3) / 1e9, 2), "ms": round(ms_g, 3),
         "plain_per_frame_ms": round(ms_gp, 3), "vs_plain": round(ms_gp / ms_g, 3),
         "schedule": gsched.__dict__, "pixel_iters": it_g}
-    # serving: Poisson arrivals at several rates, with the precision policy
-    # as specified (float-float for mid widths) and with FP64 for every window
-    # narrower than FP32 handles (on MI355X FP64 runs at the FP32 rate)
-    from paper_1611_03079_amd.serve import PrecisionPolicy
-    serve = {}
-    policies = {"ff_mid": PrecisionPolicy(), "fp64_narrow": PrecisionPolicy(ff_min_width=float("inf"))}
-    for pname, rates in (("ff_mid", (50, 200, 800, 2000)), ("fp64_narrow", (200, 2000))):
-        for rate in rates:
-            n = max(20, int(rate * args.serve_seconds))
-            reqs = wl.serving_stream(11, float(rate), n)
-            cap = 8 * 1920 * 1080
-            srv = Server(GpuBackend(cap), cap, step_budget=2.0e8, copy_out=False,
-                         policy=policies[pname])
-            st = run_open_loop(srv, reqs, drain_timeout=5.0)
-            torch.cuda.synchronize()
-            span = max(st.t_last - st.t_first, 1e-9)
-            serve["%s_rate_%d" % (pname, rate)] = {
-                "offered": n, "completed": st.completed,
-                "p50_ms": round(st.percentile(50) * 1e3, 2), "p99_ms": round(st.percentile(99) * 1e3, 2),
-                "completed_req_s": round(st.completed / span, 1), "steps": st.steps}
-            del srv
-            torch.cuda.empty_cache()
-    ex["serving"] = serve
+    # serving: open-loop Poisson arrivals at the specified rates, each for
+    # --serve-seconds or --serve-requests requests, whichever ends first,
+    # with the calibrated precision policy (FP32 where it stays within 0.5%
+    # of FP64, FP64 elsewhere) and with the three-way policy (float-float
+    # between 1e-5 and the FP32 region); the step budget is learnt from
+    # measured step times (2 ms target).  Unfinished requests count in the
+    # percentiles at the latency they had when the run was cut off.
+    ex["serving"] = serving_sweep(args, torch, wl)
     # the paper's timing study (Figure 1): square images of side 10 .. 10000,
     # C = -0.8 + 0.156i, window [-1.5, 1.5]^2, cap 100, FP64: GPU time per
     # image (tuned and plain, synchronised, launch included) beside the
-    # single-threaded oracle on this host (sides up to 3162)
+    # single-threaded oracle on this host
     if not args.no_cpu:
         import oracle
     sweep = {}
@@ -313,7 +450,7 @@ def extra_legs(args, torch, jr, wl, frames, sched, ms_headline, iters):
             torch.cuda.synchronize()
             row["gpu_plain_ms" if plain else "gpu_tuned_ms"] = round(
                 (time.perf_counter() - t0) * 1e3 / reps, 4)
-        if not args.no_cpu and f.width <= 3162:
+        if not args.no_cpu:
             t0 = time.perf_counter()
             oracle.render(f.c, f.window, f.width, f.height, 100, "fp64")
             row["cpu_oracle_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
@@ -367,6 +504,7 @@ def main():
     info = plan.info()
     plan.close()
     pixels = sum(f.pixels for f in frames)
+    traffic, traffic_src = measured_traffic(kernel_instance(sched), "parameter_path_fp32")
     value = iters / (ms_step * 1e-3) / 1e9
     store_gbs = BYTES_PER_PIXEL * pixels / (kernel_ms * 1e-3) / 1e9
     alu_tflops = FLOP_PER_ITER * iters / (kernel_ms * 1e-3) / 1e12
@@ -391,7 +529,8 @@ def main():
                    "tiles": info["tiles"], "workgroups": info["workgroups"]},
         "roofline": {"bound": "hbm", "achieved": round(store_gbs, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(store_gbs / PEAK_HBM_GBS, 4),
-                     "traffic": MEASURED_TRAFFIC_BYTES.get(kernel_instance(sched)),
+                     "traffic": traffic,
+                     "traffic_source": traffic_src,
                      "algorithmic_bytes_per_launch": BYTES_PER_PIXEL * pixels,
                      "kernel_ms": round(kernel_ms, 4),
                      "alu": {"achieved": round(alu_tflops, 2), "peak": PEAK_FP32_TFLOPS,
@@ -404,9 +543,15 @@ def main():
     if not args.no_extra:
         line["extra"] = extra_legs(args, torch, jr, wl, frames, sched, ms_step, iters)
     if not args.no_cpu:
-        rate, sample = cpu_baseline(frames, args.cpu_seconds)
-        line["cpu_baseline"] = {"value": round(rate / 1e9, 5), "unit": "Gpixel-iter/s",
-                                "cores": 1, "kind": "oracle", "sample": sample}
+        cb = cpu_baseline(frames, args.cpu_seconds)
+        rate_all, n_all, sample_all = cb["all"]
+        rate_1, sample_1 = cb["single"]
+        line["cpu_baseline"] = {"value": round(rate_all / 1e9, 5), "unit": "Gpixel-iter/s",
+                                "cores": n_all, "kind": "oracle", "sample": sample_all,
+                                "cpu_model": cb["cpu_model"], "nproc": cb["nproc"],
+                                "cpus_allowed": cb["cpus_allowed"],
+                                "single_thread": {"value": round(rate_1 / 1e9, 5), "cores": 1,
+                                                  "sample": sample_1}}
     print(json.dumps(line), flush=True)
 
 

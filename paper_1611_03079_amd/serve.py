@@ -10,7 +10,11 @@ zooms).  This loop serves a stream of such requests on one GPU:
   * every step takes rows from all admitted requests, oldest first, up to a
     work budget, and renders them in ONE launch of the batch kernel (frames of
     different sizes, caps and dtypes together; a large frame is split over
-    several steps by row ranges);
+    several steps by row ranges).  The budget is fed back from measured step
+    times: a row costs its worst case (every pixel runs to the cap), and the
+    rate at which the device clears such work is learnt from the device time
+    of finished steps, so a step lasts about `step_target_s` at most and a new
+    arrival starts within one step;
   * two steps are kept in flight on two streams, so work admitted while
     others run overlaps with them on the device;
   * a request completes when the step holding its last rows has finished; its
@@ -34,11 +38,26 @@ DTYPE_COST = {"fp32": 1.0, "fp64": 1.75, "ff": 20.0}
 
 @dataclass
 class PrecisionPolicy:
-    """dtype by window width and cap: FP32 for wide windows and small caps,
-    float-float for narrower windows, FP64 below `ff_min_width`."""
-    fp32_min_width: float = 0.5
-    fp32_max_iter: int = 200
-    ff_min_width: float = 1e-5
+    """dtype by window width and cap: FP32 where its counts stay within the
+    stated bound of FP64's, float-float for narrower windows down to
+    `ff_min_width`, FP64 below.
+
+    The thresholds come from the measured precision table (FP32 and
+    float-float against FP64, windows centred on the Julia set, the hardest
+    case): FP32 differs from FP64 on at most 0.32% of pixels for windows at
+    least 0.1 wide with caps up to 1000, and on more (0.69% to 93%) for
+    narrower windows or larger caps; float-float on at most 0.28% down to
+    1e-9.  The default routes everything that FP32 does not cover to FP64:
+    on MI355X FP64 is exact and costs about 1.75 times FP32, float-float about
+    13 times.  `specified()` is the three-way policy with float-float between
+    1e-5 and the FP32 region."""
+    fp32_min_width: float = 0.1
+    fp32_max_iter: int = 1000
+    ff_min_width: float = math.inf
+
+    @staticmethod
+    def specified() -> "PrecisionPolicy":
+        return PrecisionPolicy(ff_min_width=1e-5)
 
     def pick(self, width: float, max_iter: int) -> str:
         if width >= self.fp32_min_width and max_iter <= self.fp32_max_iter:
@@ -46,6 +65,32 @@ class PrecisionPolicy:
         if width >= self.ff_min_width:
             return "ff"
         return "fp64"
+
+
+class StepRate:
+    """The rate (worst-case cost units per second) at which the device clears
+    a step, learnt from finished steps.  A row's cost assumes every pixel runs
+    to the cap, so a step's measured rate is at least the device's true rate
+    and equals it when the rows are all interior.  The estimate follows the
+    lower envelope of the measured rates: it drops to any lower measurement at
+    once and rises by at most `growth` per step, and it never exceeds `ceiling`
+    (the FP32 issue-rate limit of MI355X in these units), so a heavy step
+    after a run of light ones overruns its target by a bounded factor."""
+
+    def __init__(self, prior: float = 2.0e12, ceiling: float = 9.0e12, growth: float = 1.05,
+                 fixed_s: float = 15e-6):
+        self.rate = prior
+        self.ceiling = ceiling
+        self.growth = growth
+        self.fixed_s = fixed_s   # launch and event overhead of one step
+        self.samples = 0
+
+    def update(self, units: float, seconds: float):
+        busy = seconds - self.fixed_s
+        if units <= 0 or busy <= 0:
+            return
+        self.samples += 1
+        self.rate = min(self.ceiling, self.rate * self.growth, units / busy)
 
 
 class ArenaAllocator:
@@ -127,7 +172,9 @@ class Stats:
 
 
 class GpuBackend:
-    """libjulia.so on the current CUDA device: device arena, two streams."""
+    """libjulia.so on the current CUDA device: device arena, two streams.  A
+    launch is bracketed by timing events on its stream; their times give the
+    step's device time (the budget's feedback) and show steps overlapping."""
 
     def __init__(self, arena_elements: int, streams: int = 2):
         import torch
@@ -141,14 +188,25 @@ class GpuBackend:
 
     def launch(self, frames, offsets, rows, stream_idx: int, schedule=None):
         st = self.streams[stream_idx]
+        ev0 = self.torch.cuda.Event(enable_timing=True)
+        ev1 = self.torch.cuda.Event(enable_timing=True)
+        ev0.record(st)
         self.jr.render_batch(frames, schedule, arena=self.arena, offsets=offsets, rows=rows,
                              stream=st)
-        ev = self.torch.cuda.Event()
-        ev.record(st)
-        return ev
+        ev1.record(st)
+        return (ev0, ev1)
 
     def done(self, handle) -> bool:
-        return handle.query()
+        return handle[1].query() if isinstance(handle, tuple) else handle.query()
+
+    def seconds(self, handle) -> float:
+        """Device time of a finished launch."""
+        return handle[0].elapsed_time(handle[1]) * 1e-3
+
+    def between(self, a, b) -> float:
+        """Device time from the start event of launch a to the end event of
+        launch b (negative when b ended before a started)."""
+        return a[0].elapsed_time(b[1]) * 1e-3
 
     def fetch(self, offset: int, frame, stream_idx: int):
         st = self.streams[stream_idx]
@@ -160,13 +218,34 @@ class GpuBackend:
         return ev, out
 
 
+@dataclass
+class StepRecord:
+    """One launch of the loop, kept for inspection (tests, reports)."""
+    step: int
+    stream: int
+    rids: List[int]
+    units: float              # worst-case cost of its rows
+    t_launch: float           # host clock when it was enqueued
+    inflight_at_launch: List[int]  # steps not yet finished at that moment
+    handle: object = None
+    seconds: float = math.nan  # device time, once finished
+
+
 class Server:
-    def __init__(self, backend, arena_elements: int, step_budget: float = 2.0e8,
+    def __init__(self, backend, arena_elements: int, step_budget: Optional[float] = None,
                  max_inflight: int = 2, policy: Optional[PrecisionPolicy] = None,
-                 copy_out: bool = True, schedule=None):
+                 copy_out: bool = True, schedule=None, step_target_s: float = 2e-3,
+                 rate: Optional[StepRate] = None, keep_log: bool = False):
         self.b = backend
         self.alloc = ArenaAllocator(arena_elements)
-        self.step_budget = step_budget
+        # a fixed budget (cost units per step), or None: step_target_s times
+        # the learnt rate
+        self.fixed_budget = step_budget
+        self.step_target_s = step_target_s
+        self.rate = rate or StepRate()
+        self.keep_log = keep_log
+        self.log: List[StepRecord] = []
+        self.admitted_at: Dict[int, tuple] = {}   # rid -> (host time, steps in flight)
         self.max_inflight = max_inflight
         self.policy = policy or PrecisionPolicy()
         self.copy_out = copy_out
@@ -223,45 +302,71 @@ class Server:
                     break   # first come first served: the head waits for memory
                 r.offset = off
                 self.active.append(self.queue.popleft())
+                if self.keep_log:
+                    self.admitted_at[r.rid] = (self.b.now(), [s[0] for s in self.inflight])
 
-    def _row_cost(self, f) -> float:
-        return f.width * (4.0 + min(f.max_iter, 256)) * DTYPE_COST[f.dtype]
+    @staticmethod
+    def _row_cost(f) -> float:
+        """Worst-case cost of one row: every pixel runs to the cap."""
+        return f.width * (4.0 + f.max_iter) * DTYPE_COST[f.dtype]
+
+    @property
+    def step_budget(self) -> float:
+        if self.fixed_budget is not None:
+            return self.fixed_budget
+        return self.step_target_s * self.rate.rate
 
     def _build_step(self):
-        frames, offsets, rows, ending = [], [], [], []
+        frames, offsets, rows, ending, rids = [], [], [], [], []
+        units = 0.0
         budget = self.step_budget
         for r in self.active:
             if r.next_row >= r.frame.height:
                 continue
             f = r.frame
-            take = max(1, min(f.height - r.next_row, int(budget // self._row_cost(f))))
+            rc = self._row_cost(f)
+            take = max(1, min(f.height - r.next_row, int(budget // rc)))
             frames.append(f)
             offsets.append(r.offset)
             rows.append((r.next_row, r.next_row + take))
+            rids.append(r.rid)
             r.next_row += take
             if r.next_row >= f.height:
                 r.last_step = self.step_id
                 ending.append(r)
-            budget -= take * self._row_cost(f)
+            budget -= take * rc
+            units += take * rc
             if budget <= 0:
                 break
-        return frames, offsets, rows, ending
+        return frames, offsets, rows, ending, rids, units
 
     def step(self) -> bool:
         """One scheduler pass; returns True when it did anything."""
         busy = False
         self._admit()
         if len(self.inflight) < self.max_inflight:
-            frames, offsets, rows, ending = self._build_step()
+            frames, offsets, rows, ending, rids, units = self._build_step()
             if frames:
                 sidx = self.step_id % self.max_inflight
+                t = self.b.now()
+                before = [s[0] for s in self.inflight]
                 h = self.b.launch(frames, offsets, rows, sidx, self.schedule)
-                self.inflight.append((self.step_id, sidx, h, ending))
+                rec = StepRecord(self.step_id, sidx, rids, units, t, before, h)
+                self.inflight.append((self.step_id, sidx, h, ending, rec))
+                if self.keep_log:
+                    self.log.append(rec)
                 self.step_id += 1
                 self.stats.steps += 1
                 busy = True
         while self.inflight and self.b.done(self.inflight[0][2]):
-            _, sidx, _, ending = self.inflight.popleft()
+            _, sidx, h, ending, rec = self.inflight.popleft()
+            seconds = getattr(self.b, "seconds", None)
+            if seconds is not None:
+                rec.seconds = seconds(h)
+                # only steps that used most of their budget say how fast the
+                # device clears work; small ones are mostly launch overhead
+                if self.fixed_budget is None and rec.units >= 0.5 * self.step_budget:
+                    self.rate.update(rec.units, rec.seconds)
             for r in ending:
                 if self.copy_out:
                     h, out = self.b.fetch(r.offset, r.frame, sidx)

@@ -4,11 +4,12 @@ from FP64 counts, by window width and iteration cap.
 Calls only the CPU oracle (oracle/).  FP64 is the defining arithmetic (its
 counts are the method's); FP32 and float-float are the two faster
 formulations, and the fraction of pixels whose count differs from FP64 is
-the accuracy they are judged by.  For every cell (width, cap) of
-workloads.PRECISION_WIDTHS x workloads.PRECISION_CAPS the script takes the
-cell's 32 windows (workloads.precision_windows: the serving stream's
-constants and centres at that width, 640 x 480 grids) and 1024 probed pixels
-of each, renders the probed pixels in all three formulations, and records
+the accuracy they are judged by.  For every cell (kind, width, cap) of
+{serving, boundary} x workloads.PRECISION_WIDTHS x workloads.PRECISION_CAPS
+the script takes the cell's 32 windows (workloads.probe_windows: the serving
+stream's constants and centres at that width, or the same constants with
+windows centred on the Julia set; 640 x 480 grids) and 1024 probed pixels of
+each, renders the probed pixels in all three formulations, and records
 
     pixels        probed pixels in the cell (32 x 1024)
     fp32_diff     probed pixels whose FP32 count differs from FP64
@@ -36,8 +37,8 @@ OUT = os.path.join(HERE, "precision_table.txt")
 
 
 def cell(job):
-    width, cap = job
-    wins = wl.precision_windows(wl.precision_seed(width, cap), width, cap)
+    kind, width, cap = job
+    wins = wl.probe_windows(kind, width, cap)
     diff = {"fp32": 0, "ff": 0}
     worst = {"fp32": 0.0, "ff": 0.0}
     total = 0
@@ -52,26 +53,33 @@ def cell(job):
             diff[dt] += d
             worst[dt] = max(worst[dt], d / ii.size)
         total += ii.size
-    return width, cap, total, diff["fp32"], diff["ff"], worst["fp32"], worst["ff"]
+    return kind, width, cap, total, diff["fp32"], diff["ff"], worst["fp32"], worst["ff"]
 
 
 def main():
     p = argparse.ArgumentParser()
     p.add_argument("--workers", type=int, default=min(8, os.cpu_count() or 1))
     a = p.parse_args()
-    jobs = [(w, c) for w in wl.PRECISION_WIDTHS for c in wl.PRECISION_CAPS]
+    jobs = [(k, w, c) for k in ("serving", "boundary") for w in wl.PRECISION_WIDTHS
+            for c in wl.PRECISION_CAPS]
+    # the most expensive cells (boundary windows, large caps) first
+    order = sorted(range(len(jobs)), key=lambda i: (jobs[i][0] != "boundary", -jobs[i][2]))
     with Pool(a.workers) as pool:
-        rows = pool.map(cell, jobs)
+        got = dict(zip(order, pool.map(cell, [jobs[i] for i in order])))
+    rows = [got[i] for i in range(len(jobs))]
     with open(OUT, "w") as out:
         out.write("# FP32 and float-float counts against FP64, by window width and cap.\n"
-                  "# Windows: workloads.precision_windows (serving-stream constants and\n"
-                  "# centres, 640x480 grids, 32 windows x 1024 probed pixels per cell).\n"
+                  "# Windows (640x480 grids, 32 windows x 1024 probed pixels per cell):\n"
+                  "#   serving   workloads.precision_windows: the serving stream's constants\n"
+                  "#             and centres (uniform in [-1.5, 1.5]^2);\n"
+                  "#   boundary  workloads.boundary_windows: the same constants, each window\n"
+                  "#             centred on a point of the Julia set J(C).\n"
                   "# Written by tests/golden/make_precision_table.py (oracle only).\n"
-                  "# columns: width cap pixels fp32_diff ff_diff fp32_worst ff_worst\n")
+                  "# columns: kind width cap pixels fp32_diff ff_diff fp32_worst ff_worst\n")
         for r in rows:
-            out.write("%g %d %d %d %d %.6f %.6f\n" % r)
-            print("width %-6g cap %-5d  fp32 %.4f%%  ff %.4f%%" % (
-                r[0], r[1], 100.0 * r[3] / r[2], 100.0 * r[4] / r[2]), flush=True)
+            out.write("%s %g %d %d %d %d %.6f %.6f\n" % r)
+            print("%-8s width %-6g cap %-5d  fp32 %.4f%%  ff %.4f%%" % (
+                r[0], r[1], r[2], 100.0 * r[4] / r[3], 100.0 * r[5] / r[3]), flush=True)
     print(OUT)
 
 

@@ -131,12 +131,97 @@ def test_oversized_frame_is_rejected():
 
 
 def test_precision_policy():
+    """The calibrated default: FP32 for windows >= 0.1 wide with caps up to
+    1000, FP64 elsewhere; the specified three-way policy puts float-float
+    between 1e-5 and that region."""
     p = PrecisionPolicy()
     assert p.pick(3.0, 100) == "fp32"
-    assert p.pick(3.0, 1000) == "ff"
-    assert p.pick(1e-3, 100) == "ff"
+    assert p.pick(0.1, 1000) == "fp32"
+    assert p.pick(3.0, 1001) == "fp64"
+    assert p.pick(0.05, 100) == "fp64"
     assert p.pick(1e-7, 100) == "fp64"
+    q = PrecisionPolicy.specified()
+    assert q.pick(3.0, 100) == "fp32"
+    assert q.pick(3.0, 5000) == "ff"
+    assert q.pick(1e-3, 100) == "ff"
+    assert q.pick(1e-5, 100) == "ff"
+    assert q.pick(9e-6, 100) == "fp64"
     f = Frame(0j, (-1e-8, 1e-8, -1e-8, 1e-8), 8, 8, 100, "auto")
     srv = Server(FakeBackend(100), 100)
     srv.submit(f)
     assert f.dtype == "fp64"
+
+
+def test_precision_policy_matches_the_table():
+    """Every cell of the oracle's precision table that a policy routes to FP32
+    or float-float has that arithmetic within 0.5% of FP64 on its probed
+    pixels, for windows centred on the Julia set and for the serving
+    stream's windows."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "precision_table.txt")
+    rows = [l.split() for l in open(path) if not l.startswith("#")]
+    assert len(rows) == 36
+    for pol in (PrecisionPolicy(), PrecisionPolicy.specified()):
+        for kind, width, cap, px, d32, dff, _, _ in rows:
+            dt = pol.pick(float(width), int(cap))
+            frac = {"fp32": int(d32), "ff": int(dff), "fp64": 0}[dt] / int(px)
+            assert frac <= 0.005, (kind, width, cap, dt, frac)
+
+
+class TimedBackend(FakeBackend):
+    """Fake backend whose launches render nothing and report a device time
+    proportional to the worst-case cost of their rows (an all-interior
+    workload)."""
+
+    def __init__(self, capacity, rate):
+        super().__init__(capacity, polls=0)
+        self.rate = rate
+        self.rows = []
+
+    def launch(self, frames, offsets, rows, stream_idx, schedule=None):
+        u = sum((r1 - r0) * Server._row_cost(f) for f, (r0, r1) in zip(frames, rows))
+        self.rows.extend(rows)
+        return [self.polls, u / self.rate + 15e-6]
+
+    def seconds(self, h):
+        return h[1]
+
+
+def test_step_budget_follows_measured_step_times():
+    """With the budget fed back from device times, steps settle at the target
+    time: the learnt rate drops to the device's (here 5e10 units/s) after the
+    first full step, and a large frame is then split into steps of about the
+    target length."""
+    from paper_1611_03079_amd.serve import StepRate
+    f = Frame(complex(-0.8, 0.156), (-1.5, 1.5, -1.5, 1.5), 200, 4000, 3000, "fp64")
+    b = TimedBackend(200 * 4000, rate=5e10)
+    srv = Server(b, 200 * 4000, step_target_s=1e-3, rate=StepRate(prior=4e11), keep_log=True)
+    srv.submit(f)
+    srv.run_until_idle(timeout=60)
+    assert abs(srv.rate.rate - 5e10) / 5e10 < 1e-6
+    times = [r.seconds for r in srv.log]
+    # the first steps use the prior (too large); once learnt, every full
+    # step lasts about the target
+    assert times[0] > 2e-3
+    full = [t for r, t in zip(srv.log[2:], times[2:]) if r.units >= 0.5 * srv.step_budget]
+    assert len(full) >= 10 and all(abs(t - 1e-3) < 0.1e-3 for t in full)
+    # the rows are covered once and the row costs have no cap
+    rows = sorted(b.rows)
+    assert rows[0][0] == 0 and rows[-1][1] == 4000
+    assert all(a[1] == c[0] for a, c in zip(rows, rows[1:]))
+    assert Server._row_cost(f) == 200 * 3004 * 1.75
+
+
+def test_step_rate_rises_slowly_and_is_capped():
+    from paper_1611_03079_amd.serve import StepRate
+    r = StepRate(prior=1e12, ceiling=3e12, growth=1.1)
+    r.update(1e12 * 1e-3, 1e-3 + 15e-6)        # as fast as the prior
+    assert abs(r.rate - 1e12) < 1e3
+    for _ in range(5):
+        r.update(1e20, 1e-3)                   # light steps: at most 10% up each
+    assert abs(r.rate - 1e12 * 1.1 ** 5) < 1e6
+    for _ in range(50):
+        r.update(1e20, 1e-3)
+    assert r.rate == 3e12
+    r.update(2e11 * 1e-3, 1e-3 + 15e-6)        # a heavy step: down at once
+    assert abs(r.rate - 2e11) < 1e3

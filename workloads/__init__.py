@@ -253,6 +253,59 @@ def precision_windows(seed: int, width: float, max_iter: int, n: int = 32,
     return out
 
 
-def precision_seed(width: float, max_iter: int) -> int:
+def precision_seed(width: float, max_iter: int, kind: str = "serving") -> int:
     """The seed of a (width, cap) cell of the precision table."""
-    return 1000 + 10 * PRECISION_WIDTHS.index(width) + PRECISION_CAPS.index(max_iter)
+    base = 1000 if kind == "serving" else 5000
+    return base + 10 * PRECISION_WIDTHS.index(width) + PRECISION_CAPS.index(max_iter)
+
+
+# --------------------------------------------------------------------------
+# Windows centred on the Julia set itself: what an exploring user zooms into,
+# and the hardest case for a short arithmetic (neighbouring pixels have very
+# different counts).  The centre is found without any escape-time count, from
+# two facts about the map f(z) = z^2 + c:
+#   * its fixed point beta = (1 + sqrt(1 - 4c)) / 2 (principal root) has
+#     multiplier |2 beta| = |1 + sqrt(1 - 4c)| >= 1 (the root's real part is
+#     not negative), so it is repelling, or parabolic at c = 1/4, and such a
+#     fixed point lies in the Julia set J(c);
+#   * J(c) is completely invariant, so both preimages +-sqrt(z - c) of a point
+#     of J(c) lie in J(c) (the inverse-iteration construction of J).
+# `steps` preimages with random branches move the centre off beta along J.
+# --------------------------------------------------------------------------
+def julia_set_point(c: complex, rng: SplitMix64, steps: int = 12) -> complex:
+    import cmath
+    z = 0.5 * (1.0 + cmath.sqrt(1.0 - 4.0 * c))
+    for _ in range(steps):
+        z = cmath.sqrt(z - c)
+        if rng.uniform() < 0.5:
+            z = -z
+    return z
+
+
+def boundary_windows(seed: int, width: float, max_iter: int, n: int = 32,
+                     pixels: int = 1024, size=(640, 480)) -> List[ProbeWindow]:
+    """precision_windows with each window centred on a point of J(C)."""
+    rng = SplitMix64(seed)
+    W, H = size
+    out = []
+    for _ in range(n):
+        c = sample_c_disk(rng)
+        z = julia_set_point(c, rng)
+        height = width * H / W
+        win = (z.real - 0.5 * width, z.real + 0.5 * width,
+               z.imag - 0.5 * height, z.imag + 0.5 * height)
+        ii = [rng.randint(0, W - 1) for _ in range(pixels)]
+        jj = [rng.randint(0, H - 1) for _ in range(pixels)]
+        out.append(ProbeWindow(Frame(c, win, W, H, max_iter, "fp64"), ii, jj))
+    return out
+
+
+def probe_windows(kind: str, width: float, max_iter: int, **kw) -> List[ProbeWindow]:
+    """The windows of one cell of the precision table: kind "serving" (the
+    serving stream's centres) or "boundary" (centred on the Julia set)."""
+    seed = precision_seed(width, max_iter, kind)
+    if kind == "serving":
+        return precision_windows(seed, width, max_iter, **kw)
+    if kind == "boundary":
+        return boundary_windows(seed, width, max_iter, **kw)
+    raise ValueError(kind)
