@@ -69,6 +69,13 @@ def _open(path):
     lib.jro_render_pixels_general.argtypes = [i32, i32, i32, d, d, d, d, d, d, i32, i32, i32,
                                               i64, p_i32, p_i32, p_i32]
     lib.jro_render_pixels_general.restype = None
+    lib.jro_count_rational.argtypes = [i32, i32, d, d, d, d, d, d, i32]
+    lib.jro_count_rational.restype = i32
+    lib.jro_render_rational.argtypes = [i32, i32, d, d, d, d, d, d, d, d, i32, i32, i32, p_i32]
+    lib.jro_render_rational.restype = None
+    lib.jro_render_pixels_rational.argtypes = [i32, i32, d, d, d, d, d, d, d, d, i32, i32, i32,
+                                               i64, p_i32, p_i32, p_i32]
+    lib.jro_render_pixels_rational.restype = None
     p_u32 = ctypes.POINTER(ctypes.c_uint32)
     lib.jro_colorize.argtypes = [p_i32, i64, p_u32, i32, p_u32]
     lib.jro_colorize.restype = None
@@ -79,17 +86,32 @@ def _as_ptr(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
 
 
-def render(c, window, width, height, max_iter, dtype="fp64", mode="julia", degree=2):
+def _rational_args(dtype, mode, lam):
+    if mode != "julia" or dtype not in ("fp64", "fp32"):
+        raise ValueError("the rational maps have Julia images in fp64 and fp32 only")
+    lam = complex(lam)
+    return lam.real, lam.imag
+
+
+def render(c, window, width, height, max_iter, dtype="fp64", mode="julia", degree=2,
+           lam=None):
     """Counts of a whole image: int32 array of shape (height, width), row 0 = im_max.
 
     ``c`` is a complex (ignored in Mandelbrot mode); ``window`` is
     (re_min, re_max, im_min, im_max).  ``degree`` 3..8 iterates the general
-    map Z^d + C (jro_render_general); 2 is the paper's Z^2 + C.
+    map Z^d + C (jro_render_general); 2 is the paper's Z^2 + C.  With ``lam``
+    (a complex) the map is the rational Z^d + C + lam / Z^d
+    (jro_render_rational; Julia images, fp64 or fp32).
     """
     lib = _load()
     c = complex(c)
     out = np.empty((int(height), int(width)), dtype=np.int32)
-    if degree == 2:
+    if lam is not None:
+        lr, li = _rational_args(dtype, mode, lam)
+        lib.jro_render_rational(DTYPES[dtype], int(degree), c.real, c.imag, lr, li,
+                                *[float(v) for v in window], int(width), int(height),
+                                int(max_iter), _as_ptr(out))
+    elif degree == 2:
         lib.jro_render(DTYPES[dtype], MODES[mode], c.real, c.imag,
                        *[float(v) for v in window], int(width), int(height),
                        int(max_iter), _as_ptr(out))
@@ -112,7 +134,7 @@ def render_general(c, window, width, height, max_iter, dtype="fp64", mode="julia
 
 
 def render_pixels(c, window, width, height, max_iter, ii, jj, dtype="fp64",
-                  mode="julia", degree=2):
+                  mode="julia", degree=2, lam=None):
     """Counts at the pixels (column ii[k], row jj[k]) of the image ``render`` gives."""
     lib = _load()
     c = complex(c)
@@ -120,7 +142,13 @@ def render_pixels(c, window, width, height, max_iter, ii, jj, dtype="fp64",
     jj = np.ascontiguousarray(jj, dtype=np.int32)
     assert ii.shape == jj.shape and ii.ndim == 1
     out = np.empty(ii.shape, dtype=np.int32)
-    if degree == 2:
+    if lam is not None:
+        lr, li = _rational_args(dtype, mode, lam)
+        lib.jro_render_pixels_rational(DTYPES[dtype], int(degree), c.real, c.imag, lr, li,
+                                       *[float(v) for v in window], int(width), int(height),
+                                       int(max_iter), ii.size, _as_ptr(ii), _as_ptr(jj),
+                                       _as_ptr(out))
+    elif degree == 2:
         lib.jro_render_pixels(DTYPES[dtype], MODES[mode], c.real, c.imag,
                               *[float(v) for v in window], int(width), int(height),
                               int(max_iter), ii.size, _as_ptr(ii), _as_ptr(jj),
@@ -156,11 +184,16 @@ def pixel_center(window, width, height, i, j):
     return x.value, y.value
 
 
-def count(z0, c, max_iter, dtype="fp64", degree=None):
+def count(z0, c, max_iter, dtype="fp64", degree=None, lam=None):
     """Count of one orbit with explicit Z_0 and C.  ``degree`` None: the
-    Z^2 + C formulations; 2..8: the general-map formulations."""
+    Z^2 + C formulations; 2..8: the general-map formulations; with ``lam``
+    the rational map Z^d + C + lam / Z^d (degree None means 2)."""
     lib = _load()
     z0, c = complex(z0), complex(c)
+    if lam is not None:
+        lr, li = _rational_args(dtype, "julia", lam)
+        return int(lib.jro_count_rational(DTYPES[dtype], int(degree or 2), z0.real, z0.imag,
+                                          c.real, c.imag, lr, li, int(max_iter)))
     if degree is None:
         return int(lib.jro_count(DTYPES[dtype], z0.real, z0.imag, c.real, c.imag,
                                  int(max_iter)))

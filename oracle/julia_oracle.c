@@ -368,6 +368,131 @@ void jro_render_pixels_general(int32_t dtype, int32_t mode, int32_t degree, doub
 }
 
 /* ------------------------------------------------------------------------ */
+/* Rational maps with two parameters: Z^d + C + lambda / Z^d (d = 2..8).     */
+/* W = Z^d by the general maps' products; lambda / W is                      */
+/* ((lr wr + li wi) + i (li wr - lr wi)) / (wr wr + wi wi), each product,    */
+/* sum and quotient rounded; then Z' = ((wr + cr) + tr) + i ((wi + ci) + ti).*/
+/* The test is "escaped unless |Z|^2 <= 4", so an iterate that is not a     */
+/* number (0 / 0 at the pole Z = 0) counts as escaped.                       */
+/* ------------------------------------------------------------------------ */
+static int32_t count_fp64_rational(double x, double y, double cr, double ci, double lr,
+                                   double li, int32_t d, int32_t max_iter)
+{
+    int32_t n = 0;
+    while (n < max_iter) {
+        double x2 = x * x;
+        double y2 = y * y;
+        double m = x2 + y2;
+        if (!(m <= 4.0))
+            break;
+        double wr = x, wi = y;          /* W = Z^d, as for the general maps */
+        for (int32_t k = 1; k < d; k++) {
+            double u_rr = wr * x;
+            double u_ii = wi * y;
+            double u_ri = wr * y;
+            double u_ir = wi * x;
+            double vr = u_rr - u_ii;
+            double vi = u_ri + u_ir;
+            wr = vr;
+            wi = vi;
+        }
+        double q_r = wr * wr;
+        double q_i = wi * wi;
+        double q = q_r + q_i;          /* |W|^2 */
+        double a = lr * wr;
+        double b = li * wi;
+        double e = li * wr;
+        double f = lr * wi;
+        double num_r = a + b;          /* Re(lambda conj(W)) */
+        double num_i = e - f;          /* Im(lambda conj(W)) */
+        double tr = num_r / q;
+        double ti = num_i / q;
+        double sr = wr + cr;
+        double si = wi + ci;
+        x = sr + tr;
+        y = si + ti;
+        n = n + 1;
+    }
+    return n;
+}
+
+static int32_t count_fp32_rational(float x, float y, float cr, float ci, float lr, float li,
+                                   int32_t d, int32_t max_iter)
+{
+    int32_t n = 0;
+    while (n < max_iter) {
+        float x2 = x * x;
+        float y2 = y * y;
+        float m = x2 + y2;
+        if (!(m <= 4.0f))
+            break;
+        float wr = x, wi = y;          /* W = Z^d, as for the general maps */
+        for (int32_t k = 1; k < d; k++) {
+            float u_rr = wr * x;
+            float u_ii = wi * y;
+            float u_ri = wr * y;
+            float u_ir = wi * x;
+            float vr = u_rr - u_ii;
+            float vi = u_ri + u_ir;
+            wr = vr;
+            wi = vi;
+        }
+        float q_r = wr * wr;
+        float q_i = wi * wi;
+        float q = q_r + q_i;
+        float a = lr * wr;
+        float b = li * wi;
+        float e = li * wr;
+        float f = lr * wi;
+        float num_r = a + b;
+        float num_i = e - f;
+        float tr = num_r / q;
+        float ti = num_i / q;
+        float sr = wr + cr;
+        float si = wi + ci;
+        x = sr + tr;
+        y = si + ti;
+        n = n + 1;
+    }
+    return n;
+}
+
+int32_t jro_count_rational(int32_t dtype, int32_t degree, double x0, double y0, double cr,
+                           double ci, double lr, double li, int32_t max_iter)
+{
+    if (dtype == JRO_FP32)
+        return count_fp32_rational((float)x0, (float)y0, (float)cr, (float)ci, (float)lr,
+                                   (float)li, degree, max_iter);
+    return count_fp64_rational(x0, y0, cr, ci, lr, li, degree, max_iter);
+}
+
+void jro_render_rational(int32_t dtype, int32_t degree, double cr, double ci, double lr,
+                         double li, double re_min, double re_max, double im_min,
+                         double im_max, int32_t W, int32_t H, int32_t max_iter, int32_t *out)
+{
+    for (int32_t j = 0; j < H; j++)
+        for (int32_t i = 0; i < W; i++) {
+            double x, y;
+            jro_pixel_center(re_min, re_max, im_min, im_max, W, H, i, j, &x, &y);
+            out[(int64_t)j * W + i] = jro_count_rational(dtype, degree, x, y, cr, ci, lr, li,
+                                                         max_iter);
+        }
+}
+
+void jro_render_pixels_rational(int32_t dtype, int32_t degree, double cr, double ci,
+                                double lr, double li, double re_min, double re_max,
+                                double im_min, double im_max, int32_t W, int32_t H,
+                                int32_t max_iter, int64_t n, const int32_t *ii,
+                                const int32_t *jj, int32_t *out)
+{
+    for (int64_t k = 0; k < n; k++) {
+        double x, y;
+        jro_pixel_center(re_min, re_max, im_min, im_max, W, H, ii[k], jj[k], &x, &y);
+        out[k] = jro_count_rational(dtype, degree, x, y, cr, ci, lr, li, max_iter);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* One orbit in the chosen formulation.                                      */
 /* ------------------------------------------------------------------------ */
 int32_t jro_count(int32_t dtype, double x0, double y0, double cr, double ci,

@@ -89,6 +89,31 @@ void jro_render_pixels_general(int32_t dtype, int32_t mode, int32_t degree, doub
                                double im_max, int32_t W, int32_t H, int32_t max_iter,
                                int64_t n, const int32_t *ii, const int32_t *jj, int32_t *out);
 
+/* Rational maps with two complex parameters (the further functions and
+ * parameters of Section 4 and the closing discussion):
+ *     Z_{n+1} = W + C + lambda / W,   W = Z_n^d,  d = 2..8,
+ * Julia images only (the pixel gives Z_0), FP64 or FP32.  W is formed as in
+ * the general maps; lambda / W as (Re(lambda conj W) + i Im(lambda conj W)) /
+ * |W|^2 with
+ *     |W|^2 = wr*wr + wi*wi,  Re = lr*wr + li*wi,  Im = li*wr - lr*wi,
+ * each product, sum and quotient rounded in the formulation's precision (no
+ * fused operations; IEEE division); then
+ *     x' = (wr + cr) + Re/|W|^2,   y' = (wi + ci) + Im/|W|^2.
+ * Count and pixel mapping as above; the test is "escaped unless
+ * fl(fl(x*x) + fl(y*y)) <= 4", so an iterate that is not a number (Z = 0 is
+ * a pole: 0/0) counts as escaped.  With lambda = 0 the counts are those of
+ * Z^d + C wherever no iterate is exactly 0. */
+int32_t jro_count_rational(int32_t dtype, int32_t degree, double x0, double y0, double cr,
+                           double ci, double lr, double li, int32_t max_iter);
+void jro_render_rational(int32_t dtype, int32_t degree, double cr, double ci, double lr,
+                         double li, double re_min, double re_max, double im_min,
+                         double im_max, int32_t W, int32_t H, int32_t max_iter, int32_t *out);
+void jro_render_pixels_rational(int32_t dtype, int32_t degree, double cr, double ci,
+                                double lr, double li, double re_min, double re_max,
+                                double im_min, double im_max, int32_t W, int32_t H,
+                                int32_t max_iter, int64_t n, const int32_t *ii,
+                                const int32_t *jj, int32_t *out);
+
 /* Colour levels from counts (Section 2: each pixel is given a colour level by
  * its iteration count): out[k] = palette[min(counts[k], palette_len - 1)],
  * for counts >= 0 and palette_len >= 1. */

@@ -226,6 +226,42 @@ def render_general(c, window, W, H, max_iter, dtype="fp64", mode="julia", degree
     return counts_general(x, y, c.real, c.imag, max_iter, degree, dtype)
 
 
+def counts_rational(x0, y0, cr, ci, lr, li, max_iter, degree, dtype):
+    """The two-parameter rational map Z^d + C + lam / Z^d, one ufunc per
+    rounded operation: W = Z^d as in _power_add, lam / W = (lam conj W) /
+    |W|^2 in real arithmetic (numpy's own complex division uses another
+    algorithm), then (W + C) + lam / W.  An iterate that is not a number
+    counts as escaped (the test is "not |Z|^2 <= 4")."""
+    T = F32 if dtype == "fp32" else F64
+    x0 = np.asarray(x0, F64).astype(T)
+    y0 = np.asarray(y0, F64).astype(T)
+    cr, ci, lr, li = (np.broadcast_to(np.asarray(v, F64).astype(T), x0.shape)
+                      for v in (cr, ci, lr, li))
+
+    def esc(s):
+        x, y = s
+        return ~((x * x + y * y) <= T(4.0))
+
+    def step(s, act):
+        x, y = s
+        wr, wi = x, y
+        for _ in range(degree - 1):
+            wr, wi = wr * x - wi * y, wr * y + wi * x
+        q = wr * wr + wi * wi
+        xn = (wr + cr) + (lr * wr + li * wi) / q
+        yn = (wi + ci) + (li * wr - lr * wi) / q
+        return (np.where(act, xn, x), np.where(act, yn, y))
+
+    with np.errstate(all="ignore"):
+        return _iterate((x0, y0), step, esc, max_iter)
+
+
+def render_rational(c, lam, window, W, H, max_iter, dtype="fp64", degree=2):
+    x, y = pixel_grid(window, W, H)
+    c, lam = complex(c), complex(lam)
+    return counts_rational(x, y, c.real, c.imag, lam.real, lam.imag, max_iter, degree, dtype)
+
+
 COUNTS = {"fp64": counts_fp64, "fp32": counts_fp32, "ff": counts_ff}
 
 

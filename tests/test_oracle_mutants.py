@@ -67,6 +67,17 @@ MUTANTS = {
                            "                             W, H, max_iter, ii[k], jj[k > 0 ? k - 1 : 0]);"),
     "pixels_mode_dropped": ("        out[k] = pixel_count(dtype, mode, cr, ci,",
                             "        out[k] = pixel_count(dtype, JRO_JULIA, cr, ci,"),
+    # the two-parameter rational maps: a pole's 0/0 taken as bounded, a sign
+    # in lam conj(W), |W|^2 with a minus, Im(lam / W) dropped, lam's parts
+    # swapped (FP32), the per-pixel entry's column and row swapped
+    "rational_nan_inside": ("if (!(m <= 4.0))", "if (m > 4.0)"),
+    "rational_re_sign": ("double num_r = a + b;", "double num_r = a - b;"),
+    "rational_im_sign": ("double num_i = e - f;", "double num_i = f - e;"),
+    "rational_norm_sign": ("double q = q_r + q_i;", "double q = q_r - q_i;"),
+    "rational_dropped_im": ("double si = wi + ci;\n        x = sr + tr;\n        y = si + ti;",
+                            "double si = wi + ci;\n        x = sr + tr;\n        y = si;"),
+    "rational_fp32_lambda_parts": ("float a = lr * wr;", "float a = li * wr;"),
+    "rational_pixels_ij_swap": ("W, H, ii[k], jj[k], &x, &y);", "W, H, jj[k], ii[k], &x, &y);"),
 }
 
 
@@ -95,6 +106,12 @@ def _battery():
     checks += [("pixels_%s_%d_%d" % (d, case, deg), pins.test_render_pixels_matches_whole_images,
                 (d, case, deg))
                for d, case, deg in (("fp64", 0, 2), ("fp32", 1, 2), ("ff", 0, 3), ("fp64", 1, 5))]
+    checks += [("rational_orbits_" + d, pins.test_rational_exact_small_orbits, (d,))
+               for d in pins.RATIONAL_DTYPES]
+    checks += [("rational_numpy_%s_%d" % (d, k), pins.test_rational_matches_numpy_reimplementation,
+                (d, k)) for d, k in (("fp64", 2), ("fp32", 3))]
+    checks += [("rational_pixels_fp64", pins.test_render_pixels_rational_matches_whole_images,
+                ("fp64",))]
     for name, fn, args in checks:
         try:
             fn(*args)

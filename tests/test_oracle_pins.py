@@ -658,3 +658,128 @@ def test_render_pixels_matches_whole_images(dtype, case, degree):
     np.testing.assert_array_equal(got, whole[jj, ii])
     # the images must not be trivial: several distinct counts, some capped
     assert len(np.unique(got)) >= 5 and (got == cap).any()
+
+
+# ------------------------- rational maps Z^d + C + lam / Z^d (two parameters)
+# Orbits whose every value is dyadic: exact in binary64 and binary32, so the
+# counts are those of exact arithmetic.  Each is worked by hand.
+RATIONAL_ORBITS = [
+    # degree, Z_0, C, lam, count (cap 100)
+    (2, 1, 0, 1, 2),               # 1; 1 + 1/1 = 2 (|2|^2 = 4 is not > 4); 4 + 1/4
+    (2, 1j, 0, -1, 2),             # i; -1 + (-1)/(-1) = 0; then 0/0: not a number
+    (2, 0, 0, 1, 1),               # the pole itself: 0, then 0/0
+    (2, 1, -1 - 1j, 1 + 1j, 100),  # lam / 1 cancels C: 1 is a fixed point
+    (2, 1, 0, 1j, 2),              # 1; 1 + i; W = 2i, i/(2i) = 1/2: 1/2 + 2i
+    (2, 1, 0, 1 + 1j, 1),          # 1; 2 + i
+    (3, 1, 0, 2, 1),               # 1; 1 + 2 = 3
+    (2, 3, 0, 1, 0),
+    (2, 2, 0, 0, 1),               # lam = 0: 2; 4
+    (2, 1, -1, 1, 100),            # 1 - 1 + 1 = 1
+    (4, -1, -1, 1, 100),           # (-1)^4 = 1: 1 - 1 + 1 = 1, then 1 again
+]
+RATIONAL_DTYPES = ["fp64", "fp32"]
+
+
+@pytest.mark.parametrize("dtype", RATIONAL_DTYPES)
+def test_rational_exact_small_orbits(dtype):
+    for d, z0, c, lam, want in RATIONAL_ORBITS:
+        assert oracle.count(z0, c, 100, dtype, degree=d, lam=lam) == want, (d, z0, c, lam)
+        assert oracle.count(z0, c, 1, dtype, degree=d, lam=lam) == min(want, 1)
+        assert oracle.count(z0, c, 0, dtype, degree=d, lam=lam) == 0
+
+
+@pytest.mark.parametrize("dtype", RATIONAL_DTYPES)
+@pytest.mark.parametrize("degree", [2, 3, 5])
+def test_rational_lambda_zero_is_the_polynomial_map(dtype, degree):
+    """lam = 0 adds 0 / |W|^2 = +0 to each coordinate, which changes no
+    nonzero value: the counts are those of Z^d + C (no iterate of these
+    grids is exactly 0)."""
+    for c, win in ((complex(0.4, 0.3), (-1.3, 1.3, -1.2, 1.2)),
+                   (complex(-0.8, 0.156), (-1.5, 1.5, -1.5, 1.5))):
+        a = oracle.render(c, win, 41, 30, 90, dtype, "julia", degree, lam=0j)
+        b = oracle.render_general(c, win, 41, 30, 90, dtype, "julia", degree)
+        np.testing.assert_array_equal(a, b)
+
+
+RATIONAL_CASES = [
+    # c, lam, window: each image holds escapes, bounded orbits and many
+    # counts at degrees 2, 3 and 4 (an attracting cycle away from the pole)
+    (complex(-0.55, 0.1), complex(-0.02, 0.01), (-1.5, 1.5, -1.2, 1.2)),
+    (complex(-0.1, 0.65), complex(0.005, 0.005), (-1.3, 1.1, -0.9, 1.0)),
+]
+
+
+@pytest.mark.parametrize("dtype", RATIONAL_DTYPES)
+@pytest.mark.parametrize("degree", [2, 3, 4])
+def test_rational_matches_numpy_reimplementation(dtype, degree):
+    for c, lam, win in RATIONAL_CASES:
+        a = oracle.render(c, win, 37, 29, 70, dtype, "julia", degree, lam=lam)
+        b = ind.render_rational(c, lam, win, 37, 29, 70, dtype, degree)
+        np.testing.assert_array_equal(a, b)
+        # the images are not trivial: escapes, interior and several counts
+        assert len(np.unique(a)) >= 5 and (a == 70).any() and (a < 3).any()
+
+
+@pytest.mark.parametrize("dtype", RATIONAL_DTYPES)
+def test_rational_symmetries(dtype):
+    """Conjugating C and lam mirrors the image top to bottom (every
+    operation, the division included, is sign-symmetric); for even d the map
+    is even, f(-Z) = f(Z) bit for bit, so the centred image is its own
+    180-degree rotation."""
+    W, H, cap = 60, 44, 80
+    win = (-1.4, 1.4, -1.1, 1.1)
+    c, lam = complex(-0.35, 0.52), complex(0.04, 0.03)
+    for d in (2, 3, 4):
+        a = oracle.render(c, win, W, H, cap, dtype, "julia", d, lam=lam)
+        b = oracle.render(c.conjugate(), win, W, H, cap, dtype, "julia", d,
+                          lam=lam.conjugate())
+        np.testing.assert_array_equal(b, a[::-1, :])
+        if d % 2 == 0:
+            np.testing.assert_array_equal(a, a[::-1, ::-1])
+
+
+@pytest.mark.parametrize("degree", [2, 3])
+def test_rational_exact_rational_counts_small_cap(degree):
+    """Brute force in exact rationals on an 8 x 8 grid with cap 4 (the exact
+    values' sizes multiply by about 2d + 2 per step): the FP64 count must
+    agree wherever no exact |Z_n|^2 lies within 1e-9 of 4."""
+    win = (-1.3, 1.3, -1.3, 1.3)
+    c, lam = complex(-0.25, 0.375), complex(0.0625, -0.03125)
+    cr, ci, lr, li = (Fraction(v) for v in (c.real, c.imag, lam.real, lam.imag))
+    cap = 4
+    got = oracle.render(c, win, 8, 8, cap, "fp64", "julia", degree, lam=lam)
+    compared = 0
+    for j in range(8):
+        for i in range(8):
+            x0, y0 = oracle.pixel_center(win, 8, 8, i, j)
+            x, y = Fraction(x0), Fraction(y0)
+            n, close = 0, False
+            while n < cap:
+                m = x * x + y * y
+                if abs(m - 4) < Fraction(1, 10 ** 9):
+                    close = True
+                if m > 4:
+                    break
+                wr, wi = x, y
+                for _ in range(degree - 1):
+                    wr, wi = wr * x - wi * y, wr * y + wi * x
+                q = wr * wr + wi * wi          # nonzero: no grid orbit hits 0
+                x, y = wr + cr + (lr * wr + li * wi) / q, wi + ci + (li * wr - lr * wi) / q
+                n += 1
+            if not close:
+                assert got[j, i] == n, (i, j, got[j, i], n)
+                compared += 1
+    assert compared >= 56
+
+
+@pytest.mark.parametrize("dtype", RATIONAL_DTYPES)
+def test_render_pixels_rational_matches_whole_images(dtype):
+    c, lam, win = RATIONAL_CASES[1]
+    W, H, cap, d = 29, 23, 70, 3
+    ii, jj = _pixel_list(W, H, 31)
+    got = oracle.render_pixels(c, win, W, H, cap, ii, jj, dtype, "julia", d, lam=lam)
+    np.testing.assert_array_equal(got, ind.render_rational(c, lam, win, W, H, cap, dtype,
+                                                           d)[jj, ii])
+    whole = oracle.render(c, win, W, H, cap, dtype, "julia", d, lam=lam)
+    np.testing.assert_array_equal(got, whole[jj, ii])
+    assert len(np.unique(got)) >= 5 and (got == cap).any()
