@@ -95,7 +95,26 @@ typedef struct { double re_min, re_max, im_min, im_max; } jr_window;
  * and test fl(fl(x x) + fl(y y)) > 4; float-float uses its double-word
  * operations throughout.  Count, escape radius and pixel mapping are those
  * of Z^2 + C.
+ *
+ * map selects the family (the further functions and parameters of Section 4
+ * and the closing discussion):
+ *   JR_MAP_POLY      Z^degree + C (above);
+ *   JR_MAP_RATIONAL  the two-parameter rational map
+ *                        Z_{n+1} = W + C + lambda / W,  W = Z_n^degree
+ *                    (degree 0 means 2), Julia mode only, dtype JR_FP64 or
+ *                    JR_FP32.  W is formed as for the general maps; with
+ *                    q = wr*wr + wi*wi, the update is
+ *                        x' = (wr + cr) + (lr*wr + li*wi) / q,
+ *                        y' = (wi + ci) + (li*wr - lr*wi) / q,
+ *                    every product, sum and quotient rounded (IEEE division,
+ *                    no fused operations); a pixel escapes unless
+ *                    fl(fl(x*x) + fl(y*y)) <= 4, so the iterate after a hit on
+ *                    the pole Z = 0 (0/0, not a number) counts as escaped.
+ *                    Launches holding such frames run the rows kernel (a
+ *                    schedule asking for the tiled or hybrid kernels is
+ *                    carried over to it) or, when asked, the plain kernel.
  */
+typedef enum { JR_MAP_POLY = 0, JR_MAP_RATIONAL = 1 } jr_map;
 typedef struct {
     jr_complex c;
     jr_window w;
@@ -107,6 +126,9 @@ typedef struct {
     int32_t row_end;    /* one past the last row; 0 = height   */
     int32_t degree;     /* 0 or 2: Z^2 + C; 3..8: Z^degree + C */
     int64_t out_offset; /* element offset of pixel (0, 0)      */
+    int32_t map;        /* jr_map                               */
+    int32_t reserved;   /* 0                                    */
+    jr_complex lambda;  /* JR_MAP_RATIONAL: lambda; finite      */
 } jr_frame;
 
 /*
@@ -236,7 +258,7 @@ int julia_render_batch(const jr_frame *frames, int32_t n, int32_t *out_base,
  * them, on one stream or with events.  Other errors are julia_render_batch's.
  */
 #define JR_NOALLOC_MAX_FRAMES 1024
-#define JR_NOALLOC_SCRATCH_BYTES (64 * 4096 + JR_NOALLOC_MAX_FRAMES * 112)
+#define JR_NOALLOC_SCRATCH_BYTES (64 * 4096 + JR_NOALLOC_MAX_FRAMES * 144)
 int julia_render_batch_noalloc(const jr_frame *frames, int32_t n, int32_t *out_base,
                                int64_t out_capacity, const jr_schedule *sched, void *stream);
 

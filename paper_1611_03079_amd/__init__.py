@@ -45,7 +45,8 @@ class jr_frame(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("mode", ctypes.c_int32), ("row_begin", ctypes.c_int32),
                 ("row_end", ctypes.c_int32), ("degree", ctypes.c_int32),
-                ("out_offset", ctypes.c_int64)]
+                ("out_offset", ctypes.c_int64), ("map", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("lam", jr_complex)]
 
 
 class jr_schedule(ctypes.Structure):
@@ -57,7 +58,7 @@ class jr_schedule(ctypes.Structure):
                 ("handoff", ctypes.c_int32)]
 
 
-assert ctypes.sizeof(jr_frame) == 88
+assert ctypes.sizeof(jr_frame) == 112
 
 
 @dataclass(frozen=True)
@@ -301,7 +302,7 @@ def set_image_schedule(dtype: str, max_iter_limit: int, pixels_limit: int, sched
 
 def render(c, window, width: int, height: int, max_iter: int, dtype: str = "fp64",
            out=None, stream=None, mode: str = "julia", plain: bool = False,
-           schedule: Optional["Schedule"] = None, palette=None, degree: int = 2):
+           schedule: Optional["Schedule"] = None, palette=None, degree: int = 2, lam=None):
     """Counts of one image as an int32 (height, width) CUDA tensor (row 0 = im_max).
 
     ``plain=True`` uses the one-thread-per-pixel comparator kernel.  Otherwise
@@ -312,15 +313,17 @@ def render(c, window, width: int, height: int, max_iter: int, dtype: str = "fp64
     With ``palette`` (see _palette_ptr) each pixel holds the 32 bits of
     palette[min(count, len - 1)] instead of its count, stored by the kernel
     itself (julia_render_batch_colored).  ``degree`` 3..8 iterates the
-    general map Z^degree + C (through julia_render_batch).
+    general map Z^degree + C (through julia_render_batch); with ``lam`` the
+    map is the rational Z^degree + C + lam / Z^degree (Julia images, fp64 or
+    fp32).
     """
     out = _out_tensor(out, (height, width))
     st = _stream_ptr(stream)
     dt = DTYPES[dtype]
-    if degree != 2 and palette is None:
+    if (degree != 2 or lam is not None) and palette is None:
         if plain:
             schedule = Schedule(kernel="plain")
-        f = _OneFrame(c, window, width, height, max_iter, dtype, mode, degree)
+        f = _OneFrame(c, window, width, height, max_iter, dtype, mode, degree, lam)
         sched = ctypes.byref(schedule.to_c()) if schedule is not None else None
         _check(lib.julia_render_batch(_frames_array([f], [0]), 1, ctypes.c_void_p(out.data_ptr()),
                                       width * height, sched, st))
@@ -329,9 +332,9 @@ def render(c, window, width: int, height: int, max_iter: int, dtype: str = "fp64
         pp, plen = _palette_ptr(palette)
         if plain:
             schedule = Schedule(kernel="plain")
-        elif schedule is None and (mode != "julia" or degree != 2):
+        elif schedule is None and (mode != "julia" or degree != 2 or lam is not None):
             schedule = tuned_schedule(dtype, max_iter, width * height)
-        if schedule is None and mode == "julia" and degree == 2:
+        if schedule is None and mode == "julia" and degree == 2 and lam is None:
             _install_image_schedules()
             c = complex(c)
             _check(lib.julia_render_colored(jr_complex(c.real, c.imag), _window(window), width,
@@ -339,7 +342,7 @@ def render(c, window, width: int, height: int, max_iter: int, dtype: str = "fp64
                                             ctypes.c_void_p(out.data_ptr()), st))
         else:
             arr = _frames_array([_OneFrame(c, window, width, height, max_iter, dtype, mode,
-                                           degree)], [0])
+                                           degree, lam)], [0])
             sched = ctypes.byref(schedule.to_c()) if schedule is not None else None
             _check(lib.julia_render_batch_colored(arr, 1, pp, plen,
                                                   ctypes.c_void_p(out.data_ptr()),
@@ -378,16 +381,24 @@ class _OneFrame:
     dtype: str
     mode: str
     degree: int = 2
+    lam: Optional[complex] = None
 
 
 def _frames_array(frames, offsets, rows=None):
+    """jr_frame records of objects with c, window, width, height, max_iter,
+    dtype and optionally mode, degree and lam (a complex: the rational map
+    Z^d + C + lam / Z^d)."""
     arr = (jr_frame * len(frames))()
     for k, f in enumerate(frames):
         c = complex(f.c)
         rb, re_ = (0, 0) if rows is None else rows[k]
+        lam = getattr(f, "lam", None)
+        lam_c = jr_complex(0.0, 0.0) if lam is None else jr_complex(complex(lam).real,
+                                                                    complex(lam).imag)
         arr[k] = jr_frame(jr_complex(c.real, c.imag), _window(f.window), f.width, f.height,
                           f.max_iter, DTYPES[f.dtype], MODES[getattr(f, "mode", "julia")],
-                          rb, re_, int(getattr(f, "degree", 2)), int(offsets[k]))
+                          rb, re_, int(getattr(f, "degree", 2)), int(offsets[k]),
+                          0 if lam is None else 1, 0, lam_c)
     return arr
 
 

@@ -8,14 +8,20 @@ events around prepared launches (jr_plan_launch) and keeps the fastest.
 
 Search, in stages from a base schedule:
   1. the iteration block (unroll, defer),
-  2. tile shape x scheduling mode x refill threshold,
+  2. tile shape x scheduling mode x refill threshold, then the tile order
+     (frames as given, or the most expensive first),
   3. resident waves per compute unit (persistent mode only),
   4. the iteration block again under the chosen tiling,
   5. the hybrid stream (fresh packets tested every iteration, survivors
      refilled) under that tiling, for several bail points,
   6. the two-phase row-packet kernel: its first block, then scheduling mode,
-     refill, resident waves and tile shape, then its first block again,
-  7. the batched one-thread-per-pixel kernel as a last candidate.
+     refill, resident waves and tile shape, then the tile order, then its
+     first block again,
+  7. the batched one-thread-per-pixel kernel, in both tile orders, as the
+     last candidates.
+A workload too large to search whole is searched on a subset of its frames;
+``confirm`` then times the subset's best candidates on the whole workload and
+keeps the fastest there.
 
 Results are cached in a JSON file keyed by (device, dtype, cap bucket, pixel
 bucket); ``apply_cache`` installs the cached winners as the library defaults
@@ -37,6 +43,7 @@ WAVES = [8, 16, 24, 32]
 HYBRID_BAILS = [4, 8, 16, 32]
 ROWS_FIRST = [4, 8, 12, 16, 20, 24, 32, 48, 64]
 ROWS_HANDOFF = [0, 16, 32, 64, 96, 128, 160, 192]
+ORDERS = [dict(order="table"), dict(order="cost")]
 
 DEFAULT_CACHE = os.environ.get(
     "JR_AUTOTUNE_CACHE",
@@ -189,6 +196,7 @@ def tune(frames: Sequence, base: Optional[jr.Schedule] = None, reps: int = 3,
     s = _stage(frames, s, [dict(tile_w=tw, tile_h=th, persistent=p, refill=r)
                            for tw, th in TILES for p in (1, 0) for r in REFILLS], reps, log,
                singles)
+    s = _stage(frames, s, ORDERS, reps, log, singles)
     if s.persistent:
         s = _stage(frames, s, [dict(waves_per_cu=w) for w in WAVES], reps, log, singles)
     # re-check the block choice under the final tiling
@@ -212,18 +220,44 @@ def tune(frames: Sequence, base: Optional[jr.Schedule] = None, reps: int = 3,
                            for p in (1, 0) for rf in (8, 16, 32) for w in (16, 32)
                            for tw, th in ((64, 8), (64, 16), (64, 32), (64, 64), (32, 16))],
                reps, log, singles)
+    r = _stage(frames, r, ORDERS, reps, log, singles)
     r = _stage(frames, r, [dict(bail=p, handoff=h) for p in ROWS_FIRST for h in ROWS_HANDOFF],
                reps, log, singles)
     t = min(tt for d, tt in log if jr.Schedule(**d) == r)
     if t < best_t:
         s, best_t = r, t
     # the one-thread-per-pixel kernel over the batch is a candidate too
-    plain = jr.Schedule(kernel="plain", order=s.order)
-    t = _time(frames, plain, reps, singles)
-    log.append((asdict(plain), t))
-    if t < best_t:
-        s, best_t = plain, t
+    for order in ("table", "cost"):
+        plain = jr.Schedule(kernel="plain", order=order)
+        t = _time(frames, plain, reps, singles)
+        log.append((asdict(plain), t))
+        if t < best_t:
+            s, best_t = plain, t
     return s, best_t, log
+
+
+def confirm(frames: Sequence, log: list, top: int = 6, reps: int = 2,
+            singles: bool = False) -> Tuple[jr.Schedule, float, list]:
+    """Times the `top` fastest distinct schedules of a tuning log (taken on a
+    subset of a workload), each also in the other tile order, on `frames`
+    (the whole workload); returns the fastest there, its time and the
+    timings."""
+    ranked = []
+    for d, t in sorted(log, key=lambda e: e[1]):
+        sc = jr.Schedule(**d)
+        if sc not in ranked:
+            ranked.append(sc)
+        if len(ranked) == top:
+            break
+    cands = []
+    for sc in ranked:
+        for o in ("cost", "table"):
+            v = replace(sc, order=o)
+            if v not in cands:
+                cands.append(v)
+    timings = [(asdict(v), _time(frames, v, reps, singles)) for v in cands]
+    d, t = min(timings, key=lambda e: e[1])
+    return jr.Schedule(**d), t, timings
 
 
 _DEVICE_NAMES: Dict[int, str] = {}
@@ -310,6 +344,8 @@ def standard_workloads():
     import workloads as wl
     return {
         "parameter_path_fp32": wl.parameter_path(),
+        "parameter_path_fp64": wl.parameter_path(dtype="fp64"),
+        "parameter_path_ff": wl.parameter_path(dtype="ff"),
         "single_4096_fp32_cap100": [wl.single_4096(s, 100, "fp32") for s in range(2)],
         "single_4096_fp32_cap1000": [wl.single_4096(s, 1000, "fp32") for s in range(2)],
         "single_4096_fp64_cap100": [wl.single_4096(s, 100, "fp64") for s in range(2)],
@@ -319,10 +355,15 @@ def standard_workloads():
         "single_small_fp64": wl.square_sweep("fp64", sides=(32, 100, 200)),
         "single_1000_fp64": wl.square_sweep("fp64", sides=(1000, 2000)),
         "single_10000_fp64": wl.square_sweep("fp64", sides=(10000,)),
+        # searched on its first 64 frames, confirmed on all 1024 (CONFIRM)
         "uneven_fp32_ff": wl.uneven_batch(0, n=64),
         "cardioid_path_fp32": wl.cardioid_path(64),
         "general_deg3_fp32": wl.general_path(32, 3),
     }
+
+
+# workloads searched on a subset and confirmed on the whole workload
+CONFIRM = {"uneven_fp32_ff": lambda: __import__("workloads").uneven_batch(0, n=1024)}
 
 
 def main(argv=None):
@@ -341,8 +382,20 @@ def main(argv=None):
         singles = name in SINGLES
         best, ms, log = tune(frames, reps=args.reps, singles=singles)
         record(cache, frames, best, ms, singles=singles)
-        cache.setdefault("_workloads", {})[name] = {"schedule": asdict(best), "ms": ms,
-                                                    "candidates": len(log)}
+        entry = {"schedule": asdict(best), "ms": ms, "candidates": len(log)}
+        if name in CONFIRM:
+            whole = CONFIRM[name]()
+            subset_best = best
+            best, ms_whole, timings = confirm(whole, log)
+            entry = {"schedule": asdict(best), "ms": ms_whole, "candidates": len(log),
+                     "searched_on_frames": len(frames), "confirmed_on_frames": len(whole),
+                     "subset_winner": asdict(subset_best),
+                     "subset_winner_ms_whole": min(t for d, t in timings
+                                                   if jr.Schedule(**d) == subset_best),
+                     "confirmed": [[d, t] for d, t in timings]}
+            print("%-22s confirmed on %d frames: %9.4f ms  %s" % (name, len(whole), ms_whole,
+                                                                  best), flush=True)
+        cache.setdefault("_workloads", {})[name] = entry
         print("%-22s %9.4f ms  %s" % (name, ms, best), flush=True)
         save_cache(cache, args.out)
 

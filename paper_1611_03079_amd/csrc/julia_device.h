@@ -10,7 +10,9 @@ namespace jr {
 enum { kFP64 = 0, kFP32 = 1, kFF = 2 };
 enum { kModeJulia = 0, kModeMandelbrot = 1 };
 
-// One frame of the device frame table (112 bytes).  Built on the host from a
+enum { kMapPoly = 0, kMapRational = 1 };
+
+// One frame of the device frame table (144 bytes).  Built on the host from a
 // jr_frame: the mapping scalars hx, hy, cx, cy are computed there in binary64
 // with the same expressions as in the header's pixel-centre formula.
 struct alignas(16) DevFrame {
@@ -18,17 +20,20 @@ struct alignas(16) DevFrame {
     double cx, cy, hx, hy;   // pixel-centre mapping
     int64_t out_offset;      // element offset of pixel (0, 0) in the arena
     int64_t tile_begin;      // global index of this frame's first tile
+    double lr, li;           // lambda of the rational map (kMapRational)
     int32_t width, height;
     int32_t max_iter;
     int32_t dtype;           // kFP64 / kFP32 / kFF
     int32_t mode;            // kModeJulia / kModeMandelbrot
-    int32_t defer;           // 1: escape absorbing over the whole frame (|C| <= 1.9)
+    int32_t defer;           // 1: escape absorbing over the whole frame
     int32_t row_begin, row_end;
     int32_t tiles_x;         // tiles per tile row of this frame
     int32_t tile_w, tile_h;
     int32_t degree;          // map Z^degree + C (2: the quadratic map)
+    int32_t map;             // kMapPoly, or kMapRational: Z^degree + C + lambda / Z^degree
+    int32_t reserved[3];
 };
-static_assert(sizeof(DevFrame) == 112, "DevFrame layout");
+static_assert(sizeof(DevFrame) == 144, "DevFrame layout");
 
 // Work queues of the persistent kernel.  Same-address device-scope atomics
 // serialise (about 12 ns each on MI355X), so the tile counter is split into
@@ -78,6 +83,9 @@ constexpr int kOneWavePalette = 256;
 constexpr int kColorBit = 8;
 // Kernel variants that also hold the general maps Z^d + C (d = 3..8).
 constexpr int kGeneralBit = 16;
+// Kernel variants (rows and plain kernels only) that also hold the rational
+// maps Z^d + C + lambda / Z^d; they carry kGeneralBit too.
+constexpr int kRationalBit = 32;
 
 struct PlainArgs {
     int32_t* out;
@@ -89,7 +97,7 @@ struct PlainArgs {
 // counters and the frame table in one fixed device array of the library, the
 // counters first (kCounterBytes), then room for kNoAllocMaxFrames frames.
 constexpr int kNoAllocMaxFrames = 1024;
-constexpr int kPutFrames = 32;  // frame records per jr_put_frames launch
+constexpr int kPutFrames = 24;  // frame records per jr_put_frames launch (kernel arguments <= 4 KiB)
 constexpr size_t kNoAllocScratchBytes = kCounterBytes + (size_t)kNoAllocMaxFrames * sizeof(DevFrame);
 // Device address of that array on the current device (looked up once per
 // device; `dev` is the current device's index, 0 <= dev < 64).

@@ -145,6 +145,16 @@ int check_frames(const jr_frame* frames, int32_t n, int64_t capacity) {
             return fail(JR_EINVAL, "%s: rows [%d, %d) outside [0, %d)", who, f.row_begin, rend, f.height);
         if (f.degree != 0 && (f.degree < 2 || f.degree > kMaxDegree))
             return fail(JR_EINVAL, "%s: degree %d not 0 or 2..%d", who, f.degree, kMaxDegree);
+        if (f.map != JR_MAP_POLY && f.map != JR_MAP_RATIONAL)
+            return fail(JR_EINVAL, "%s: unknown map %d", who, f.map);
+        if (f.map == JR_MAP_RATIONAL) {
+            if (f.mode != JR_JULIA)
+                return fail(JR_EINVAL, "%s: rational maps render Julia images only", who);
+            if (f.dtype == JR_FF)
+                return fail(JR_EINVAL, "%s: rational maps run in FP64 or FP32", who);
+            if (!finite(f.lambda.re) || !finite(f.lambda.im))
+                return fail(JR_EINVAL, "%s: lambda must be finite", who);
+        }
         if (f.out_offset < 0) return fail(JR_EINVAL, "%s: out_offset must be >= 0", who);
         const int64_t px = (int64_t)f.width * f.height;
         if (f.out_offset > capacity - px)
@@ -218,12 +228,22 @@ double dtype_cost(int dtype) {
 double frame_cost(const jr_frame& f) {
     const int32_t rend = f.row_end == 0 ? f.height : f.row_end;
     const double px = (double)f.width * (double)(rend - f.row_begin);
-    // a general map's iteration costs about degree - 1 complex products
-    const double deg = f.degree > 2 ? (double)(f.degree - 1) : 1.0;
+    // a general map's iteration costs about degree - 1 complex products; the
+    // rational term adds |W|^2, lambda conj(W) and two divisions
+    double deg = f.degree > 2 ? (double)(f.degree - 1) : 1.0;
+    if (f.map == JR_MAP_RATIONAL) deg += 3.0;
     return px * (4.0 + std::min<double>(f.max_iter, 256.0)) * dtype_cost(f.dtype) * deg;
 }
 
 bool absorbing(const jr_frame& f) {
+    if (f.map == JR_MAP_RATIONAL) {
+        // |Z| > 2 gives |W| = |Z|^d > 2^d and |W + C + lambda / W| >=
+        // |W| - |C| - |lambda| / |W| > 2^d - |C| - |lambda| / 2^d, which
+        // stays above 2 (margin 0.1) under this condition
+        const double p = std::ldexp(1.0, f.degree == 0 ? 2 : f.degree);
+        return std::hypot(f.c.re, f.c.im) + std::hypot(f.lambda.re, f.lambda.im) / p <=
+               p - 2.1;
+    }
     if (f.mode == JR_JULIA) return std::hypot(f.c.re, f.c.im) <= kAbsorbingC;
     // Mandelbrot: C ranges over the window; its largest modulus is at a corner.
     const double xs[2] = {f.w.re_min, f.w.re_max}, ys[2] = {f.w.im_min, f.w.im_max};
@@ -294,6 +314,9 @@ int64_t fill_frame(const jr_frame& f, const jr_schedule& s, int64_t tile_begin, 
     d.mode = f.mode;
     d.defer = absorbing(f) ? 1 : 0;
     d.degree = f.degree == 0 ? 2 : f.degree;
+    d.map = f.map;
+    d.lr = f.map == JR_MAP_RATIONAL ? f.lambda.re : 0.0;
+    d.li = f.map == JR_MAP_RATIONAL ? f.lambda.im : 0.0;
     d.row_begin = f.row_begin;
     d.row_end = f.row_end == 0 ? f.height : f.row_end;
     const int32_t tw = s.kernel == JR_KERNEL_PLAIN ? 16 : s.tile_w;
@@ -325,6 +348,20 @@ void account(TableStats& t, const jr_frame& f, const DevFrame& d, int64_t tiles)
     t.max_tile_cost = std::max(t.max_tile_cost, frame_cost(f) / (double)tiles);
     t.dtmask |= 1 << f.dtype;
     if (d.degree > 2) t.dtmask |= jr::kGeneralBit;
+    if (d.map == jr::kMapRational) t.dtmask |= jr::kGeneralBit | jr::kRationalBit;
+}
+
+// Launches holding rational frames run the rows kernel (or the plain kernel):
+// a schedule that asks for the tiled or hybrid stream is carried over to the
+// rows kernel with the same tiles, scheduling mode and refill threshold.
+void route_rational(const TableStats& t, jr_schedule& s) {
+    if (!(t.dtmask & jr::kRationalBit)) return;
+    if (s.kernel != JR_KERNEL_TILED && s.kernel != JR_KERNEL_HYBRID) return;
+    s.kernel = JR_KERNEL_ROWS;
+    s.unroll = s.unroll >= 8 ? 8 : 4;
+    s.defer = 0;
+    s.bail = 8;
+    s.handoff = 0;
 }
 
 // Fills rows[0, n) in launch order and returns the table's totals; idx is
@@ -473,6 +510,7 @@ int enqueue_batch(const jr_frame* frames, int32_t n, int32_t* out_base, int64_t 
     if ((rc = current_device(&dev, &info))) return rc;
     Table t;
     build_table(frames, n, s, t);
+    route_rational(t, s);
     const int blocks = grid_blocks(info, s, t.total_tiles);
     const bool queues = s.persistent && s.kernel != JR_KERNEL_PLAIN;
     if (n == 1 && !queues) {
@@ -574,6 +612,7 @@ int enqueue_batch_noalloc(const jr_frame* frames, int32_t n, int32_t* out_base, 
     std::lock_guard<std::mutex> g(g_na_mu);
     TableStats t;
     build_rows(frames, n, s, g_na_rows, g_na_idx, t);
+    route_rational(t, s);
     const int blocks = grid_blocks(info, s, t.total_tiles);
     jr::PersistentArgs args = make_args(t, n == 1 ? nullptr : table, out_base, ctr, n, blocks, s);
     if (n == 1) {
@@ -812,6 +851,7 @@ int jr_plan_create(const jr_frame* frames, int32_t n, int32_t* out_base, int64_t
     if ((rc = current_device(&dev, &info))) return rc;
     Table t;
     build_table(frames, n, s, t);
+    route_rational(t, s);
     jr_plan* p = new jr_plan();
     p->dev = dev;
     p->total_tiles = t.total_tiles;

@@ -49,6 +49,7 @@ namespace jr {
 // check_step() (tests the current Z, then advances it, sharing the squares).
 // ---------------------------------------------------------------------------
 struct ArF64 {
+    static constexpr bool kRational = false;
     struct Z { double x, y; };
     struct C { double r, i; };
     using V = double;  // one coordinate
@@ -89,6 +90,7 @@ struct ArF64 {
 // x' = fma(-y, y, t), y' = fma(x + x, y, ci): the test shares t with the
 // update, 7 vector instructions per tested iteration with the count.
 struct ArF32 {
+    static constexpr bool kRational = false;
     struct Z { float x, y; };
     struct C { float r, i, lim; };
     using V = float;
@@ -123,6 +125,7 @@ struct ArF32 {
 // (ACM TOMS 2017): accurate double-word + double-word (error < 3u^2) and
 // FMA double-word x double-word (error < 4u^2), u = 2^-24.
 struct ArFF {
+    static constexpr bool kRational = false;
     struct D { float hi, lo; };
     struct Z { D x, y; };
     struct C { D r, i; };
@@ -287,6 +290,102 @@ struct ArFFG : ArFF {
     }
 };
 
+// Rational maps with two parameters: Z' = W + C + lambda / W, W = Z^d (d =
+// 2..8, formed as for the general maps), lambda / W = (lambda conj W) / |W|^2
+// with every product, sum and quotient rounded (IEEE division, no fused
+// operations).  A pixel escapes unless |Z|^2 <= 4: the iterate after a hit on
+// the pole Z = 0 is 0/0, not a number, and counts as escaped.  Julia images in
+// FP64 and FP32; the constant carries lambda beside C.
+template <class T>
+struct RationalOps {
+    __device__ static void map(T& x, T& y, T cr, T ci, T lr, T li, int d) {
+        T wr = x, wi = y;
+#pragma unroll 1
+        for (int k = 1; k < d; ++k) {
+            T p_rr = wr * x;
+            T p_ii = wi * y;
+            T p_ri = wr * y;
+            T p_ir = wi * x;
+            T nr = p_rr - p_ii;
+            T ni = p_ri + p_ir;
+            wr = nr;
+            wi = ni;
+        }
+        T q_r = wr * wr;
+        T q_i = wi * wi;
+        T q = q_r + q_i;
+        T a = lr * wr;
+        T b = li * wi;
+        T e = li * wr;
+        T f = lr * wi;
+        T num_r = a + b;
+        T num_i = e - f;
+        T tr = num_r / q;
+        T ti = num_i / q;
+        T sr = wr + cr;
+        T si = wi + ci;
+        x = sr + tr;
+        y = si + ti;
+    }
+};
+
+struct ArF64R : ArF64 {
+    static constexpr bool kRational = true;
+    struct C { double r, i, lr, li; };
+    __device__ static C cmake(V r, V i) { return C{r, i, 0.0, 0.0}; }
+    __device__ static C cmake_rational(V r, V i, V lr, V li) { return C{r, i, lr, li}; }
+    __device__ static bool inside(const Z& z, const C&, int) {
+        double x2 = z.x * z.x;
+        double y2 = z.y * z.y;
+        return x2 + y2 <= 4.0;
+    }
+    __device__ static void step(Z& z, const C& c, int d) {
+        RationalOps<double>::map(z.x, z.y, c.r, c.i, c.lr, c.li, d);
+    }
+    __device__ static bool check_step(Z& z, const C& c, int d) {
+        bool ok = inside(z, c, d);
+        step(z, c, d);
+        return ok;
+    }
+};
+
+struct ArF32R : ArF32 {
+    static constexpr bool kRational = true;
+    struct C { float r, i, lr, li; };
+    __device__ static C cmake(V r, V i) { return C{r, i, 0.0f, 0.0f}; }
+    __device__ static C cmake_rational(V r, V i, V lr, V li) { return C{r, i, lr, li}; }
+    __device__ static bool inside(const Z& z, const C&, int) {
+        float x2 = z.x * z.x;
+        float y2 = z.y * z.y;
+        return x2 + y2 <= 4.0f;
+    }
+    __device__ static void step(Z& z, const C& c, int d) {
+        RationalOps<float>::map(z.x, z.y, c.r, c.i, c.lr, c.li, d);
+    }
+    __device__ static bool check_step(Z& z, const C& c, int d) {
+        bool ok = inside(z, c, d);
+        step(z, c, d);
+        return ok;
+    }
+};
+
+// p ? a : b for an iterate, one 32-bit word at a time.  Written on the whole
+// struct, the select of a 16-byte iterate (FP64, float-float) became a select
+// between two stack slots and a load from per-lane stack memory.
+template <class T>
+__device__ __forceinline__ T select_words(bool p, const T& a, const T& b) {
+    constexpr int W = (int)(sizeof(T) / 4);
+    static_assert(sizeof(T) % 4 == 0, "whole words");
+    uint32_t wa[W], wb[W];
+    __builtin_memcpy(wa, &a, sizeof(T));
+    __builtin_memcpy(wb, &b, sizeof(T));
+#pragma unroll
+    for (int j = 0; j < W; ++j) wa[j] = p ? wa[j] : wb[j];
+    T r;
+    __builtin_memcpy(&r, wa, sizeof(T));
+    return r;
+}
+
 // Pixel centre in binary64: cx + (2i + 1 - W) hx, cy - (2j + 1 - H) hy.  The
 // odd integer is formed exactly in binary64 (|values| < 2^33).
 __device__ __forceinline__ double pixel_re(double cx, double hx, int i, int W) {
@@ -321,8 +420,8 @@ __device__ __forceinline__ void stage_palette(const PersistentArgs& a) {
 }
 
 // The 32 bits a pixel stores: its count, or (COLOR) its colour.
-template <int COLOR>
-__device__ __forceinline__ int32_t shade(const PersistentArgs& a, int cnt) {
+template <int COLOR, class Args>
+__device__ __forceinline__ int32_t shade(const Args& a, int cnt) {
     if (!COLOR) return cnt;
     return (int32_t)palette_lds()[min(cnt, a.palette_len - 1)];
 }
@@ -446,6 +545,16 @@ __device__ __forceinline__ int64_t next_tile(Claimer& cl, const PersistentArgs& 
 // might alias the output.
 typedef const __attribute__((address_space(4))) DevFrame CFrame;
 typedef const __attribute__((address_space(4))) char CByte;
+
+// A frame's constant in the arithmetic A (C, and lambda for the rational maps).
+template <class A>
+__device__ __forceinline__ typename A::C frame_c(CFrame& F) {
+    if constexpr (A::kRational)
+        return A::cmake_rational(A::coord(F.cr), A::coord(F.ci), A::coord(F.lr),
+                                 A::coord(F.li));
+    else
+        return A::cmake(A::coord(F.cr), A::coord(F.ci));
+}
 
 // The frame table of a launch: the device table, or for a one-frame launch
 // the copy inside the kernel arguments (the single by-value PersistentArgs
@@ -630,7 +739,7 @@ __device__ void run_stream(Src& s, Claimer& cl, const PersistentArgs& a, double&
             if (running == 0) return;
         }
         if (DEFER) {
-            zs = pe ? zs : z;  // a lane waiting for its replay keeps its block start
+            zs = select_words(pe, zs, z);  // a lane waiting for its replay keeps its block start
 #pragma unroll
             for (int u = 0; u < K; ++u) A::step(z, c, deg);
             const bool esc = !A::inside(z, c, deg);
@@ -834,7 +943,7 @@ __device__ void run_hybrid(Src& s, Claimer& cl, const PersistentArgs& a, double&
                 }
             }
             if (DEFER) {
-                zs = pe ? zs : z;
+                zs = select_words(pe, zs, z);
 #pragma unroll
                 for (int u = 0; u < K; ++u) A::step(z, c, deg);
                 const bool esc = !A::inside(z, c, deg);
@@ -936,7 +1045,7 @@ __device__ __forceinline__ void plain_pixel(const PersistentArgs& a, CFrame& F, 
         c = A::cmake(A::coord(px), A::coord(py));
     } else {
         z = A::make(A::coord(px), A::coord(py));
-        c = A::cmake(A::coord(F.cr), A::coord(F.ci));
+        c = frame_c<A>(F);
     }
     int n = 0;
     while (n < F.max_iter) {
@@ -967,7 +1076,12 @@ __global__ __launch_bounds__(256) void jr_plain_batch(PersistentArgs a) {
     const int j = F.row_begin + ty * F.tile_h + (int)(threadIdx.x >> 4);
     if (i >= F.width || j >= F.row_end) return;
     int32_t* out = a.out_base + F.out_offset;
-    if ((DTMASK & kGeneralBit) && F.degree > 2) {
+    if ((DTMASK & kRationalBit) && F.map == kMapRational) {
+        if (F.dtype == kFP32)
+            plain_pixel<ArF32R, COLOR>(a, F, i, j, out);
+        else
+            plain_pixel<ArF64R, COLOR>(a, F, i, j, out);
+    } else if ((DTMASK & kGeneralBit) && F.degree > 2) {
         if (F.dtype == kFP32)
             plain_pixel<ArF32G, COLOR>(a, F, i, j, out);
         else if (F.dtype == kFP64)
@@ -1065,8 +1179,18 @@ __device__ __forceinline__ typename A::Z list_get(const uint32_t* list, int cap,
 // holds `cap` entries; word W of entry e's iterate is list[W * cap + e], and
 // its position (row << 6 | column) is the 16-bit element e of the array that
 // follows the iterate words.
+// The kernel's arguments read in place, in the kernel-argument segment (the
+// single by-value PersistentArgs argument sits at offset 0).  A function that
+// is not inlined and takes the by-value argument by reference gets a copy of
+// it in per-lane stack memory; through this reference it reads the arguments
+// with scalar loads instead.
+typedef const __attribute__((address_space(4))) PersistentArgs CArgs;
+__device__ __forceinline__ CArgs& kernel_args() {
+    return *(CArgs*)__builtin_amdgcn_kernarg_segment_ptr();
+}
+
 template <class A, int K, int MANDEL, int COLOR, int LROWS>
-__device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, uint32_t* list) {
+__device__ void rows_tile(CArgs& a, CFrame& F, int64_t t, int P, uint32_t* list) {
     constexpr int cap = 64 * LROWS;  // list entries
     using V = typename A::V;
     constexpr int ZW = (int)(sizeof(typename A::Z) / 4);
@@ -1084,7 +1208,7 @@ __device__ void rows_tile(const PersistentArgs& a, CFrame& F, int64_t t, int P, 
     const V zero = A::coord(0.0);
     const V xl = A::coord(pixel_re(F.cx, F.hx, col0 + min(lane, tw - 1), W));
     const V yl = A::coord(pixel_im(F.cy, F.hy, row0 + min(lane, th - 1), F.height));
-    const typename A::C cj = A::cmake(A::coord(F.cr), A::coord(F.ci));
+    const typename A::C cj = frame_c<A>(F);
     int32_t* tout = a.out_base + F.out_offset + ((int64_t)row0 * W + col0);
     const bool col_ok = lane < tw;
     const uint64_t cols = tw >= 64 ? ~0ull : ((1ull << tw) - 1ull);  // lanes inside the tile
@@ -1295,6 +1419,7 @@ __global__ __launch_bounds__(64 * WPB) void jr_rows(PersistentArgs a) {
     Claimer cl;
     claimer_init(cl, a);
     CFrame* frames = cframes(a);
+    CArgs& ka = kernel_args();
     int f = 0;
     for (int64_t t = next_tile(cl, a); t >= 0; t = next_tile(cl, a)) {
         f = find_frame(frames, a.nframes, t, f);
@@ -1309,12 +1434,23 @@ __global__ __launch_bounds__(64 * WPB) void jr_rows(PersistentArgs a) {
         const bool mandel = F.mode == kModeMandelbrot;
 #define JR_ROWS(A_)                                                                      \
     do {                                                                                 \
-        if (abs && !mandel) rows_tile<A_, K, 0, COLOR, S::rows>(a, F, t, P, list);  \
-        else if (abs) rows_tile<A_, K, 1, COLOR, S::rows>(a, F, t, P, list);        \
-        else if (!mandel) rows_tile<A_, 1, 0, COLOR, S::rows>(a, F, t, P, list);    \
-        else rows_tile<A_, 1, 1, COLOR, S::rows>(a, F, t, P, list);                 \
+        if (abs && !mandel) rows_tile<A_, K, 0, COLOR, S::rows>(ka, F, t, P, list); \
+        else if (abs) rows_tile<A_, K, 1, COLOR, S::rows>(ka, F, t, P, list);       \
+        else if (!mandel) rows_tile<A_, 1, 0, COLOR, S::rows>(ka, F, t, P, list);   \
+        else rows_tile<A_, 1, 1, COLOR, S::rows>(ka, F, t, P, list);                \
     } while (0)
-        if ((DTMASK & kGeneralBit) && F.degree > 2) {
+        // rational maps: Julia images in FP64 or FP32 (the host checks)
+#define JR_ROWS_R(A_)                                                              \
+    do {                                                                           \
+        if (abs) rows_tile<A_, K, 0, COLOR, S::rows>(ka, F, t, P, list);          \
+        else rows_tile<A_, 1, 0, COLOR, S::rows>(ka, F, t, P, list);              \
+    } while (0)
+        if ((DTMASK & kRationalBit) && F.map == kMapRational) {
+            if (F.dtype == kFP32)
+                JR_ROWS_R(ArF32R);
+            else
+                JR_ROWS_R(ArF64R);
+        } else if ((DTMASK & kGeneralBit) && F.degree > 2) {
             if (F.dtype == kFP32)
                 JR_ROWS(ArF32G);
             else if (F.dtype == kFP64)
@@ -1328,6 +1464,7 @@ __global__ __launch_bounds__(64 * WPB) void jr_rows(PersistentArgs a) {
         else if ((DTMASK & (1 << kFF)) && F.dtype == kFF)
             JR_ROWS(ArFF);
 #undef JR_ROWS
+#undef JR_ROWS_R
     }
 }
 
@@ -1378,6 +1515,7 @@ using TiledFn = void (*)(PersistentArgs);
 
 template <int K, int DEFER, int HYB>
 static TiledFn pick_mask(int dtmask) {
+    if (dtmask & kRationalBit) return nullptr;  // the host runs these on the rows kernel
     if (dtmask & kGeneralBit)  // general maps: every dtype, refill stream
         return (dtmask & kColorBit) ? jr_tiled<K, DEFER, 7 | kGeneralBit | kColorBit, 0>
                                     : jr_tiled<K, DEFER, 7 | kGeneralBit, 0>;
@@ -1419,6 +1557,11 @@ static TiledFn pick_block(int unroll, int defer, int dtmask) {
 
 template <int K>
 static TiledFn pick_rows_mask(int dtmask, bool one_wave) {
+    constexpr int kGR = 7 | kGeneralBit | kRationalBit;
+    if (dtmask & kRationalBit) {
+        if (dtmask & kColorBit) return jr_rows<K, kGR | kColorBit, 4>;
+        return one_wave ? jr_rows<K, kGR, 1> : jr_rows<K, kGR, 4>;
+    }
     if (one_wave && dtmask == ((1 << kFP32) | kColorBit))
         return jr_rows<K, (1 << kFP32) | kColorBit, 1>;
     if (one_wave && !(dtmask & kColorBit)) {
@@ -1455,6 +1598,9 @@ static TiledFn pick(int unroll, int defer, int dtmask, int hybrid) {
 }
 
 static TiledFn pick_plain(int dtmask) {
+    if (dtmask & kRationalBit)
+        return (dtmask & kColorBit) ? jr_plain_batch<7 | kGeneralBit | kRationalBit | kColorBit>
+                                    : jr_plain_batch<7 | kGeneralBit | kRationalBit>;
     if (dtmask & kGeneralBit)
         return (dtmask & kColorBit) ? jr_plain_batch<7 | kGeneralBit | kColorBit>
                                     : jr_plain_batch<7 | kGeneralBit>;

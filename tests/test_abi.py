@@ -203,6 +203,24 @@ def test_noalloc_batch_rejects_before_device():
     assert call(arr, 2, FAKE_OUT, 32, ctypes.byref(bad), None) == jr.JR_EINVAL
 
 
+def test_rational_frames_are_validated_before_device():
+    """Rational maps: Julia mode, FP64 or FP32, finite lambda, a known map."""
+    from workloads import Frame
+    good = Frame(0.3 + 0.2j, (-1.5, 1.5, -1.5, 1.5), 8, 8, 50, "fp32", "julia", 2, 0.01 + 0j)
+    bad = [Frame(0j, good.window, 8, 8, 50, "fp32", "mandelbrot", 2, 0.01 + 0j),
+           Frame(good.c, good.window, 8, 8, 50, "ff", "julia", 2, 0.01 + 0j),
+           Frame(good.c, good.window, 8, 8, 50, "fp64", "julia", 2, complex(math.nan, 0)),
+           Frame(good.c, good.window, 8, 8, 50, "fp64", "julia", 9, 0.01 + 0j)]
+    assert jr.check_frames([good], [0], 64) == jr.JR_OK
+    for f in bad:
+        assert jr.check_frames([f], [0], 64) == jr.JR_EINVAL, f
+        assert jr.last_error()
+    arr = jr._frames_array([good], [0])
+    arr[0].map = 2
+    assert jr.lib.jr_check_frames(arr, 1, 64) == jr.JR_EINVAL
+    assert "unknown map" in jr.last_error()
+
+
 def test_valid_call_without_gpu_reports_no_device():
     import torch
     if torch.cuda.is_available():

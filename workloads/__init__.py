@@ -62,6 +62,7 @@ class Frame:
     dtype: str = "fp64"        # "fp64" | "fp32" | "ff"
     mode: str = "julia"        # "julia" | "mandelbrot"
     degree: int = 2            # map Z^degree + C
+    lam: Optional[complex] = None  # set: the rational map Z^degree + C + lam / Z^degree
 
     @property
     def pixels(self) -> int:
