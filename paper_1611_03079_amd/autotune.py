@@ -380,7 +380,8 @@ def main(argv=None):
         if args.only and name not in args.only:
             continue
         singles = name in SINGLES
-        best, ms, log = tune(frames, reps=args.reps, singles=singles)
+        print("autotune: %s (%d frames)" % (name, len(frames)), flush=True)
+        best, ms, log = tune(frames, reps=args.reps, singles=singles, verbose=True)
         record(cache, frames, best, ms, singles=singles)
         entry = {"schedule": asdict(best), "ms": ms, "candidates": len(log)}
         if name in CONFIRM:
