@@ -55,14 +55,16 @@ def kernel_source_sha256():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic(kernel: str, workload: str):
-    """HBM bytes per launch of `kernel` on `workload` from the rocprofv3
-    FETCH_SIZE / WRITE_SIZE summaries in profiles/: a summary states
-        traffic_bytes_per_launch: <workload> | <kernel> | <bytes>
+def measured_traffic(kernel: str, workload: str, schedule: dict):
+    """HBM bytes per launch of `kernel` on `workload` under `schedule` from
+    the rocprofv3 FETCH_SIZE / WRITE_SIZE summaries in profiles/: a summary
+    states
+        traffic_bytes_per_launch: <workload> | <kernel> | <schedule json> | <bytes>
         kernel_source_sha256: <hash of julia_kernels.hip the counters ran on>
-    Returns (bytes, file) when a summary matches the kernel, the workload and
-    the current kernel source; (None, reason) otherwise, so that a kernel
-    changed since its counters were taken reports no traffic."""
+    Returns (bytes, file) when a summary matches the kernel, the workload, the
+    schedule and the current kernel source; (None, reason) otherwise, so that
+    a kernel or schedule changed since its counters were taken reports no
+    traffic."""
     if not os.path.isdir(PROFILES):
         return None, "no profiles/ folder"
     now = kernel_source_sha256()
@@ -75,8 +77,11 @@ def measured_traffic(kernel: str, workload: str):
                     entries.append([x.strip() for x in line.split(":", 1)[1].split("|")])
                 elif line.startswith("kernel_source_sha256:"):
                     sha = line.split(":", 1)[1].strip()
-        for wl_name, kern, nbytes in entries:
-            if wl_name == workload and kern == kernel:
+        for e in entries:
+            if len(e) != 4:
+                continue
+            wl_name, kern, sched_json, nbytes = e
+            if wl_name == workload and kern == kernel and json.loads(sched_json) == schedule:
                 if sha == now:
                     return int(nbytes), "profiles/" + name
                 stale = "profiles/%s was taken on another kernel source" % name
@@ -109,6 +114,15 @@ def parse():
                    help="headline schedule: the autotuned one (default), the batched "
                         "one-thread-per-pixel kernel, or the refill stream (64x64 tiles, "
                         "counted blocks of 8), for profiling comparisons")
+    p.add_argument("--leg", choices=("headline", "single_4096_fp64", "single_4096_fp32",
+                                      "parameter_path_fp64", "parameter_path_ff"),
+                   default="headline",
+                   help="run one workload alone (for profiling): the 8 single 4096^2 "
+                        "images (seeds 0..3, caps 100 and 1000) rendered one call each, "
+                        "tuned or with --plain; or a parameter path in FP64 / float-float "
+                        "in one launch per step (autotuned schedule, or --plain)")
+    p.add_argument("--plain", action="store_true",
+                   help="with --leg: the one-thread-per-pixel comparator kernel")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run an elementwise device copy of 1 GiB (read 1 GiB, write 1 GiB) "
                         "whose FETCH_SIZE / WRITE_SIZE counters calibrate the traffic figures")
@@ -176,6 +190,23 @@ def serving_sweep(args, torch, wl):
                 break   # higher rates only queue longer
         out["%s_highest_rate_kept_up" % pname] = sat
     return out
+
+
+SETTLE_S = 0.5
+
+
+def settle_clocks(torch, plan, seconds=SETTLE_S):
+    """Replays the step, untimed, for `seconds` before the warm-up steps.  The
+    GPU raises its clock over the first tens of milliseconds of sustained
+    load (a profile of 23 back-to-back launches ran 1.26 ms at first and
+    0.92 ms at the end), so without this the timed steps would measure the
+    ramp.  Returns the settle time in ms."""
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(20):
+            plan.replay()
+        torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3
 
 
 def time_plan_steps(torch, plan, steps, warmup, graph=True):
@@ -471,6 +502,33 @@ def extra_legs(args, torch, jr, wl, frames, sched, ms_headline, iters):
     return ex
 
 
+def run_leg(args, torch, jr, wl):
+    """One workload alone, for profiling: `steps` timed repetitions after
+    `warmup`; prints one JSON line with its rate."""
+    if args.leg.startswith("single_4096"):
+        dt = args.leg.rsplit("_", 1)[1]
+        fr = [wl.single_4096(s, it, dt) for it in (100, 1000) for s in range(4)]
+        outs = [torch.empty((f.height, f.width), dtype=torch.int32, device="cuda") for f in fr]
+        time_renders(jr, torch, fr, outs, args.warmup, plain=args.plain)
+        ms = time_renders(jr, torch, fr, outs, args.steps, plain=args.plain)
+        iters = count_sum(torch, outs)
+        sched = "plain" if args.plain else "per-image schedules from the autotune cache"
+    else:
+        dt = args.leg.rsplit("_", 1)[1]
+        fr = wl.parameter_path(dtype=dt)
+        sc = jr.Schedule(kernel="plain") if args.plain else tuned_schedule_or_default(
+            jr, args.leg)[0]
+        plan = jr.Plan(fr, sc)
+        ms, _ = time_plan_steps(torch, plan, args.steps, args.warmup, graph=False)
+        iters = count_sum(torch, plan.views)
+        plan.close()
+        sched = sc.__dict__ if sc else "library default"
+    print(json.dumps({"leg": args.leg, "plain": args.plain, "ms_per_step": round(ms, 4),
+                      "gpixel_iter_s": round(iters / (ms * 1e-3) / 1e9, 2),
+                      "pixel_iters": iters, "schedule": sched, "steps": args.steps}),
+          flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -490,6 +548,9 @@ def main():
             torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
+    if args.leg != "headline":
+        run_leg(args, torch, jr, wl)
+        return
     frames = wl.parameter_path()
     if args.schedule == "plain":
         sched, sched_src = jr.Schedule(kernel="plain"), "--schedule plain"
@@ -499,12 +560,14 @@ def main():
         sched, sched_src = tuned_schedule(jr, "parameter_path_fp32", frames)
     plan = jr.Plan(frames, sched)
     plan.capture()
+    settle_ms = settle_clocks(torch, plan)
     ms_step, kernel_ms = time_plan_steps(torch, plan, args.steps, args.warmup, graph=True)
     iters = count_sum(torch, plan.views)
     info = plan.info()
     plan.close()
     pixels = sum(f.pixels for f in frames)
-    traffic, traffic_src = measured_traffic(kernel_instance(sched), "parameter_path_fp32")
+    traffic, traffic_src = measured_traffic(kernel_instance(sched), "parameter_path_fp32",
+                                            sched.__dict__)
     value = iters / (ms_step * 1e-3) / 1e9
     store_gbs = BYTES_PER_PIXEL * pixels / (kernel_ms * 1e-3) / 1e9
     alu_tflops = FLOP_PER_ITER * iters / (kernel_ms * 1e-3) / 1e12
@@ -526,6 +589,7 @@ def main():
                                "per step (hipGraph replay) with the schedule below",
                    "frames": len(frames), "pixels_per_step": pixels, "pixel_iters_per_step": iters,
                    "schedule": sched.__dict__, "schedule_source": sched_src,
+                   "clock_settle_ms": round(settle_ms, 1),
                    "tiles": info["tiles"], "workgroups": info["workgroups"]},
         "roofline": {"bound": "hbm", "achieved": round(store_gbs, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(store_gbs / PEAK_HBM_GBS, 4),

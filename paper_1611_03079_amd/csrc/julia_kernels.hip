@@ -1183,14 +1183,18 @@ __device__ __forceinline__ typename A::Z list_get(const uint32_t* list, int cap,
 // single by-value PersistentArgs argument sits at offset 0).  A function that
 // is not inlined and takes the by-value argument by reference gets a copy of
 // it in per-lane stack memory; through this reference it reads the arguments
-// with scalar loads instead.
+// with scalar loads instead.  The general and rational maps' tiles, which
+// are not inlined, take this; the quadratic maps' tiles are inlined and take
+// the by-value argument, which keeps the hot loop's registers as they were
+// (the kernel-argument reference there cost 16 more vector registers and
+// about 10% of the parameter path's time).
 typedef const __attribute__((address_space(4))) PersistentArgs CArgs;
 __device__ __forceinline__ CArgs& kernel_args() {
     return *(CArgs*)__builtin_amdgcn_kernarg_segment_ptr();
 }
 
-template <class A, int K, int MANDEL, int COLOR, int LROWS>
-__device__ void rows_tile(CArgs& a, CFrame& F, int64_t t, int P, uint32_t* list) {
+template <class A, int K, int MANDEL, int COLOR, int LROWS, class Args>
+__device__ void rows_tile(const Args& a, CFrame& F, int64_t t, int P, uint32_t* list) {
     constexpr int cap = 64 * LROWS;  // list entries
     using V = typename A::V;
     constexpr int ZW = (int)(sizeof(typename A::Z) / 4);
@@ -1432,12 +1436,21 @@ __global__ __launch_bounds__(64 * WPB) void jr_rows(PersistentArgs a) {
         // may keep the trip count in a vector register.
         const int P = __builtin_amdgcn_readfirstlane(abs ? (a.bail + 3) & ~3 : 1);
         const bool mandel = F.mode == kModeMandelbrot;
-#define JR_ROWS(A_)                                                                      \
+#define JR_ROWS(A_, ARGS_)                                                               \
     do {                                                                                 \
-        if (abs && !mandel) rows_tile<A_, K, 0, COLOR, S::rows>(ka, F, t, P, list); \
-        else if (abs) rows_tile<A_, K, 1, COLOR, S::rows>(ka, F, t, P, list);       \
-        else if (!mandel) rows_tile<A_, 1, 0, COLOR, S::rows>(ka, F, t, P, list);   \
-        else rows_tile<A_, 1, 1, COLOR, S::rows>(ka, F, t, P, list);                \
+        if (abs && !mandel) rows_tile<A_, K, 0, COLOR, S::rows>(ARGS_, F, t, P, list); \
+        else if (abs) rows_tile<A_, K, 1, COLOR, S::rows>(ARGS_, F, t, P, list);       \
+        else if (!mandel) rows_tile<A_, 1, 0, COLOR, S::rows>(ARGS_, F, t, P, list);   \
+        else rows_tile<A_, 1, 1, COLOR, S::rows>(ARGS_, F, t, P, list);                \
+    } while (0)
+        // quadratic maps: kernels that also hold the general maps call tiles
+        // that are not inlined, which take the arguments in place
+#define JR_ROWS_Q(A_)                          \
+    do {                                       \
+        if constexpr ((DTMASK & kGeneralBit) != 0) \
+            JR_ROWS(A_, ka);                   \
+        else                                   \
+            JR_ROWS(A_, a);                    \
     } while (0)
         // rational maps: Julia images in FP64 or FP32 (the host checks)
 #define JR_ROWS_R(A_)                                                              \
@@ -1452,19 +1465,20 @@ __global__ __launch_bounds__(64 * WPB) void jr_rows(PersistentArgs a) {
                 JR_ROWS_R(ArF64R);
         } else if ((DTMASK & kGeneralBit) && F.degree > 2) {
             if (F.dtype == kFP32)
-                JR_ROWS(ArF32G);
+                JR_ROWS(ArF32G, ka);
             else if (F.dtype == kFP64)
-                JR_ROWS(ArF64G);
+                JR_ROWS(ArF64G, ka);
             else
-                JR_ROWS(ArFFG);
+                JR_ROWS(ArFFG, ka);
         } else if ((DTMASK & (1 << kFP32)) && F.dtype == kFP32)
-            JR_ROWS(ArF32);
+            JR_ROWS_Q(ArF32);
         else if ((DTMASK & (1 << kFP64)) && F.dtype == kFP64)
-            JR_ROWS(ArF64);
+            JR_ROWS_Q(ArF64);
         else if ((DTMASK & (1 << kFF)) && F.dtype == kFF)
-            JR_ROWS(ArFF);
+            JR_ROWS_Q(ArFF);
 #undef JR_ROWS
 #undef JR_ROWS_R
+#undef JR_ROWS_Q
     }
 }
 
