@@ -76,6 +76,8 @@ def _open(path):
     lib.jro_render_pixels_rational.argtypes = [i32, i32, d, d, d, d, d, d, d, d, i32, i32, i32,
                                                i64, p_i32, p_i32, p_i32]
     lib.jro_render_pixels_rational.restype = None
+    lib.jro_cardioid_constant.argtypes = [d, d, d, d, i32, p_d, p_d]
+    lib.jro_cardioid_constant.restype = None
     p_u32 = ctypes.POINTER(ctypes.c_uint32)
     lib.jro_colorize.argtypes = [p_i32, i64, p_u32, i32, p_u32]
     lib.jro_colorize.restype = None
@@ -230,3 +232,15 @@ def dw_mul(x, y):
 
 def dw_split(v):
     return _pair("jro_dw_split", float(v))
+
+
+def cardioid_constant(step, a0, da, k):
+    """The constant of frame k of a prescribed cardioid path (Section 3):
+    (2 u_k - u_k^2) / (a0 - da k) with u_k = step^k by square-and-multiply
+    (jro_cardioid_constant)."""
+    lib = _load()
+    step = complex(step)
+    cr, ci = ctypes.c_double(), ctypes.c_double()
+    lib.jro_cardioid_constant(step.real, step.imag, float(a0), float(da), int(k),
+                              ctypes.byref(cr), ctypes.byref(ci))
+    return complex(cr.value, ci.value)

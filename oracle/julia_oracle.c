@@ -493,6 +493,43 @@ void jro_render_pixels_rational(int32_t dtype, int32_t degree, double cr, double
 }
 
 /* ------------------------------------------------------------------------ */
+/* Prescribed parameter path (Section 3): constants on the cardioid          */
+/*   f(t) = ((2 cos t - cos 2t) / a, (2 sin t - sin 2t) / a) = (2u - u^2) / a, */
+/* u = e^{it}, with the cardioid growing along the path (a decreasing).      */
+/* Frame k: u_k = step^k (step = e^{i dt}) by square-and-multiply over the   */
+/* bits of k from the highest, a_k = a0 - da k, C_k = (2 u_k - u_k^2) / a_k; */
+/* every product, sum and quotient rounded to binary64, no fused operation.  */
+/* ------------------------------------------------------------------------ */
+static void cmul(double a, double b, double c, double d, double *re, double *im)
+{
+    double ac = a * c;
+    double bd = b * d;
+    double ad = a * d;
+    double bc = b * c;
+    *re = ac - bd;
+    *im = ad + bc;
+}
+
+void jro_cardioid_constant(double step_re, double step_im, double a0, double da, int32_t k,
+                           double *cr, double *ci)
+{
+    double pr = 1.0, pi = 0.0;
+    for (int32_t bit = 30; bit >= 0; bit--) {
+        cmul(pr, pi, pr, pi, &pr, &pi);
+        if ((k >> bit) & 1)
+            cmul(pr, pi, step_re, step_im, &pr, &pi);
+    }
+    double wr, wi;
+    cmul(pr, pi, pr, pi, &wr, &wi);        /* u^2 */
+    double dk = da * (double)k;
+    double a = a0 - dk;
+    double nr = 2.0 * pr - wr;
+    double ni = 2.0 * pi - wi;
+    *cr = nr / a;
+    *ci = ni / a;
+}
+
+/* ------------------------------------------------------------------------ */
 /* One orbit in the chosen formulation.                                      */
 /* ------------------------------------------------------------------------ */
 int32_t jro_count(int32_t dtype, double x0, double y0, double cr, double ci,

@@ -114,6 +114,19 @@ void jro_render_pixels_rational(int32_t dtype, int32_t degree, double cr, double
                                 int32_t max_iter, int64_t n, const int32_t *ii,
                                 const int32_t *jj, int32_t *out);
 
+/* Prescribed parameter path (Section 3): the constant of frame k on the
+ * cardioid f(t) = ((2 cos t - cos 2t) / a, (2 sin t - sin 2t) / a), which is
+ * (2u - u^2) / a for u = e^{it}, with a changing along the path:
+ *     u_k = step^k by square-and-multiply over the bits of k, highest first
+ *           (p = 1; for each bit: p = p*p, then p = p*step if the bit is set),
+ *     a_k = a0 - da * k,
+ *     C_k = (2 u_k - u_k*u_k) / a_k,
+ * every complex product (a + ib)(c + id) taken as (a*c - b*d) + i (a*d + b*c),
+ * and every product, sum and quotient rounded to binary64.  step = e^{i dt}
+ * is given (the caller forms it once); a decreasing a grows the cardioid. */
+void jro_cardioid_constant(double step_re, double step_im, double a0, double da, int32_t k,
+                           double *cr, double *ci);
+
 /* Colour levels from counts (Section 2: each pixel is given a colour level by
  * its iteration count): out[k] = palette[min(counts[k], palette_len - 1)],
  * for counts >= 0 and palette_len >= 1. */

@@ -78,6 +78,15 @@ MUTANTS = {
                             "double si = wi + ci;\n        x = sr + tr;\n        y = si;"),
     "rational_fp32_lambda_parts": ("float a = lr * wr;", "float a = li * wr;"),
     "rational_pixels_ij_swap": ("W, H, ii[k], jj[k], &x, &y);", "W, H, jj[k], ii[k], &x, &y);"),
+    # the prescribed cardioid path: 2u lost, a growing instead of shrinking,
+    # the conjugate step, the bits of k taken lowest first, u^2 with a sign
+    "cardioid_no_two": ("double nr = 2.0 * pr - wr;", "double nr = pr - wr;"),
+    "cardioid_a_plus": ("double a = a0 - dk;", "double a = a0 + dk;"),
+    "cardioid_conj_step": ("cmul(pr, pi, step_re, step_im, &pr, &pi);",
+                           "cmul(pr, pi, step_re, -step_im, &pr, &pi);"),
+    "cardioid_bit_order": ("for (int32_t bit = 30; bit >= 0; bit--) {\n        cmul(pr",
+                           "for (int32_t bit = 0; bit <= 30; bit++) {\n        cmul(pr"),
+    "cardioid_square_sign": ("    *re = ac - bd;\n    *im = ad + bc;", "    *re = ac + bd;\n    *im = ad + bc;"),
 }
 
 
@@ -112,6 +121,8 @@ def _battery():
                 (d, k)) for d, k in (("fp64", 2), ("fp32", 3))]
     checks += [("rational_pixels_fp64", pins.test_render_pixels_rational_matches_whole_images,
                 ("fp64",))]
+    checks += [("cardioid_exact", pins.test_cardioid_constants_exact_quarter_turns, ()),
+               ("cardioid_mp", pins.test_cardioid_constants_against_high_precision, ())]
     for name, fn, args in checks:
         try:
             fn(*args)

@@ -783,3 +783,64 @@ def test_render_pixels_rational_matches_whole_images(dtype):
     whole = oracle.render(c, win, W, H, cap, dtype, "julia", d, lam=lam)
     np.testing.assert_array_equal(got, whole[jj, ii])
     assert len(np.unique(got)) >= 5 and (got == cap).any()
+
+
+# -------------------------------- prescribed cardioid path (Section 3)
+def test_cardioid_constants_exact_quarter_turns():
+    """step = i: u_k = i^k exactly, and with a = 4 every constant is dyadic:
+    C = (2u - u^2) / 4 gives 1/4, 1/4 + i/2, -3/4, 1/4 - i/2, ... (k = 6
+    tells the order of the square-and-multiply bits apart)."""
+    want = [0.25 + 0j, 0.25 + 0.5j, -0.75 + 0j, 0.25 - 0.5j]
+    for k in range(12):
+        assert oracle.cardioid_constant(1j, 4.0, 0.0, k) == want[k % 4], k
+    # a_k = a0 - da k: a_1 = 3.5, C_1 = (1 + 2i) / 3.5 correctly rounded
+    assert oracle.cardioid_constant(1j, 4.0, 0.5, 1) == complex(
+        float(Fraction(1) / Fraction(7, 2)), float(Fraction(2) / Fraction(7, 2)))
+    assert oracle.cardioid_constant(1j, 4.0, 0.25, 6) == -3.0 / 2.5 + 0j   # u = -1, a = 2.5
+
+
+def test_cardioid_constants_against_high_precision():
+    """The exact power of the binary64 step, in 60-digit arithmetic, and the
+    definition's own rounded a_k: every constant within 1e-13 relative for
+    k < 4096 (u_k takes up to 2 log2(k) + 1 rounded complex products).  And within 1e-13 of the closed form with t_k = 2 pi k / n for
+    the first trips."""
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 60
+    n, a0, da = 64, 3.9, 0.4 / 255
+    step = complex(math.cos(2 * math.pi / n), math.sin(2 * math.pi / n))
+    s = mpmath.mpc(step.real, step.imag)
+    for k in list(range(0, 300)) + [511, 1000, 2047, 4095]:
+        got = oracle.cardioid_constant(step, a0, da, k)
+        u = s ** k
+        ak = a0 - da * k                     # binary64, as the definition rounds it
+        want = (2 * u - u * u) / ak
+        err = abs(mpmath.mpc(got.real, got.imag) - want) / abs(want)
+        assert err < 1e-13, (k, float(err))
+        if k < 256:
+            t = 2 * math.pi * k / n
+            closed = complex((2 * math.cos(t) - math.cos(2 * t)) / ak,
+                             (2 * math.sin(t) - math.sin(2 * t)) / ak)
+            assert abs(got - closed) < 1e-13, k
+
+
+def test_cardioid_a4_is_the_main_cardioid():
+    """With a = 4, C = u/2 - u^2/4, so 1 - 4C = (1 - u)^2 and the fixed point
+    (1 - sqrt(1 - 4C)) / 2 has multiplier u: modulus 1, the border of the
+    main cardioid of the Mandelbrot set (Section 3)."""
+    step = complex(math.cos(2 * math.pi / 64), math.sin(2 * math.pi / 64))
+    for k in range(1, 64):
+        c = oracle.cardioid_constant(step, 4.0, 0.0, k)
+        mult = 1 - np.sqrt(1 - 4 * c)
+        assert abs(abs(mult) - 1.0) < 1e-13, k
+
+
+def test_cardioid_path_passes_the_paper_constants():
+    """The four constants of Figure 2 lie on the a = 3.9 cardioid: the path
+    with 2^16 frames per trip passes within 5e-5 of each."""
+    rows = {r[0]: complex(float(r[1]), float(r[2])) for r in read_table("paper_constants.txt")}
+    consts = [rows[k] for k in ("fig2_a", "fig2_b", "fig2_c", "fig2_d")]
+    n = 1 << 16
+    step = complex(math.cos(2 * math.pi / n), math.sin(2 * math.pi / n))
+    pts = np.array([oracle.cardioid_constant(step, 3.9, 0.0, k) for k in range(0, n, 1)])
+    for c in consts:
+        assert np.abs(pts - c).min() < 5e-5, c
