@@ -17,6 +17,8 @@ launch on the stream it runs on), the single-threaded CPU oracle on a bounded
 sample of the same workload, and further legs in "extra":
   - the plain one-thread-per-pixel kernel on the same frames, the
     persistent-queue mode, and the fused colour store;
+  - the parameter path in FP64 and in float-float, and Section 3's
+    prescribed cardioid path with its constants generated on the device;
   - the single 4096x4096 images in FP32 and FP64, and the 512x512 FP64
     image's latency;
   - the 1024-frame uneven batch (FP32 and float-float, one launch);
@@ -359,6 +361,35 @@ def extra_legs(args, torch, jr, wl, frames, sched, ms_headline, iters):
                                               4),
             "peak_tflops": peak, "schedule": (dsched.__dict__ if dsched else dsrc),
             "workgroups": info_d["workgroups"]}
+    # Section 3's prescribed path with a growing cardioid: 256 frames of
+    # 1920x1080, four trips of 64 frames while a goes from 3.9 to 3.5, FP32,
+    # cap 100; the constants are generated on the device in every step (one
+    # graph holds the generator and the render), beside per-frame launches of
+    # the plain kernel with the same constants formed on the host (libm)
+    g = wl.growing_cardioid_path()
+    path = jr.CardioidPath(g.step, g.a0, g.da, g.window, g.frames, g.width, g.height,
+                           g.max_iter, g.dtype)
+    csched, csrc = tuned_schedule_or_default(jr, "cardioid_path_fp32")
+    plan = jr.Plan.cardioid(path, csched)
+    plan.capture()
+    ms_cd, kms_cd = time_plan_steps(torch, plan, 10, 2, graph=True)
+    it_cd = count_sum(torch, plan.views)
+    plan.close()
+    import math
+    host = [wl.Frame(wl.cardioid_point(2.0 * math.pi * k / 64, g.a0 - g.da * k), g.window,
+                     g.width, g.height, g.max_iter, g.dtype) for k in range(g.frames)]
+    outs = [torch.empty((f.height, f.width), dtype=torch.int32, device="cuda") for f in host]
+    ms_cp = time_renders(jr, torch, host, outs, 1, plain=True)
+    it_cp = count_sum(torch, outs)
+    del outs
+    ex["cardioid_path_device_generated_fp32"] = {
+        "gpixel_iter_s": round(it_cd / (ms_cd * 1e-3) / 1e9, 2), "ms_per_step": round(ms_cd, 4),
+        "kernel_ms": round(kms_cd, 4), "pixel_iters": it_cd, "frames": g.frames,
+        "a0": g.a0, "a_last": round(g.a0 - g.da * (g.frames - 1), 6),
+        "schedule": csched.__dict__ if csched else csrc,
+        "plain_per_frame_host_constants_ms": round(ms_cp, 4),
+        "plain_gpixel_iter_s": round(it_cp / (ms_cp * 1e-3) / 1e9, 2),
+        "vs_plain": round(ms_cp / ms_cd, 3)}
     # persistent work-queue mode of the same batch
     from dataclasses import replace
     pers = replace(sched, persistent=1, waves_per_cu=32)

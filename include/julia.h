@@ -263,6 +263,41 @@ int julia_render_batch_noalloc(const jr_frame *frames, int32_t n, int32_t *out_b
                                int64_t out_capacity, const jr_schedule *sched, void *stream);
 
 /*
+ * Prescribed parameter path (Section 3) with its constants generated on the
+ * device: frames 0 .. frames-1 of one size, window, cap and dtype, whose
+ * constants lie on the cardioid
+ *     f(t) = ((2 cos t - cos 2t) / a, (2 sin t - sin 2t) / a) = (2u - u^2) / a,
+ * u = e^{it}, stepping by `step` = e^{i dt} per frame while the cardioid grows
+ * (a decreasing: a_k = a0 - da k; a = 4 is the main cardioid's border).  A
+ * kernel writes the frame table, frame k's constant being
+ *     u_k = step^k  by square-and-multiply over the bits of k, highest first
+ *                   (p = 1; per bit: p = p*p, then p = p*step if it is set),
+ *     C_k = (2 u_k - u_k*u_k) / (a0 - da k),
+ * with every complex product (a + ib)(c + id) = (a*c - b*d) + i (a*d + b*c)
+ * and every real operation rounded to binary64; then the batch is rendered as
+ * julia_render_batch renders it.  Frame k occupies width*height elements at
+ * out_offset + k*width*height.
+ *   step     finite; frames * |log|step|| <= 1e-6 (so |u_k| stays within
+ *            1e-6 of 1).
+ *   a0, da   finite; a0 and a0 - da (frames - 1) at least JR_CARDIOID_MIN_A,
+ *            so that |C_k| <= 3.000003 / 1.6 < 1.9 and escape is absorbing.
+ *   frames   1 .. 2^22; dtype any; Julia mode, Z^2 + C.
+ * Errors as julia_render_batch; JR_EINVAL for a path outside these limits.
+ */
+#define JR_CARDIOID_MIN_A 1.6
+typedef struct {
+    jr_complex step;
+    double a0, da;
+    jr_window w;
+    int32_t frames;
+    int32_t width, height, max_iter, dtype;
+    int32_t reserved;
+    int64_t out_offset;
+} jr_cardioid_path;
+int julia_render_cardioid_path(const jr_cardioid_path *path, int32_t *out_base,
+                               int64_t out_capacity, const jr_schedule *sched, void *stream);
+
+/*
  * Fused count -> colour store (Section 2: every pixel is given a colour level
  * by its iteration count).  The frames, schedules and kernels are those of
  * julia_render_batch; only the stored value changes: each pixel stores the
@@ -304,6 +339,11 @@ int julia_render_colored(jr_complex c, jr_window w, int32_t width, int32_t heigh
 typedef struct jr_plan jr_plan;
 int jr_plan_create(const jr_frame *frames, int32_t n, int32_t *out_base,
                    int64_t out_capacity, const jr_schedule *sched, jr_plan **plan);
+/* A plan over a prescribed cardioid path (julia_render_cardioid_path): each
+ * launch (and a captured graph) first generates the frame table on the
+ * device, then renders it. */
+int jr_plan_create_cardioid(const jr_cardioid_path *path, int32_t *out_base,
+                            int64_t out_capacity, const jr_schedule *sched, jr_plan **plan);
 int jr_plan_launch(jr_plan *plan, void *stream);
 /* Capture one launch into a hipGraph on `stream` (once), then replay it. */
 int jr_plan_capture(jr_plan *plan, void *stream);

@@ -61,6 +61,37 @@ class jr_schedule(ctypes.Structure):
 assert ctypes.sizeof(jr_frame) == 112
 
 
+class jr_cardioid_path(ctypes.Structure):
+    _fields_ = [("step", jr_complex), ("a0", ctypes.c_double), ("da", ctypes.c_double),
+                ("w", jr_window), ("frames", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("out_offset", ctypes.c_int64)]
+
+
+@dataclass(frozen=True)
+class CardioidPath:
+    """A prescribed cardioid path whose constants the device generates
+    (julia_render_cardioid_path): frame k has C_k = (2 u_k - u_k^2) /
+    (a0 - da k), u_k = step^k, rendered on `window` at width x height."""
+    step: complex
+    a0: float
+    da: float
+    window: tuple
+    frames: int
+    width: int
+    height: int
+    max_iter: int
+    dtype: str = "fp32"
+
+    def to_c(self, out_offset: int = 0) -> jr_cardioid_path:
+        st = complex(self.step)
+        return jr_cardioid_path(jr_complex(st.real, st.imag), float(self.a0), float(self.da),
+                                _window(self.window), int(self.frames), int(self.width),
+                                int(self.height), int(self.max_iter), DTYPES[self.dtype], 0,
+                                int(out_offset))
+
+
 @dataclass(frozen=True)
 class Schedule:
     """Schedule of the tiled kernel (see include/julia.h); never changes counts."""
@@ -92,7 +123,7 @@ class Schedule:
 EXPORTS = (
     "julia_render", "julia_render_plain", "mandelbrot_render", "mandelbrot_render_plain",
     "julia_render_batch", "julia_render_batch_noalloc", "julia_render_batch_colored",
-    "julia_render_colored",
+    "julia_render_colored", "julia_render_cardioid_path", "jr_plan_create_cardioid",
     "jr_plan_create", "jr_plan_set_palette", "jr_set_image_schedule", "jr_get_image_schedule",
     "jr_clear_image_schedules", "jr_plan_launch", "jr_plan_capture",
     "jr_plan_replay", "jr_plan_info", "jr_plan_destroy", "jr_get_default_schedule",
@@ -132,6 +163,10 @@ def _load():
     lib.julia_render_batch.restype = ctypes.c_int
     lib.julia_render_batch_noalloc.argtypes = [P(jr_frame), i32, vp, i64, P(jr_schedule), vp]
     lib.julia_render_batch_noalloc.restype = ctypes.c_int
+    lib.julia_render_cardioid_path.argtypes = [P(jr_cardioid_path), vp, i64, P(jr_schedule), vp]
+    lib.julia_render_cardioid_path.restype = ctypes.c_int
+    lib.jr_plan_create_cardioid.argtypes = [P(jr_cardioid_path), vp, i64, P(jr_schedule), P(vp)]
+    lib.jr_plan_create_cardioid.restype = ctypes.c_int
     lib.julia_render_batch_colored.argtypes = [P(jr_frame), i32, vp, i32, vp, i64,
                                                P(jr_schedule), vp]
     lib.julia_render_batch_colored.restype = ctypes.c_int
@@ -464,8 +499,48 @@ def render_batch_noalloc(frames: Sequence, arena, schedule: Optional[Schedule] =
             for o, f in zip(offsets, frames)]
 
 
+def render_cardioid_path(path: CardioidPath, schedule: Optional[Schedule] = None, arena=None,
+                         stream=None):
+    """All frames of a prescribed cardioid path in one call, their constants
+    generated on the device (julia_render_cardioid_path).  Returns (arena,
+    views) like render_batch."""
+    import torch
+    px = path.width * path.height
+    if arena is None:
+        arena = torch.empty(path.frames * px, dtype=torch.int32, device="cuda")
+    _arena_tensor(arena, path.frames * px)
+    sched = ctypes.byref(schedule.to_c()) if schedule is not None else None
+    _check(lib.julia_render_cardioid_path(ctypes.byref(path.to_c()),
+                                          ctypes.c_void_p(arena.data_ptr()), arena.numel(),
+                                          sched, _stream_ptr(stream)))
+    return arena, [arena[k * px: (k + 1) * px].view(path.height, path.width)
+                   for k in range(path.frames)]
+
+
 class Plan:
     """A prepared batch: frame table uploaded once; launch() or a captured hipGraph."""
+
+    @classmethod
+    def cardioid(cls, path: CardioidPath, schedule: Optional[Schedule] = None, arena=None):
+        """A plan over a prescribed cardioid path: every launch (and a
+        captured graph) generates the frame table on the device, then renders
+        it (jr_plan_create_cardioid)."""
+        import torch
+        self = cls.__new__(cls)
+        self._h = None
+        px = path.width * path.height
+        self.arena = arena if arena is not None else torch.empty(path.frames * px,
+                                                                 dtype=torch.int32, device="cuda")
+        _arena_tensor(self.arena, path.frames * px)
+        self.frames, self.offsets = [], [k * px for k in range(path.frames)]
+        sched = ctypes.byref(schedule.to_c()) if schedule is not None else None
+        h = ctypes.c_void_p()
+        _check(lib.jr_plan_create_cardioid(ctypes.byref(path.to_c()),
+                                           ctypes.c_void_p(self.arena.data_ptr()),
+                                           self.arena.numel(), sched, ctypes.byref(h)))
+        self._h = h
+        self.views = [self.arena[o: o + px].view(path.height, path.width) for o in self.offsets]
+        return self
 
     def __init__(self, frames: Sequence, schedule: Optional[Schedule] = None, arena=None,
                  offsets=None):

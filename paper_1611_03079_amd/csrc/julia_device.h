@@ -106,6 +106,18 @@ hipError_t noalloc_scratch(int dev, void** ptr);
 // arguments (no copy call, no staging memory): ceil(n / kPutFrames) launches.
 hipError_t put_frames(const DevFrame* rows, int n, DevFrame* dst, hipStream_t stream);
 
+// Frame table of a prescribed cardioid path, written on the device: frame k
+// is `tmpl` with C_k (see julia.h), out_offset0 + k * frame_px and first tile
+// k * tiles_per_frame.
+struct CardioidArgs {
+    DevFrame tmpl;
+    DevFrame* dst;
+    double step_re, step_im, a0, da;
+    int64_t out_offset0, frame_px, tiles_per_frame;
+    int32_t frames;
+};
+hipError_t launch_cardioid_table(const CardioidArgs& g, hipStream_t stream);
+
 // Runs the tiled kernel; in persistent mode a small kernel zeroes the queue
 // counters first (both may be captured into a hipGraph).
 hipError_t launch_tiled(int unroll, int defer, int dtmask, int blocks, const PersistentArgs& args,

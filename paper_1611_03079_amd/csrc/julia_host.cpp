@@ -477,6 +477,20 @@ int get_workspace(int dev, hipStream_t stream, Workspace** out) {
     return JR_OK;
 }
 
+// The workspace's device frame table holds at least `bytes` (caller holds ws->mu).
+int ensure_table(Workspace* ws, size_t bytes, hipStream_t stream) {
+    if (ws->table_cap >= bytes) return JR_OK;
+    // The old table may still be read by work queued on this stream.
+    HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    if (ws->d_table) HIP_TRY(hipFree(ws->d_table), "hipFree");
+    ws->d_table = nullptr;
+    ws->table_cap = 0;
+    size_t cap_bytes = std::max<size_t>(bytes, 64 * sizeof(DevFrame));
+    HIP_TRY(hipMalloc((void**)&ws->d_table, cap_bytes), "hipMalloc frame table");
+    ws->table_cap = cap_bytes;
+    return JR_OK;
+}
+
 int grid_blocks(const DeviceInfo& info, const jr_schedule& s, int64_t total_tiles) {
     if (s.kernel == JR_KERNEL_PLAIN) return (int)std::min<int64_t>(total_tiles, INT32_MAX);
     if (!s.persistent) return (int)std::min<int64_t>((total_tiles + 3) / 4, INT32_MAX);
@@ -545,16 +559,7 @@ int enqueue_batch(const jr_frame* frames, int32_t n, int32_t* out_base, int64_t 
     if (cap != hipStreamCaptureStatusNone)
         return fail(JR_EINVAL, "batch of %d frames on a capturing stream; use jr_plan_capture", n);
     const size_t bytes = (size_t)n * sizeof(DevFrame);
-    if (ws->table_cap < bytes) {
-        // The old table may still be read by work queued on this stream.
-        HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
-        if (ws->d_table) HIP_TRY(hipFree(ws->d_table), "hipFree");
-        ws->d_table = nullptr;
-        ws->table_cap = 0;
-        size_t cap_bytes = std::max<size_t>(bytes, 64 * sizeof(DevFrame));
-        HIP_TRY(hipMalloc((void**)&ws->d_table, cap_bytes), "hipMalloc frame table");
-        ws->table_cap = cap_bytes;
-    }
+    if ((rc = ensure_table(ws, bytes, stream))) return rc;
     const int k = ws->slot;
     ws->slot = (ws->slot + 1) % kStages;
     if (ws->ev_used[k]) HIP_TRY(hipEventSynchronize(ws->ev[k]), "hipEventSynchronize");
@@ -696,6 +701,98 @@ int render_plain(jr_complex c, jr_window w, int32_t W, int32_t H, int32_t max_it
     return JR_OK;
 }
 
+// ------------------------------------------------------------- cardioid paths
+int check_cardioid(const jr_cardioid_path* p, int64_t capacity, const char* who) {
+    if (p == nullptr) return fail(JR_EINVAL, "%s: path is null", who);
+    if (p->frames < 1 || p->frames > kMaxFrames)
+        return fail(JR_EINVAL, "%s: frames must be in 1..%d", who, kMaxFrames);
+    int rc = check_image(p->width, p->height, p->max_iter, p->dtype, JR_JULIA,
+                         jr_complex{0.0, 0.0}, p->w, who);
+    if (rc) return rc;
+    if (!finite(p->step.re) || !finite(p->step.im) || !finite(p->a0) || !finite(p->da))
+        return fail(JR_EINVAL, "%s: step, a0 and da must be finite", who);
+    const double m = std::hypot(p->step.re, p->step.im);
+    if (!(m > 0.0) || std::fabs(std::log(m)) * (double)p->frames > 1e-6)
+        return fail(JR_EINVAL, "%s: frames * |log|step|| must be <= 1e-6", who);
+    const double a_last = p->a0 - p->da * (double)(p->frames - 1);
+    if (!(p->a0 >= JR_CARDIOID_MIN_A) || !(a_last >= JR_CARDIOID_MIN_A))
+        return fail(JR_EINVAL, "%s: a must stay >= %g along the path (a0 %g, last %g)", who,
+                    JR_CARDIOID_MIN_A, p->a0, a_last);
+    const int64_t px = (int64_t)p->width * p->height;
+    if (p->out_offset < 0 || p->out_offset > capacity ||
+        (int64_t)p->frames > (capacity - p->out_offset) / px)
+        return fail(JR_EINVAL, "%s: out_offset + frames*width*height exceeds out_capacity", who);
+    return JR_OK;
+}
+
+jr_schedule path_schedule(const jr_cardioid_path& p, const jr_schedule* sched, int* rc) {
+    *rc = JR_OK;
+    if (sched) {
+        *rc = check_schedule(*sched);
+        return *sched;
+    }
+    return default_schedule(p.dtype);
+}
+
+// The generator's arguments (the record every frame shares; C, offset and
+// first tile are set per frame on the device) and the launch totals.
+jr::CardioidArgs cardioid_args(const jr_cardioid_path& p, const jr_schedule& s, DevFrame* dst,
+                               TableStats& t) {
+    jr::CardioidArgs g;
+    std::memset(&g, 0, sizeof g);
+    jr_frame f = single_frame(jr_complex{0.0, 0.0}, p.w, p.width, p.height, p.max_iter,
+                              p.dtype, JR_JULIA);
+    f.out_offset = p.out_offset;
+    const int64_t tiles = fill_frame(f, s, 0, g.tmpl);
+    g.tmpl.defer = 1;  // every |C_k| < 1.9 (check_cardioid): escape is absorbing
+    g.dst = dst;
+    g.step_re = p.step.re;
+    g.step_im = p.step.im;
+    g.a0 = p.a0;
+    g.da = p.da;
+    g.out_offset0 = p.out_offset;
+    g.frame_px = (int64_t)p.width * p.height;
+    g.tiles_per_frame = tiles;
+    g.frames = p.frames;
+    t = TableStats();
+    t.total_tiles = tiles * p.frames;
+    t.total_cost = frame_cost(f) * (double)p.frames;
+    t.max_tile_cost = frame_cost(f) / (double)tiles;
+    t.dtmask = 1 << p.dtype;
+    return g;
+}
+
+int render_cardioid(const jr_cardioid_path* path, int32_t* out, int64_t capacity,
+                    const jr_schedule* sched, hipStream_t stream) {
+    const char* who = "julia_render_cardioid_path";
+    int rc = check_cardioid(path, capacity, who);
+    if (rc) return rc;
+    if ((rc = check_out(out, who))) return rc;
+    jr_schedule s = path_schedule(*path, sched, &rc);
+    if (rc) return rc;
+    int dev;
+    DeviceInfo info;
+    if ((rc = current_device(&dev, &info))) return rc;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(stream, &cap), "hipStreamIsCapturing");
+    if (cap != hipStreamCaptureStatusNone)
+        return fail(JR_EINVAL, "%s on a capturing stream; use jr_plan_create_cardioid", who);
+    Workspace* ws;
+    if ((rc = get_workspace(dev, stream, &ws))) return rc;
+    std::lock_guard<std::mutex> g(ws->mu);
+    if ((rc = ensure_table(ws, (size_t)path->frames * sizeof(DevFrame), stream))) return rc;
+    TableStats t;
+    jr::CardioidArgs gen = cardioid_args(*path, s, ws->d_table, t);
+    const int blocks = grid_blocks(info, s, t.total_tiles);
+    HIP_TRY(jr::launch_cardioid_table(gen, stream), "cardioid table launch");
+    jr::PersistentArgs args = make_args(t, ws->d_table, out, ws->d_ctr, path->frames, blocks, s);
+    hipError_t e = s.kernel == JR_KERNEL_PLAIN
+                       ? jr::launch_plain_batch(t.dtmask, args, stream)
+                       : jr::launch_tiled(s.unroll, s.defer, t.dtmask, blocks, args, stream);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return JR_OK;
+}
+
 }  // namespace
 
 // ======================================================================== C ABI
@@ -707,6 +804,8 @@ struct jr_plan {
     int dtmask = 0;
     int unroll = 1, defer = 0, blocks = 1, kernel = JR_KERNEL_TILED;
     jr::PersistentArgs args;
+    bool generated = false;       // the table is written on the device per launch
+    jr::CardioidArgs gen;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -816,6 +915,49 @@ int julia_render_batch(const jr_frame* frames, int32_t n, int32_t* out_base,
     return enqueue_batch(frames, n, out_base, out_capacity, sched, (hipStream_t)stream);
 }
 
+int julia_render_cardioid_path(const jr_cardioid_path* path, int32_t* out_base,
+                               int64_t out_capacity, const jr_schedule* sched, void* stream) {
+    return render_cardioid(path, out_base, out_capacity, sched, (hipStream_t)stream);
+}
+
+int jr_plan_create_cardioid(const jr_cardioid_path* path, int32_t* out_base,
+                            int64_t out_capacity, const jr_schedule* sched, jr_plan** plan) {
+    const char* who = "jr_plan_create_cardioid";
+    if (!plan) return fail(JR_EINVAL, "plan is null");
+    *plan = nullptr;
+    int rc = check_cardioid(path, out_capacity, who);
+    if (rc) return rc;
+    if ((rc = check_out(out_base, who))) return rc;
+    jr_schedule s = path_schedule(*path, sched, &rc);
+    if (rc) return rc;
+    int dev;
+    DeviceInfo info;
+    if ((rc = current_device(&dev, &info))) return rc;
+    jr_plan* p = new jr_plan();
+    p->dev = dev;
+    const size_t bytes = (size_t)path->frames * sizeof(DevFrame);
+    hipError_t e = hipMalloc((void**)&p->d_table, bytes);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_ctr, jr::kCounterBytes);
+    if (e == hipSuccess) e = hipMemset(p->d_ctr, 0, jr::kCounterBytes);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        jr_plan_destroy(p);
+        return hip_fail(e, "plan setup");
+    }
+    TableStats t;
+    p->gen = cardioid_args(*path, s, p->d_table, t);
+    p->generated = true;
+    p->total_tiles = t.total_tiles;
+    p->dtmask = t.dtmask;
+    p->unroll = s.unroll;
+    p->defer = s.defer;
+    p->kernel = s.kernel;
+    p->blocks = grid_blocks(info, s, t.total_tiles);
+    p->args = make_args(t, p->d_table, out_base, p->d_ctr, path->frames, p->blocks, s);
+    *plan = p;
+    return JR_OK;
+}
+
 int julia_render_batch_noalloc(const jr_frame* frames, int32_t n, int32_t* out_base,
                                int64_t out_capacity, const jr_schedule* sched, void* stream) {
     return enqueue_batch_noalloc(frames, n, out_base, out_capacity, sched, (hipStream_t)stream);
@@ -876,6 +1018,10 @@ int jr_plan_create(const jr_frame* frames, int32_t n, int32_t* out_base, int64_t
 }
 
 static hipError_t plan_enqueue(const jr_plan* p, hipStream_t stream) {
+    if (p->generated) {
+        hipError_t e = jr::launch_cardioid_table(p->gen, stream);
+        if (e != hipSuccess) return e;
+    }
     return p->kernel == JR_KERNEL_PLAIN
                ? jr::launch_plain_batch(p->dtmask, p->args, stream)
                : jr::launch_tiled(p->unroll, p->defer, p->dtmask, p->blocks, p->args, stream);

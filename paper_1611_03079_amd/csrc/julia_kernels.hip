@@ -1488,6 +1488,50 @@ __global__ void jr_reset_queues(unsigned long long* ctr) {
     if (threadIdx.x < kQueues) ctr[(size_t)threadIdx.x * kQueueStride] = 0ull;
 }
 
+// Frame table of a prescribed cardioid path (Section 3), one thread per
+// frame: u_k = step^k by square-and-multiply over the bits of k from the
+// highest, C_k = (2 u_k - u_k^2) / (a0 - da k), each complex product taken as
+// (a c - b d) + i (a d + b c) and every operation rounded (this translation
+// unit does not contract a*b + c).
+__device__ __forceinline__ void cmul_rounded(double a, double b, double c, double d, double& re,
+                                             double& im) {
+    const double ac = a * c;
+    const double bd = b * d;
+    const double ad = a * d;
+    const double bc = b * c;
+    re = ac - bd;
+    im = ad + bc;
+}
+
+__global__ __launch_bounds__(256) void jr_cardioid_table(CardioidArgs g) {
+    const int k = (int)(blockIdx.x * 256u + threadIdx.x);
+    if (k >= g.frames) return;
+    double pr = 1.0, pi = 0.0;
+    for (int bit = 30; bit >= 0; --bit) {
+        double r, i;
+        cmul_rounded(pr, pi, pr, pi, r, i);
+        pr = r;
+        pi = i;
+        if ((k >> bit) & 1) {
+            cmul_rounded(pr, pi, g.step_re, g.step_im, r, i);
+            pr = r;
+            pi = i;
+        }
+    }
+    double wr, wi;
+    cmul_rounded(pr, pi, pr, pi, wr, wi);
+    const double dk = g.da * (double)k;
+    const double a = g.a0 - dk;
+    const double nr = 2.0 * pr - wr;
+    const double ni = 2.0 * pi - wi;
+    DevFrame f = g.tmpl;
+    f.cr = nr / a;
+    f.ci = ni / a;
+    f.out_offset = g.out_offset0 + (int64_t)k * g.frame_px;
+    f.tile_begin = (int64_t)k * g.tiles_per_frame;
+    g.dst[k] = f;
+}
+
 // Up to kPutFrames frame records travel inside the kernel arguments of
 // jr_put_frames, which writes them to a device frame table: the table of an
 // allocation-free launch needs neither a copy call nor staging memory, and the
@@ -1693,6 +1737,13 @@ hipError_t noalloc_scratch(int dev, void** ptr) {
     }
     *ptr = addr[dev];
     return hipSuccess;
+}
+
+hipError_t launch_cardioid_table(const CardioidArgs& g, hipStream_t stream) {
+    if (g.frames < 1) return hipErrorInvalidValue;
+    const unsigned blocks = (unsigned)((g.frames + 255) / 256);
+    hipLaunchKernelGGL(jr_cardioid_table, dim3(blocks), dim3(256), 0, stream, g);
+    return hipGetLastError();
 }
 
 hipError_t put_frames(const DevFrame* rows, int n, DevFrame* dst, hipStream_t stream) {

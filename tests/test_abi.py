@@ -221,6 +221,36 @@ def test_rational_frames_are_validated_before_device():
     assert "unknown map" in jr.last_error()
 
 
+def test_cardioid_path_is_validated_before_device():
+    """A device-generated cardioid path: a must stay >= 1.6 along it (so
+    every |C_k| < 1.9), |step| must stay within 1e-6 / frames of 1, and the
+    frames must fit the output."""
+    import workloads as wl
+    g = wl.growing_cardioid_path(16, 8, 3.9, 3.5, 32, 24, 80, "fp32")
+    ok = jr.CardioidPath(g.step, g.a0, g.da, g.window, g.frames, g.width, g.height, g.max_iter,
+                         g.dtype)
+    call = jr.lib.julia_render_cardioid_path
+    px = g.width * g.height
+    bad = [dict(a0=1.5), dict(da=0.2), dict(step=1.001 * g.step), dict(frames=0),
+           dict(step=complex(float("nan"), 0.0)), dict(width=0), dict(dtype="fp16")]
+    for kw in bad:
+        d = dict(ok.__dict__)
+        d.update(kw)
+        if d["dtype"] == "fp16":
+            c = ok.to_c()
+            c.dtype = 7
+        else:
+            c = jr.CardioidPath(**d).to_c()
+        assert call(ctypes.byref(c), FAKE_OUT, g.frames * px, None, None) == jr.JR_EINVAL, kw
+        assert jr.last_error()
+    assert call(ctypes.byref(ok.to_c()), FAKE_OUT, g.frames * px - 1, None, None) == jr.JR_EINVAL
+    assert "exceeds out_capacity" in jr.last_error()
+    assert call(None, FAKE_OUT, 10 ** 6, None, None) == jr.JR_EINVAL
+    h = ctypes.c_void_p()
+    assert jr.lib.jr_plan_create_cardioid(ctypes.byref(ok.to_c()), ctypes.c_void_p(0),
+                                          g.frames * px, None, ctypes.byref(h)) == jr.JR_EINVAL
+
+
 def test_valid_call_without_gpu_reports_no_device():
     import torch
     if torch.cuda.is_available():

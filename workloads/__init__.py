@@ -109,6 +109,35 @@ def cardioid_point(t: float, a: float = 3.9) -> complex:
                    (2.0 * math.sin(t) - math.sin(2.0 * t)) / a)
 
 
+@dataclass
+class GrowingCardioid:
+    """Parameters of a prescribed cardioid path with a growing cardioid: the
+    per-frame rotation step = e^{2 pi i / per_trip} (formed here once, with
+    libm), a_k = a0 - da k from a0 down to a1 over the frames.  Each side
+    (the device generator, the oracle) forms C_k from these itself."""
+    step: complex
+    a0: float
+    da: float
+    window: Tuple[float, float, float, float]
+    frames: int
+    width: int
+    height: int
+    max_iter: int
+    dtype: str
+
+
+def growing_cardioid_path(frames: int = 256, per_trip: int = 64, a0: float = 3.9,
+                          a1: float = 3.5, width: int = 1920, height: int = 1080,
+                          max_iter: int = 100, dtype: str = "fp32",
+                          window=(-1.78, 1.78, -1.0, 1.0)) -> GrowingCardioid:
+    """Section 3: the cardioid path with a = 3.9, then a growing cardioid
+    (a decreasing) over several trips around the Mandelbrot set."""
+    t = 2.0 * math.pi / per_trip
+    da = (a0 - a1) / (frames - 1) if frames > 1 else 0.0
+    return GrowingCardioid(complex(math.cos(t), math.sin(t)), a0, da, window, frames, width,
+                           height, max_iter, dtype)
+
+
 def cardioid_path(n: int, a: float = 3.9, width: int = 1920, height: int = 1080,
                   max_iter: int = 100, dtype: str = "fp32",
                   window=(-1.78, 1.78, -1.0, 1.0)) -> List[Frame]:
