@@ -168,10 +168,14 @@ typedef struct {
  *                   counted iterations (rounded up to a multiple of 4), with
  *                   no exchange between lanes.  Pixels that finish store at
  *                   once; the others wait in a per-wave list in shared
- *                   memory, which the wave drains with refilled counted
- *                   blocks of `unroll` (4 or 8, defer 0) whenever it could
- *                   not take the next rows' survivors, and at the end of the
- *                   tile.
+ *                   memory, which the wave drains with refilled blocks of
+ *                   `unroll` (4 or 8) whenever it could not take the next
+ *                   rows' survivors, and at the end of the tile: counted
+ *                   blocks with defer 0; with defer 1, in launches of FP32
+ *                   frames only or FP64 frames only, blocks that test their
+ *                   last iterate, the lanes found escaped being replayed
+ *                   with the counted test at the next refill round (other
+ *                   launches take counted blocks).
  *   bail            JR_KERNEL_HYBRID: 1..4096; JR_KERNEL_ROWS: 1..64 (other
  *                   kernels ignore it).
  *   handoff         JR_KERNEL_ROWS, 0..256: rows run in groups for FP32 and
@@ -203,9 +207,12 @@ typedef struct {
 } jr_schedule;
 
 /*
- * Render one Julia image (Section 2) with the tuned tiled kernel.
- * out: device, width*height int32, row-major.  The schedule is the library's
- * default for (dtype, max_iter) (see jr_set_default_schedule).
+ * Render one Julia image (Section 2) with the tuned kernels.
+ * out: device, width*height int32, row-major.  The schedule is the one
+ * jr_get_image_schedule gives for (dtype, max_iter, width*height): the
+ * per-image entry installed by jr_set_image_schedule that covers the cap and
+ * size (the Python binding installs the autotuner's winners), else the
+ * dtype's default (jr_get_default_schedule).
  */
 int julia_render(jr_complex c, jr_window w, int32_t width, int32_t height,
                  int32_t max_iter, int32_t dtype, int32_t *out, void *stream);
@@ -361,7 +368,10 @@ int jr_plan_set_palette(jr_plan *plan, const uint32_t *palette, int32_t palette_
 int jr_plan_info(const jr_plan *plan, int64_t *tiles, int32_t *workgroups);
 void jr_plan_destroy(jr_plan *plan);
 
-/* Library default schedule per dtype, used when sched is NULL. */
+/* Library default schedule of a dtype, used by batch calls with sched NULL
+ * and by one-image calls that no per-image entry covers.  There is one
+ * default per dtype, the same for every cap: max_iter is checked (0 ..
+ * JR_MAX_ITER, JR_EINVAL otherwise) and does not change the result. */
 int jr_get_default_schedule(int32_t dtype, int32_t max_iter, jr_schedule *out);
 int jr_set_default_schedule(int32_t dtype, const jr_schedule *sched);
 

@@ -16,7 +16,7 @@ Search, in stages from a base schedule:
      refilled) under that tiling, for several bail points,
   6. the two-phase row-packet kernel: its first block, then scheduling mode,
      refill, resident waves and tile shape, then the tile order, then its
-     first block again,
+     first block again, then its drain's blocks (counted or deferred),
   7. the batched one-thread-per-pixel kernel, in both tile orders, as the
      last candidates.
 A workload too large to search whole is searched on a subset of its frames;
@@ -223,6 +223,9 @@ def tune(frames: Sequence, base: Optional[jr.Schedule] = None, reps: int = 3,
     r = _stage(frames, r, ORDERS, reps, log, singles)
     r = _stage(frames, r, [dict(bail=p, handoff=h) for p in ROWS_FIRST for h in ROWS_HANDOFF],
                reps, log, singles)
+    # the drain's blocks: counted, or testing their last iterate
+    r = _stage(frames, r, [dict(defer=d, unroll=k) for d in (0, 1) for k in (4, 8)], reps, log,
+               singles)
     t = min(tt for d, tt in log if jr.Schedule(**d) == r)
     if t < best_t:
         s, best_t = r, t

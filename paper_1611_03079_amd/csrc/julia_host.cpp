@@ -119,8 +119,8 @@ int check_schedule(const jr_schedule& s) {
     if (s.kernel == JR_KERNEL_HYBRID && (s.bail < 1 || s.bail > 4096))
         return fail(JR_EINVAL, "schedule: bail must be in 1..4096 (got %d)", s.bail);
     if (s.kernel == JR_KERNEL_ROWS) {
-        if (s.defer != 0 || (s.unroll != 4 && s.unroll != 8))
-            return fail(JR_EINVAL, "schedule: the rows kernel takes defer 0 and unroll 4 or 8");
+        if (s.unroll != 4 && s.unroll != 8)
+            return fail(JR_EINVAL, "schedule: the rows kernel takes unroll 4 or 8");
         if (s.bail < 1 || s.bail > 64)
             return fail(JR_EINVAL, "schedule: rows kernel bail must be in 1..64 (got %d)", s.bail);
         if (s.handoff < 0 || s.handoff > 256)
@@ -836,8 +836,9 @@ int jr_check_frames(const jr_frame* frames, int32_t n, int64_t out_capacity) {
 }
 
 int jr_get_default_schedule(int32_t dtype, int32_t max_iter, jr_schedule* out) {
-    (void)max_iter;
     if (!out) return fail(JR_EINVAL, "out is null");
+    if (max_iter < 0 || max_iter > JR_MAX_ITER)
+        return fail(JR_EINVAL, "max_iter %d outside 0..%d", max_iter, JR_MAX_ITER);
     if (dtype < 0 || dtype > 2) return fail(JR_EINVAL, "unknown dtype %d", dtype);
     *out = default_schedule(dtype);
     return JR_OK;

@@ -1193,9 +1193,11 @@ __device__ __forceinline__ CArgs& kernel_args() {
     return *(CArgs*)__builtin_amdgcn_kernarg_segment_ptr();
 }
 
-template <class A, int K, int MANDEL, int COLOR, int LROWS, class Args>
+template <class A, int K, int MANDEL, int COLOR, int LROWS, int DD, class Args>
 __device__ void rows_tile(const Args& a, CFrame& F, int64_t t, int P, uint32_t* list) {
     constexpr int cap = 64 * LROWS;  // list entries
+    // deferred drain blocks need escape to be absorbing (K > 1 means it is)
+    constexpr bool kDeferDrain = DD != 0 && K > 1;
     using V = typename A::V;
     constexpr int ZW = (int)(sizeof(typename A::Z) / 4);
     const uint32_t local = (uint32_t)(t - F.tile_begin);
@@ -1251,26 +1253,45 @@ __device__ void rows_tile(const Args& a, CFrame& F, int64_t t, int P, uint32_t* 
         }
         qn += __popcll(m);
     };
-    // Phase 2: the refill stream over the list's entries, in counted blocks of
-    // K; idle lanes read the next entries straight from the list, and C is
-    // the frame's constant.  It runs whenever the list could not take the
-    // next group's survivors, and at the end of the tile, so a drain usually
-    // holds several wave-loads of survivors and its tail stays short.
+    // Phase 2: the refill stream over the list's entries, in blocks of K;
+    // idle lanes read the next entries straight from the list, and C is the
+    // frame's constant.  It runs whenever the list could not take the next
+    // group's survivors, and at the end of the tile, so a drain usually holds
+    // several wave-loads of survivors and its tail stays short.  Counted
+    // blocks test every iterate; deferred blocks (kDeferDrain) run K untested
+    // steps and test the last iterate only.  A lane found escaped then keeps
+    // its block start and its count before the block, and the next refill
+    // round replays that block for it with the counted test, once for all
+    // such lanes.  The survivors are long orbits, most of them running to the
+    // cap, so most blocks need no replay.
     auto drain = [&]() {
         if (qn == 0) return;
         // Other lanes read the entries written above, and the next rows
         // overwrite them afterwards: keep the compiler from moving LDS
         // accesses across either point (one wave runs them in order).
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        bool it = false, fi = false;
+        bool it = false, fi = false, pe = false;
         int n = 0, cnt = 0, off = 0;
         typename A::Z z = A::make(zero, zero);
+        typename A::Z zs = z;
         typename A::C c = cj;
         int next = 0;
         uint64_t running = 0;
         const int busy_max = 64 - a.refill;
         for (;;) {
             if (__popcll(running) <= busy_max) {
+                if (kDeferDrain && __ballot(pe) != 0) {
+                    // replay, counted, the block in which these lanes escaped
+                    typename A::Z zr = zs;
+                    int lead = 0;
+#pragma unroll
+                    for (int u = 0; u < K; ++u) lead += A::check_step(zr, c, deg) ? 1 : 0;
+                    if (pe) {
+                        cnt = min(n + lead, mi);
+                        fi = true;
+                        pe = false;
+                    }
+                }
                 if (fi) {
                     // r * W + col fits an int (a frame holds < 2^31 pixels),
                     // but four times it may not fit 32 bits: index, so that
@@ -1304,14 +1325,27 @@ __device__ void rows_tile(const Args& a, CFrame& F, int64_t t, int P, uint32_t* 
                 running = __ballot(it);
                 if (running == 0) break;
             }
-            int lead = 0;
+            if (kDeferDrain) {
+                zs = select_words(pe, zs, z);  // a lane awaiting its replay keeps its block start
 #pragma unroll
-            for (int u = 0; u < K; ++u) lead += A::check_step(z, c, deg) ? 1 : 0;
-            const bool stop = (lead < K) || (n + K >= mi);
-            cnt = (it && stop) ? min(n + lead, mi) : cnt;
-            fi = fi || (it && stop);
-            it = it && !stop;
-            n += K;
+                for (int u = 0; u < K; ++u) A::step(z, c, deg);
+                const bool esc = !A::inside(z, c, deg);
+                const bool capped = n + K >= mi;  // no escape in the block: count the cap
+                cnt = (it && !esc && capped) ? mi : cnt;
+                fi = fi || (it && !esc && capped);
+                pe = pe || (it && esc);
+                n = (it && !esc) ? n + K : n;
+                it = it && !esc && !capped;
+            } else {
+                int lead = 0;
+#pragma unroll
+                for (int u = 0; u < K; ++u) lead += A::check_step(z, c, deg) ? 1 : 0;
+                const bool stop = (lead < K) || (n + K >= mi);
+                cnt = (it && stop) ? min(n + lead, mi) : cnt;
+                fi = fi || (it && stop);
+                it = it && !stop;
+                n += K;
+            }
             running = __ballot(it);
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -1410,7 +1444,7 @@ __device__ void rows_tile(const Args& a, CFrame& F, int64_t t, int P, uint32_t* 
 // work queues and for large palettes (which the workgroup stages once), 1 for
 // dispatched tiles, so that a wave's LDS is released as soon as its own tile
 // is done instead of when the slowest of four tiles is.
-template <int K, int DTMASK, int WPB>
+template <int K, int DTMASK, int WPB, int DD>
 __global__ __launch_bounds__(64 * WPB) void jr_rows(PersistentArgs a) {
     constexpr int COLOR = (DTMASK & kColorBit) ? 1 : 0;
     static_assert(WPB == 4 || WPB == 1, "one or four waves per workgroup");
@@ -1438,10 +1472,10 @@ __global__ __launch_bounds__(64 * WPB) void jr_rows(PersistentArgs a) {
         const bool mandel = F.mode == kModeMandelbrot;
 #define JR_ROWS(A_, ARGS_)                                                               \
     do {                                                                                 \
-        if (abs && !mandel) rows_tile<A_, K, 0, COLOR, S::rows>(ARGS_, F, t, P, list); \
-        else if (abs) rows_tile<A_, K, 1, COLOR, S::rows>(ARGS_, F, t, P, list);       \
-        else if (!mandel) rows_tile<A_, 1, 0, COLOR, S::rows>(ARGS_, F, t, P, list);   \
-        else rows_tile<A_, 1, 1, COLOR, S::rows>(ARGS_, F, t, P, list);                \
+        if (abs && !mandel) rows_tile<A_, K, 0, COLOR, S::rows, DD>(ARGS_, F, t, P, list); \
+        else if (abs) rows_tile<A_, K, 1, COLOR, S::rows, DD>(ARGS_, F, t, P, list);       \
+        else if (!mandel) rows_tile<A_, 1, 0, COLOR, S::rows, 0>(ARGS_, F, t, P, list);    \
+        else rows_tile<A_, 1, 1, COLOR, S::rows, 0>(ARGS_, F, t, P, list);                 \
     } while (0)
         // quadratic maps: kernels that also hold the general maps call tiles
         // that are not inlined, which take the arguments in place
@@ -1455,8 +1489,8 @@ __global__ __launch_bounds__(64 * WPB) void jr_rows(PersistentArgs a) {
         // rational maps: Julia images in FP64 or FP32 (the host checks)
 #define JR_ROWS_R(A_)                                                              \
     do {                                                                           \
-        if (abs) rows_tile<A_, K, 0, COLOR, S::rows>(ka, F, t, P, list);          \
-        else rows_tile<A_, 1, 0, COLOR, S::rows>(ka, F, t, P, list);              \
+        if (abs) rows_tile<A_, K, 0, COLOR, S::rows, DD>(ka, F, t, P, list);      \
+        else rows_tile<A_, 1, 0, COLOR, S::rows, 0>(ka, F, t, P, list);           \
     } while (0)
         if ((DTMASK & kRationalBit) && F.map == kMapRational) {
             if (F.dtype == kFP32)
@@ -1614,39 +1648,44 @@ static TiledFn pick_block(int unroll, int defer, int dtmask) {
 }
 
 template <int K>
-static TiledFn pick_rows_mask(int dtmask, bool one_wave) {
+static TiledFn pick_rows_mask(int dtmask, bool one_wave, int defer) {
+    // deferred drain blocks: launches of FP32 or FP64 frames only, counts
+    if (defer && dtmask == (1 << kFP32))
+        return one_wave ? jr_rows<K, 1 << kFP32, 1, 1> : jr_rows<K, 1 << kFP32, 4, 1>;
+    if (defer && dtmask == (1 << kFP64))
+        return one_wave ? jr_rows<K, 1 << kFP64, 1, 1> : jr_rows<K, 1 << kFP64, 4, 1>;
     constexpr int kGR = 7 | kGeneralBit | kRationalBit;
     if (dtmask & kRationalBit) {
-        if (dtmask & kColorBit) return jr_rows<K, kGR | kColorBit, 4>;
-        return one_wave ? jr_rows<K, kGR, 1> : jr_rows<K, kGR, 4>;
+        if (dtmask & kColorBit) return jr_rows<K, kGR | kColorBit, 4, 0>;
+        return one_wave ? jr_rows<K, kGR, 1, 0> : jr_rows<K, kGR, 4, 0>;
     }
     if (one_wave && dtmask == ((1 << kFP32) | kColorBit))
-        return jr_rows<K, (1 << kFP32) | kColorBit, 1>;
+        return jr_rows<K, (1 << kFP32) | kColorBit, 1, 0>;
     if (one_wave && !(dtmask & kColorBit)) {
-        if (dtmask & kGeneralBit) return jr_rows<K, 7 | kGeneralBit, 1>;
+        if (dtmask & kGeneralBit) return jr_rows<K, 7 | kGeneralBit, 1, 0>;
         switch (dtmask) {
-            case 1 << kFP32: return jr_rows<K, 1 << kFP32, 1>;
-            case 1 << kFP64: return jr_rows<K, 1 << kFP64, 1>;
-            case 1 << kFF: return jr_rows<K, 1 << kFF, 1>;
-            default: return jr_rows<K, 7, 1>;
+            case 1 << kFP32: return jr_rows<K, 1 << kFP32, 1, 0>;
+            case 1 << kFP64: return jr_rows<K, 1 << kFP64, 1, 0>;
+            case 1 << kFF: return jr_rows<K, 1 << kFF, 1, 0>;
+            default: return jr_rows<K, 7, 1, 0>;
         }
     }
     if (dtmask & kGeneralBit)
-        return (dtmask & kColorBit) ? jr_rows<K, 7 | kGeneralBit | kColorBit, 4>
-                                    : jr_rows<K, 7 | kGeneralBit, 4>;
+        return (dtmask & kColorBit) ? jr_rows<K, 7 | kGeneralBit | kColorBit, 4, 0>
+                                    : jr_rows<K, 7 | kGeneralBit, 4, 0>;
     switch (dtmask) {
-        case 1 << kFP32: return jr_rows<K, 1 << kFP32, 4>;
-        case 1 << kFP64: return jr_rows<K, 1 << kFP64, 4>;
-        case 1 << kFF: return jr_rows<K, 1 << kFF, 4>;
-        case (1 << kFP32) | kColorBit: return jr_rows<K, (1 << kFP32) | kColorBit, 4>;
-        default: return (dtmask & kColorBit) ? jr_rows<K, 7 | kColorBit, 4> : jr_rows<K, 7, 4>;
+        case 1 << kFP32: return jr_rows<K, 1 << kFP32, 4, 0>;
+        case 1 << kFP64: return jr_rows<K, 1 << kFP64, 4, 0>;
+        case 1 << kFF: return jr_rows<K, 1 << kFF, 4, 0>;
+        case (1 << kFP32) | kColorBit: return jr_rows<K, (1 << kFP32) | kColorBit, 4, 0>;
+        default: return (dtmask & kColorBit) ? jr_rows<K, 7 | kColorBit, 4, 0> : jr_rows<K, 7, 4, 0>;
     }
 }
 
-static TiledFn pick_rows(int unroll, int dtmask, bool one_wave) {
+static TiledFn pick_rows(int unroll, int dtmask, bool one_wave, int defer) {
     switch (unroll) {
-        case 4: return pick_rows_mask<4>(dtmask, one_wave);
-        case 8: return pick_rows_mask<8>(dtmask, one_wave);
+        case 4: return pick_rows_mask<4>(dtmask, one_wave, defer);
+        case 8: return pick_rows_mask<8>(dtmask, one_wave, defer);
         default: return nullptr;
     }
 }
@@ -1708,7 +1747,7 @@ hipError_t launch_tiled(int unroll, int defer, int dtmask, int blocks, const Per
     blocks = launch_workgroups(dtmask, args, blocks);
     if (args.palette_len > 0) dtmask |= kColorBit;
     const unsigned threads = one_wave ? 64u : 256u;
-    TiledFn fn = args.rows ? pick_rows(unroll, dtmask, one_wave)
+    TiledFn fn = args.rows ? pick_rows(unroll, dtmask, one_wave, defer)
                            : pick(unroll, defer, dtmask, args.hybrid);
     if (!fn || args.palette_len > kPaletteMax) return hipErrorInvalidValue;
     if (args.persistent) {

@@ -145,10 +145,11 @@ def test_check_schedule_rejects(field, value):
         assert jr.check_schedule(jr.Schedule(kernel="tiled", bail=0)) == jr.JR_OK
         rows = jr.Schedule(64, 16, 8, 0, 16, 0, 16, "cost", "rows", 4)
         assert jr.check_schedule(rows) == jr.JR_OK
-        for bad in (dict(bail=0), dict(bail=65), dict(unroll=2), dict(unroll=8, defer=1),
+        for bad in (dict(bail=0), dict(bail=65), dict(unroll=2), dict(unroll=16, defer=1),
                     dict(handoff=-1), dict(handoff=257)):
             assert jr.check_schedule(jr.Schedule(**{**rows.__dict__, **bad})) == jr.JR_EINVAL
-        for good in (dict(handoff=0), dict(handoff=256), dict(bail=64, handoff=32)):
+        for good in (dict(handoff=0), dict(handoff=256), dict(bail=64, handoff=32),
+                     dict(defer=1), dict(defer=1, unroll=4)):
             assert jr.check_schedule(jr.Schedule(**{**rows.__dict__, **good})) == jr.JR_OK
         # other kernels ignore the field
         assert jr.check_schedule(jr.Schedule(kernel="tiled", handoff=500)) == jr.JR_OK
@@ -163,6 +164,11 @@ def test_default_schedules_are_valid_and_settable():
     for dt in ("fp64", "fp32", "ff"):
         s = jr.default_schedule(dt)
         assert jr.check_schedule(s) == jr.JR_OK
+    # one default per dtype, the same for every cap; the cap is checked
+    assert jr.default_schedule("fp32", 100) == jr.default_schedule("fp32", 5000)
+    out = jr.jr_schedule()
+    assert jr.lib.jr_get_default_schedule(1, -1, ctypes.byref(out)) == jr.JR_EINVAL
+    assert jr.lib.jr_get_default_schedule(1, 2 ** 30 + 1, ctypes.byref(out)) == jr.JR_EINVAL
     old = jr.default_schedule("fp32")
     new = jr.Schedule(32, 8, 8, 1, 8, 1, 24, "table", "hybrid", 12)
     jr.set_default_schedule("fp32", new)

@@ -43,6 +43,10 @@ SCHEDULES = [
     jr.Schedule(64, 64, 4, 0, 8, 1, 8, "table", "rows", 8),   # several list drains per tile
     jr.Schedule(64, 64, 8, 0, 16, 0, 16, "cost", "rows", 64, 48),  # groups hand off early
     jr.Schedule(37, 5, 4, 0, 32, 1, 8, "table", "rows", 12, 128),  # often after one trip
+    # the rows kernel's drain in blocks that test their last iterate
+    jr.Schedule(64, 16, 8, 1, 16, 0, 16, "cost", "rows", 4),
+    jr.Schedule(64, 64, 4, 1, 8, 1, 8, "table", "rows", 8),     # several drains, queues
+    jr.Schedule(64, 32, 8, 1, 16, 0, 16, "table", "rows", 64, 128),
 ]
 
 
@@ -156,6 +160,28 @@ def mixed_frames():
         Frame(complex(0.3, 0.5), (-1.2, 1.2, -1.2, 1.2), 200, 3, 0, "ff"),
         Frame(0j, (-0.75, -0.74, 0.1, 0.11), 90, 70, 2000, "fp64", "mandelbrot"),
     ]
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "fp64"])
+def test_deferred_drain_blocks_at_the_cap(dtype):
+    """Deferred drain blocks where the cap falls inside a block (caps 37,
+    101, 203 are not multiples of 4 or 8), in Julia and Mandelbrot frames
+    (a lane's own C in the replay), in launches of one dtype (which take
+    the deferred blocks) and mixed with the other dtype (counted blocks)."""
+    for K in (4, 8):
+        sched = jr.Schedule(64, 16, K, 1, 16, 0, 16, "cost", "rows", 8)
+        for cap in (37, 101, 203):
+            frames = [Frame(complex(-0.8, 0.156), (-1.5, 1.5, -1.5, 1.5), 97, 61, cap, dtype),
+                      Frame(0j, (-1.3, 0.5, -1.1, 1.1), 80, 70, cap, dtype, "mandelbrot")]
+            _, views = batch(frames, sched)
+            for f, v in zip(frames, views):
+                np.testing.assert_array_equal(v, ref(f), err_msg="%s K=%d cap=%d" % (f, K, cap))
+            other = "fp64" if dtype == "fp32" else "fp32"
+            mixed = frames + [Frame(complex(0.285, 0.01), (-1.2, 1.2, -0.9, 0.9), 50, 40, cap,
+                                    other)]
+            _, views = batch(mixed, sched)
+            for f, v in zip(mixed, views):
+                np.testing.assert_array_equal(v, ref(f), err_msg="mixed %s" % (f,))
 
 
 @pytest.mark.parametrize("sched", [None, *range(len(SCHEDULES))])
