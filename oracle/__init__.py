@@ -57,9 +57,11 @@ def _open(path):
     for name in ("jro_two_sum", "jro_fast_two_sum", "jro_two_prod"):
         getattr(lib, name).argtypes = [f, f, p_f, p_f]
         getattr(lib, name).restype = None
-    for name in ("jro_dw_add", "jro_dw_mul"):
+    for name in ("jro_dw_add", "jro_dw_mul", "jro_dw_add_cheap"):
         getattr(lib, name).argtypes = [f, f, f, f, p_f, p_f]
         getattr(lib, name).restype = None
+    lib.jro_dw_sqr.argtypes = [f, f, p_f, p_f]
+    lib.jro_dw_sqr.restype = None
     lib.jro_dw_split.argtypes = [d, p_f, p_f]
     lib.jro_dw_split.restype = None
     lib.jro_count_general.argtypes = [i32, i32, d, d, d, d, i32]
@@ -228,6 +230,14 @@ def dw_add(x, y):
 
 def dw_mul(x, y):
     return _pair("jro_dw_mul", x[0], x[1], y[0], y[1])
+
+
+def dw_sqr(x):
+    return _pair("jro_dw_sqr", x[0], x[1])
+
+
+def dw_add_cheap(x, y):
+    return _pair("jro_dw_add_cheap", x[0], x[1], y[0], y[1])
 
 
 def dw_split(v):

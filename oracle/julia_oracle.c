@@ -209,6 +209,54 @@ void jro_dw_split(double v, float *hi, float *lo)
     *lo = z.lo;
 }
 
+/* Cheaper double-word operations of the quadratic map's float-float
+ * formulation (the general maps keep dw_add and dw_mul):
+ *   dw_sqr       the square: TwoProd of the high part, plus one fused
+ *                2*hi*lo term (2*hi is exact); the lo*lo term, below u^2
+ *                of the result, is left out; one Fast2Sum.
+ *   dw_add_cheap the sum: TwoSum of the high parts, the low parts' sum
+ *                added to its error, one Fast2Sum (the "sloppy" double-word
+ *                sum of Joldes, Muller and Popescu): for operands of one sign
+ *                its error stays below a few u^2 of the result; under
+ *                cancellation it is bounded by u^2 of the operands. */
+static dw dw_sqr(dw x)
+{
+    float p, e;
+    jro_two_prod(x.hi, x.hi, &p, &e);
+    float twice_hi = x.hi + x.hi;               /* exact */
+    float q = fmaf(twice_hi, x.lo, e);
+    dw z;
+    jro_fast_two_sum(p, q, &z.hi, &z.lo);
+    return z;
+}
+
+static dw dw_add_cheap(dw x, dw y)
+{
+    float sh, sl;
+    jro_two_sum(x.hi, y.hi, &sh, &sl);
+    float lows = x.lo + y.lo;
+    float err = sl + lows;
+    dw z;
+    jro_fast_two_sum(sh, err, &z.hi, &z.lo);
+    return z;
+}
+
+void jro_dw_sqr(float xh, float xl, float *zh, float *zl)
+{
+    dw x = {xh, xl};
+    dw z = dw_sqr(x);
+    *zh = z.hi;
+    *zl = z.lo;
+}
+
+void jro_dw_add_cheap(float xh, float xl, float yh, float yl, float *zh, float *zl)
+{
+    dw x = {xh, xl}, y = {yh, yl};
+    dw z = dw_add_cheap(x, y);
+    *zh = z.hi;
+    *zl = z.lo;
+}
+
 /* |Z|^2 <= 4 for a double-word m: hi < 4, or hi == 4 and lo <= 0. */
 static int dw_not_above_four(dw m)
 {
@@ -216,21 +264,24 @@ static int dw_not_above_four(dw m)
 }
 
 /* Float-float formulation of the same iteration:                           */
-/*   |Z|^2 = x*x + y*y,  Re Z' = (x*x + (-(y*y))) + cr,                      */
-/*   Im Z' = (2x)*y + ci,   each + and * a double-word operation above.      */
+/*   x2 = sqr(x), y2 = sqr(y), |Z|^2 = x2 +' y2 (one sign: exact enough to    */
+/*   decide |Z|^2 > 4 against the double-word 4),                           */
+/*   Re Z' = (x2 +' (-y2)) +' cr,  Im Z' = ((2x) * y) +' ci,                  */
+/* sqr the double-word square, * the double-word product, +' the cheaper     */
+/* double-word sum (dw_add_cheap).                                           */
 static int32_t count_ff(dw x, dw y, dw cr, dw ci, int32_t max_iter)
 {
     int32_t n = 0;
     while (n < max_iter) {
-        dw x2 = dw_mul(x, x);
-        dw y2 = dw_mul(y, y);
-        dw m = dw_add(x2, y2);
+        dw x2 = dw_sqr(x);
+        dw y2 = dw_sqr(y);
+        dw m = dw_add_cheap(x2, y2);
         if (!dw_not_above_four(m))
             break;
-        dw re = dw_add(x2, dw_neg(y2));
-        dw xn = dw_add(re, cr);
+        dw re = dw_add_cheap(x2, dw_neg(y2));
+        dw xn = dw_add_cheap(re, cr);
         dw im = dw_mul(dw_twice(x), y);
-        dw yn = dw_add(im, ci);
+        dw yn = dw_add_cheap(im, ci);
         x = xn;
         y = yn;
         n = n + 1;

@@ -26,7 +26,11 @@
  *     operation rounded to binary64.
  *   - FP32 and float-float are two further arithmetic formulations of the same
  *     iteration, fixed here so that a GPU kernel using them can be checked
- *     bit for bit (see julia_oracle.c).
+ *     bit for bit (see julia_oracle.c).  Float-float squares with the
+ *     double-word square, multiplies 2x by y with the double-word product,
+ *     and sums with the cheaper double-word sum (jro_dw_sqr, jro_dw_mul,
+ *     jro_dw_add_cheap); the general maps' float-float uses the accurate
+ *     double-word sum and product (jro_dw_add, jro_dw_mul) throughout.
  *
  * All functions are synchronous, single-threaded and take host pointers.
  * Arguments are not validated: callers pass W, H >= 1 and max_iter >= 0.
@@ -141,6 +145,11 @@ void jro_two_prod(float a, float b, float *p, float *e);
 void jro_dw_add(float xh, float xl, float yh, float yl, float *zh, float *zl);
 void jro_dw_mul(float xh, float xl, float yh, float yl, float *zh, float *zl);
 void jro_dw_split(double v, float *hi, float *lo);
+/* The cheaper square and sum of the quadratic map's float-float iteration
+ * (julia_oracle.c): TwoProd of the high part plus one fused 2*hi*lo term;
+ * TwoSum of the high parts plus the low parts, one Fast2Sum. */
+void jro_dw_sqr(float xh, float xl, float *zh, float *zl);
+void jro_dw_add_cheap(float xh, float xl, float yh, float yl, float *zh, float *zl);
 
 #ifdef __cplusplus
 }

@@ -140,6 +140,19 @@ def dw_mul(x, y):
     return fast_two_sum(ch, cl1 + t)
 
 
+def dw_sqr(x):
+    """h^2 exactly as p + e, then 2 h l fused onto e; l^2 left out."""
+    p = x[0] * x[0]
+    e = fmaf(x[0], x[0], -p)
+    return fast_two_sum(p, fmaf(x[0] * F32(2), x[1], e))
+
+
+def dw_add_cheap(x, y):
+    """TwoSum of the high words; the low words' sum joins its error."""
+    sh, sl = two_sum(x[0], y[0])
+    return fast_two_sum(sh, sl + (x[1] + y[1]))
+
+
 def counts_ff(x0, y0, cr, ci, max_iter):
     shape = np.shape(x0)
     x = split(x0)
@@ -149,15 +162,15 @@ def counts_ff(x0, y0, cr, ci, max_iter):
 
     def esc(s):
         xx, yy = s
-        m = dw_add(dw_mul(xx, xx), dw_mul(yy, yy))
+        m = dw_add_cheap(dw_sqr(xx), dw_sqr(yy))
         return ~((m[0] < 4) | ((m[0] == 4) & (m[1] <= 0)))
 
     def step(s, act):
         xx, yy = s
-        x2 = dw_mul(xx, xx)
-        y2 = dw_mul(yy, yy)
-        xn = dw_add(dw_add(x2, (-y2[0], -y2[1])), crs)
-        yn = dw_add(dw_mul((xx[0] * F32(2), xx[1] * F32(2)), yy), cis)
+        x2 = dw_sqr(xx)
+        y2 = dw_sqr(yy)
+        xn = dw_add_cheap(dw_add_cheap(x2, (-y2[0], -y2[1])), crs)
+        yn = dw_add_cheap(dw_mul((xx[0] * F32(2), xx[1] * F32(2)), yy), cis)
         pick = lambda new, old: (np.where(act, new[0], old[0]), np.where(act, new[1], old[1]))
         return (pick(xn, xx), pick(yn, yy))
 

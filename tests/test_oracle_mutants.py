@@ -44,6 +44,12 @@ MUTANTS = {
     "ff_lost_cross": ("float cross = fmaf(x.lo, y.hi, cross1);", "float cross = cross1;"),
     "ff_lost_tl": ("float w = tl + vl;", "float w = vl;"),
     "ff_escape_lo": ("(m.hi == 4.0f && m.lo <= 0.0f)", "(m.hi == 4.0f)"),
+    "ff_sqr_lost_cross": ("float q = fmaf(twice_hi, x.lo, e);", "float q = e;"),
+    "ff_sqr_once": ("float twice_hi = x.hi + x.hi;", "float twice_hi = x.hi;"),
+    "ff_sqr_lost_err": ("float q = fmaf(twice_hi, x.lo, e);", "float q = twice_hi * x.lo;"),
+    "ff_cheap_lost_lows": ("float err = sl + lows;", "float err = sl;"),
+    "ff_cheap_lost_sl": ("float err = sl + lows;", "float err = lows;"),
+    "ff_cheap_lost_ylo": ("float lows = x.lo + y.lo;", "float lows = x.lo;"),
     "colour_level_shift": ("out[k] = palette[level];",
                            "out[k] = palette[level > 0 ? level - 1 : 0];"),
     "colour_clamp_to_first": ("            level = palette_len - 1;", "            level = 0;"),
@@ -111,7 +117,8 @@ def _battery():
                 ("fp32", 3)),
                ("general_numpy_ff_3", pins.test_general_matches_numpy_reimplementation,
                 ("ff", 3)),
-               ("dw_bounds", pins.test_double_word_error_bounds, ())]
+               ("dw_bounds", pins.test_double_word_error_bounds, ()),
+               ("dw_cheap_bounds", pins.test_cheap_double_word_error_bounds, ())]
     checks += [("pixels_%s_%d_%d" % (d, case, deg), pins.test_render_pixels_matches_whole_images,
                 (d, case, deg))
                for d, case, deg in (("fp64", 0, 2), ("fp32", 1, 2), ("ff", 0, 3), ("fp64", 1, 5))]

@@ -417,6 +417,34 @@ def test_double_word_error_bounds():
         assert ph == _f32(ph + pl)
 
 
+def test_cheap_double_word_error_bounds():
+    """The quadratic map's float-float square and sum.  Square: relative
+    error below 4u^2 (3u^2 from rounding h^2's error plus 2hl, u^2 from the
+    dropped l^2).  Sum: relative error below 3u^2 for operands of one sign;
+    under cancellation the error stays below 3u^2 of |x| + |y| (an absolute
+    bound: the relative one is lost there).  Results normalised."""
+    rng = np.random.default_rng(6)
+    u = Fraction(1, 2 ** 24)
+    for _ in range(3000):
+        x, y = _dw(rng), _dw(rng)
+        X = Fraction(x[0]) + Fraction(x[1])
+        sh, sl = oracle.dw_sqr(x)
+        assert abs(Fraction(sh) + Fraction(sl) - X * X) <= 4 * u * u * X * X
+        assert sh == _f32(sh + sl)
+        if rng.uniform() < 0.3:  # heavy cancellation
+            y = (-x[0], _f32(-x[1] + x[0] * 2.0 ** -30 * rng.uniform(-1, 1)))
+        elif rng.uniform() < 0.5:  # one sign
+            if (x[0] > 0) != (y[0] > 0):
+                y = (-y[0], -y[1])
+        Y = Fraction(y[0]) + Fraction(y[1])
+        zh, zl = oracle.dw_add_cheap(x, y)
+        err = abs(Fraction(zh) + Fraction(zl) - (X + Y))
+        if X * Y > 0:
+            assert err <= 3 * u * u * abs(X + Y)
+        assert err <= 3 * u * u * (abs(X) + abs(Y))
+        assert zh == _f32(zh + zl)
+
+
 def test_split():
     rng = np.random.default_rng(9)
     for v in rng.uniform(-2, 2, 500):
