@@ -123,7 +123,13 @@ struct ArF32 {
 // Float-float: value = hi + lo.  TwoSum (Knuth), Fast2Sum (Dekker), FMA-based
 // TwoProd, and the double-word sum and product of Joldes, Muller and Popescu
 // (ACM TOMS 2017): accurate double-word + double-word (error < 3u^2) and
-// FMA double-word x double-word (error < 4u^2), u = 2^-24.
+// FMA double-word x double-word (error < 4u^2), u = 2^-24.  The quadratic
+// map's iteration uses two cheaper forms: the square (TwoProd of the high
+// word plus one fused 2*hi*lo term, the lo*lo term dropped: error < 4u^2)
+// and the "sloppy" sum (TwoSum of the high words, the low words added to its
+// error, one Fast2Sum: error < 3u^2 of the result for operands of one sign,
+// < 3u^2 of |a| + |b| otherwise).  The escape test sums the two squares,
+// which are of one sign, so it keeps the relative bound.
 struct ArFF {
     static constexpr bool kRational = false;
     struct D { float hi, lo; };
@@ -152,6 +158,23 @@ struct ArFF {
         quick_two_sum(v, w, r.hi, r.lo);
         return r;
     }
+    __device__ static D add_cheap(D a, D b) {
+        float s, se;
+        two_sum(a.hi, b.hi, s, se);
+        float lows = a.lo + b.lo;
+        float err = se + lows;
+        D r;
+        quick_two_sum(s, err, r.hi, r.lo);
+        return r;
+    }
+    __device__ static D sqr(D a) {
+        float p = a.hi * a.hi;
+        float pe = __builtin_fmaf(a.hi, a.hi, -p);
+        float q = __builtin_fmaf(a.hi + a.hi, a.lo, pe);
+        D r;
+        quick_two_sum(p, q, r.hi, r.lo);
+        return r;
+    }
     __device__ static D mul(D a, D b) {
         float p = a.hi * b.hi;
         float pe = __builtin_fmaf(a.hi, b.hi, -p);
@@ -176,27 +199,27 @@ struct ArFF {
     __device__ static C cmake(V r, V i) { return C{r, i}; }
     __device__ static bool le4(D m) { return (m.hi < 4.0f) || (m.hi == 4.0f && m.lo <= 0.0f); }
     __device__ static bool inside(const Z& z, const C&, int) {
-        return le4(add(mul(z.x, z.x), mul(z.y, z.y)));
+        return le4(add_cheap(sqr(z.x), sqr(z.y)));
     }
     __device__ static void advance(Z& z, const C& c, D x2, D y2) {
         D ny2 = D{-y2.hi, -y2.lo};
-        D re = add(x2, ny2);
-        D xn = add(re, c.r);
+        D re = add_cheap(x2, ny2);
+        D xn = add_cheap(re, c.r);
         D tx = D{z.x.hi + z.x.hi, z.x.lo + z.x.lo};  // 2x, exact
         D im = mul(tx, z.y);
-        D yn = add(im, c.i);
+        D yn = add_cheap(im, c.i);
         z.x = xn;
         z.y = yn;
     }
     __device__ static void step(Z& z, const C& c, int) {
-        D x2 = mul(z.x, z.x);
-        D y2 = mul(z.y, z.y);
+        D x2 = sqr(z.x);
+        D y2 = sqr(z.y);
         advance(z, c, x2, y2);
     }
     __device__ static bool check_step(Z& z, const C& c, int) {
-        D x2 = mul(z.x, z.x);
-        D y2 = mul(z.y, z.y);
-        bool ok = le4(add(x2, y2));
+        D x2 = sqr(z.x);
+        D y2 = sqr(z.y);
+        bool ok = le4(add_cheap(x2, y2));
         advance(z, c, x2, y2);
         return ok;
     }
@@ -207,7 +230,8 @@ struct ArFF {
 // (a + ib)(x + iy) taken as (a x - b y) + i (a y + b x) with every operation
 // rounded, then C is added.  FP64 and FP32 round each operation in their own
 // precision (no fused operations; escape test fl(fl(x x) + fl(y y)) > 4);
-// float-float uses the double-word product and sum throughout.  The degree is
+// float-float uses the accurate double-word product and sum throughout (its
+// escape test too).  The degree is
 // the same for every lane of a wave (it is part of the stream variant), so the
 // product loop does not diverge.
 struct ArF64G : ArF64 {
@@ -266,6 +290,9 @@ struct ArF32G : ArF32 {
 };
 
 struct ArFFG : ArFF {
+    __device__ static bool inside(const Z& z, const C&, int) {
+        return le4(add(mul(z.x, z.x), mul(z.y, z.y)));
+    }
     __device__ static void power_add(Z& z, const C& c, int d) {
         D wr = z.x, wi = z.y;
 #pragma unroll 1
