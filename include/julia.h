@@ -363,6 +363,33 @@ int jr_plan_replay(jr_plan *plan, void *stream);
  * valid while launches that use it are in flight.
  */
 int jr_plan_set_palette(jr_plan *plan, const uint32_t *palette, int32_t palette_len);
+/*
+ * Progress of a plan's launches: per-frame done counters and a stop flag, the
+ * bookkeeping of the long batches of Section 3 (parameter paths and zooms of
+ * many frames), so that a launch stopped early leaves a record of which
+ * frames are complete and a caller re-renders only the others.
+ *   done   device memory, one int32 per frame of the plan, done[k] for frame k
+ *          of the list given to jr_plan_create (frame k of the path for a
+ *          cardioid plan), caller-owned, valid while launches that use it are
+ *          in flight.  Each launch first
+ *          zeroes it (a kernel, in stream order, so a captured graph does too),
+ *          then adds each tile's pixel count to its frame's counter once all
+ *          of the tile's pixels are stored.  Frame f is complete when
+ *          done[f] == width * (row_end - row_begin) of its descriptor.
+ *   stop   NULL, or an int32 flag the kernel reads (device memory, or pinned
+ *          host memory from hipHostMalloc) before each tile it claims: while
+ *          it is nonzero, waves claim no further tiles and exit.  Tiles already
+ *          claimed are finished and counted, so a stopped launch leaves whole
+ *          tiles and exact counters; the pixels of incomplete frames are
+ *          partly written.  Requires done.
+ * done NULL (with stop NULL) turns progress off.  Only plans whose schedule
+ * runs the rows or plain kernel count progress; others return JR_EINVAL.  A
+ * graph captured earlier is discarded (capture again).  A counting launch
+ * runs a kernel variant that holds every map and dtype plus the progress
+ * code, and adds one atomic per tile; launches without progress run variants
+ * that hold none of it.
+ */
+int jr_plan_set_progress(jr_plan *plan, int32_t *done, const int32_t *stop);
 /* Number of tiles of the plan and the workgroups it launches (for
  * accounting): one per tile where the rows kernel runs one wave per tile. */
 int jr_plan_info(const jr_plan *plan, int64_t *tiles, int32_t *workgroups);

@@ -124,7 +124,7 @@ EXPORTS = (
     "julia_render", "julia_render_plain", "mandelbrot_render", "mandelbrot_render_plain",
     "julia_render_batch", "julia_render_batch_noalloc", "julia_render_batch_colored",
     "julia_render_colored", "julia_render_cardioid_path", "jr_plan_create_cardioid",
-    "jr_plan_create", "jr_plan_set_palette", "jr_set_image_schedule", "jr_get_image_schedule",
+    "jr_plan_create", "jr_plan_set_palette", "jr_plan_set_progress", "jr_set_image_schedule", "jr_get_image_schedule",
     "jr_clear_image_schedules", "jr_plan_launch", "jr_plan_capture",
     "jr_plan_replay", "jr_plan_info", "jr_plan_destroy", "jr_get_default_schedule",
     "jr_set_default_schedule", "jr_check_schedule", "jr_check_frames", "jr_strerror",
@@ -175,6 +175,8 @@ def _load():
     lib.julia_render_colored.restype = ctypes.c_int
     lib.jr_plan_set_palette.argtypes = [vp, vp, i32]
     lib.jr_plan_set_palette.restype = ctypes.c_int
+    lib.jr_plan_set_progress.argtypes = [vp, vp, vp]
+    lib.jr_plan_set_progress.restype = ctypes.c_int
     lib.jr_set_image_schedule.argtypes = [i32, i32, i64, P(jr_schedule)]
     lib.jr_set_image_schedule.restype = ctypes.c_int
     lib.jr_get_image_schedule.argtypes = [i32, i32, i64, P(jr_schedule)]
@@ -540,6 +542,7 @@ class Plan:
                                            self.arena.numel(), sched, ctypes.byref(h)))
         self._h = h
         self.views = [self.arena[o: o + px].view(path.height, path.width) for o in self.offsets]
+        self.frame_pixels = [px] * path.frames
         return self
 
     def __init__(self, frames: Sequence, schedule: Optional[Schedule] = None, arena=None,
@@ -563,6 +566,7 @@ class Plan:
         self._h = h
         self.views = [self.arena[o: o + f.width * f.height].view(f.height, f.width)
                       for o, f in zip(self.offsets, self.frames)]
+        self.frame_pixels = [f.width * f.height for f in self.frames]
 
     def launch(self, stream=None):
         _check(lib.jr_plan_launch(self._h, _stream_ptr(stream)))
@@ -583,6 +587,33 @@ class Plan:
             pp, plen = _palette_ptr(palette)
             _check(lib.jr_plan_set_palette(self._h, pp, plen))
         self.palette = palette  # keep the table alive while the plan may use it
+
+    def set_progress(self, done=None, stop=None):
+        """Per-frame done counters and a stop flag for later launches
+        (jr_plan_set_progress): ``done`` an int32 CUDA tensor of one counter
+        per frame, ``stop`` None or an int32 tensor of one element (on the
+        device, or pinned host memory that the host may set while a launch
+        runs).  None, None turns progress off.  A captured graph is dropped."""
+        import torch
+        for t, name, n in ((done, "done", len(self.frame_pixels)), (stop, "stop", 1)):
+            if t is None:
+                continue
+            if t.dtype != torch.int32 or not t.is_contiguous() or t.numel() < n:
+                raise ValueError("%s: a contiguous int32 tensor of at least %d elements" % (name, n))
+            if name == "done" and not t.is_cuda:
+                raise ValueError("done: a device tensor")
+            if name == "stop" and not (t.is_cuda or t.is_pinned()):
+                raise ValueError("stop: a device tensor or pinned host memory")
+        _check(lib.jr_plan_set_progress(self._h,
+                                        None if done is None else ctypes.c_void_p(done.data_ptr()),
+                                        None if stop is None else ctypes.c_void_p(stop.data_ptr())))
+        self.progress = (done, stop)  # keep them alive while launches may use them
+
+    def incomplete(self, done):
+        """Indices of the frames whose counter (host copy of ``done``) falls
+        short of their pixel count."""
+        d = [int(v) for v in done]
+        return [k for k, px in enumerate(self.frame_pixels) if d[k] != px]
 
     def info(self):
         t, w = ctypes.c_int64(), ctypes.c_int32()

@@ -31,7 +31,8 @@ struct alignas(16) DevFrame {
     int32_t tile_w, tile_h;
     int32_t degree;          // map Z^degree + C (2: the quadratic map)
     int32_t map;             // kMapPoly, or kMapRational: Z^degree + C + lambda / Z^degree
-    int32_t reserved[3];
+    int32_t index;           // the frame's position in the caller's list (progress counters)
+    int32_t reserved[2];
 };
 static_assert(sizeof(DevFrame) == 144, "DevFrame layout");
 
@@ -62,6 +63,11 @@ struct PersistentArgs {
                          // this many of its pixels are still inside
     int32_t palette_len; // > 0: a pixel stores palette[min(count, palette_len - 1)]
     const uint32_t* palette;
+    // Progress (rows and plain kernels; both null otherwise): done[f] gains
+    // the pixel count of each tile of frame f once all of them are stored;
+    // a nonzero *stop makes waves claim no further tiles.
+    int32_t* done;
+    const int32_t* stop;
 };
 
 // Largest colour table of the fused colour store; it is staged in LDS.
@@ -86,6 +92,10 @@ constexpr int kGeneralBit = 16;
 // Kernel variants (rows and plain kernels only) that also hold the rational
 // maps Z^d + C + lambda / Z^d; they carry kGeneralBit too.
 constexpr int kRationalBit = 32;
+// Kernel variants (rows and plain kernels, every map and dtype) that keep
+// progress: the stop flag and the per-frame done counters.  Launches without
+// progress run variants that hold no progress code at all.
+constexpr int kProgressBit = 64;
 
 struct PlainArgs {
     int32_t* out;
@@ -117,6 +127,9 @@ struct CardioidArgs {
     int32_t frames;
 };
 hipError_t launch_cardioid_table(const CardioidArgs& g, hipStream_t stream);
+// Zeroes n int32 words with a kernel (not a memset, so that it can sit in a
+// captured hipGraph).
+hipError_t launch_zero_words(int32_t* p, int64_t n, hipStream_t stream);
 
 // Runs the tiled kernel; in persistent mode a small kernel zeroes the queue
 // counters first (both may be captured into a hipGraph).

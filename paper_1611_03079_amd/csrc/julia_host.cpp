@@ -373,6 +373,7 @@ void build_rows(const jr_frame* frames, int32_t n, const jr_schedule& s, DevFram
     for (int32_t k = 0; k < n; ++k) {
         const jr_frame& f = frames[idx[k]];
         const int64_t tiles = fill_frame(f, s, t.total_tiles, rows[k]);
+        rows[k].index = idx[k];
         account(t, f, rows[k], tiles);
     }
 }
@@ -801,6 +802,7 @@ struct jr_plan {
     DevFrame* d_table = nullptr;
     unsigned long long* d_ctr = nullptr;
     int64_t total_tiles = 0;
+    int32_t nframes = 0;
     int dtmask = 0;
     int unroll = 1, defer = 0, blocks = 1, kernel = JR_KERNEL_TILED;
     jr::PersistentArgs args;
@@ -948,6 +950,7 @@ int jr_plan_create_cardioid(const jr_cardioid_path* path, int32_t* out_base,
     TableStats t;
     p->gen = cardioid_args(*path, s, p->d_table, t);
     p->generated = true;
+    p->nframes = path->frames;
     p->total_tiles = t.total_tiles;
     p->dtmask = t.dtmask;
     p->unroll = s.unroll;
@@ -997,6 +1000,7 @@ int jr_plan_create(const jr_frame* frames, int32_t n, int32_t* out_base, int64_t
     route_rational(t, s);
     jr_plan* p = new jr_plan();
     p->dev = dev;
+    p->nframes = n;
     p->total_tiles = t.total_tiles;
     p->dtmask = t.dtmask;
     p->unroll = s.unroll;
@@ -1021,6 +1025,10 @@ int jr_plan_create(const jr_frame* frames, int32_t n, int32_t* out_base, int64_t
 static hipError_t plan_enqueue(const jr_plan* p, hipStream_t stream) {
     if (p->generated) {
         hipError_t e = jr::launch_cardioid_table(p->gen, stream);
+        if (e != hipSuccess) return e;
+    }
+    if (p->args.done) {
+        hipError_t e = jr::launch_zero_words(p->args.done, p->nframes, stream);
         if (e != hipSuccess) return e;
     }
     return p->kernel == JR_KERNEL_PLAIN
@@ -1084,6 +1092,31 @@ int jr_plan_set_palette(jr_plan* p, const uint32_t* palette, int32_t palette_len
     }
     p->args.palette = palette;
     p->args.palette_len = palette_len;
+    return JR_OK;
+}
+
+int jr_plan_set_progress(jr_plan* p, int32_t* done, const int32_t* stop) {
+    if (!p) return fail(JR_EINVAL, "plan is null");
+    if ((done || stop) && p->kernel != JR_KERNEL_ROWS && p->kernel != JR_KERNEL_PLAIN)
+        return fail(JR_EINVAL, "progress counters need the rows or plain kernel (plan has %s)",
+                    p->kernel == JR_KERNEL_HYBRID ? "hybrid" : "tiled");
+    if (stop && !done) return fail(JR_EINVAL, "a stop flag needs done counters");
+    if (done) {
+        int rc = check_out(done, "jr_plan_set_progress (done)");
+        if (!rc && stop) rc = check_out(stop, "jr_plan_set_progress (stop)");
+        if (rc) return rc;
+    }
+    if (p->exec) {
+        // The captured launch carries the old pointers in its arguments.
+        HIP_TRY(hipGraphExecDestroy(p->exec), "hipGraphExecDestroy");
+        p->exec = nullptr;
+    }
+    if (p->graph) {
+        HIP_TRY(hipGraphDestroy(p->graph), "hipGraphDestroy");
+        p->graph = nullptr;
+    }
+    p->args.done = done;
+    p->args.stop = stop;
     return JR_OK;
 }
 

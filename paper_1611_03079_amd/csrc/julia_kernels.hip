@@ -573,6 +573,26 @@ __device__ __forceinline__ int64_t next_tile(Claimer& cl, const PersistentArgs& 
 typedef const __attribute__((address_space(4))) DevFrame CFrame;
 typedef const __attribute__((address_space(4))) char CByte;
 
+// Progress of a launch (rows and plain kernels).  A wave reads the stop flag
+// before it claims a tile; the host may write the flag while the kernel runs
+// (pinned host memory or device memory), so the load is a system-scope
+// atomic, and the wave acts on lane 0's value.
+__device__ __forceinline__ bool stop_requested(const int32_t* stop) {
+    if (stop == nullptr) return false;
+    const int v = __hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    return __builtin_amdgcn_readfirstlane(v) != 0;
+}
+
+// Adds `pixels` to a frame's counter once the wave's stores are done (the
+// release fence orders them first: a reader that sees the count sees the
+// pixels); one active lane adds.
+__device__ __forceinline__ void add_done(int32_t* slot, int pixels) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const uint64_t active = __ballot(true);
+    if (lane_id() == __builtin_ctzll(active))
+        __hip_atomic_fetch_add(slot, pixels, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // A frame's constant in the arithmetic A (C, and lambda for the rational maps).
 template <class A>
 __device__ __forceinline__ typename A::C frame_c(CFrame& F) {
@@ -1096,6 +1116,8 @@ __global__ __launch_bounds__(256) void jr_plain_batch(PersistentArgs a) {
         f = find_frame(frames, a.nframes, t, frames[guess].tile_begin <= t ? guess : 0);
     }
     CFrame& F = frames[f];
+    constexpr bool kProgress = (DTMASK & kProgressBit) != 0;
+    if (kProgress && stop_requested(a.stop)) return;
     const uint32_t local = (uint32_t)(t - F.tile_begin);
     const int ty = (int)(local / (uint32_t)F.tiles_x);
     const int tx = (int)(local - (uint32_t)ty * (uint32_t)F.tiles_x);
@@ -1121,6 +1143,8 @@ __global__ __launch_bounds__(256) void jr_plain_batch(PersistentArgs a) {
         plain_pixel<ArF64, COLOR>(a, F, i, j, out);
     else if ((DTMASK & (1 << kFF)) && F.dtype == kFF)
         plain_pixel<ArFF, COLOR>(a, F, i, j, out);
+    // each wave counts its own stored pixels (its lanes inside the frame)
+    if (kProgress && a.done) add_done(a.done + F.index, __popcll(__ballot(true)));
 }
 
 // ---------------------------------------------------------------------------
@@ -1221,7 +1245,8 @@ __device__ __forceinline__ CArgs& kernel_args() {
 }
 
 template <class A, int K, int MANDEL, int COLOR, int LROWS, int DD, class Args>
-__device__ void rows_tile(const Args& a, CFrame& F, int64_t t, int P, uint32_t* list) {
+__device__ void rows_tile(const Args& a, CFrame& F, int64_t t, int P, uint32_t* list,
+                          int32_t* done_at) {
     constexpr int cap = 64 * LROWS;  // list entries
     // deferred drain blocks need escape to be absorbing (K > 1 means it is)
     constexpr bool kDeferDrain = DD != 0 && K > 1;
@@ -1462,6 +1487,7 @@ __device__ void rows_tile(const Args& a, CFrame& F, int64_t t, int P, uint32_t* 
         finish_row(r, lead, z, done);
     }
     drain();
+    if (done_at) add_done(done_at, tw * th);  // the frame's progress counter
 }
 
 // Waves of 64 lanes, one tile at a time (from the dispatcher or the work
@@ -1486,7 +1512,11 @@ __global__ __launch_bounds__(64 * WPB) void jr_rows(PersistentArgs a) {
     CFrame* frames = cframes(a);
     CArgs& ka = kernel_args();
     int f = 0;
-    for (int64_t t = next_tile(cl, a); t >= 0; t = next_tile(cl, a)) {
+    constexpr bool kProgress = (DTMASK & kProgressBit) != 0;
+    for (;;) {
+        if (kProgress && stop_requested(a.stop)) break;
+        const int64_t t = next_tile(cl, a);
+        if (t < 0) break;
         f = find_frame(frames, a.nframes, t, f);
         CFrame& F = frames[f];
         const bool abs = F.defer != 0;
@@ -1497,12 +1527,13 @@ __global__ __launch_bounds__(64 * WPB) void jr_rows(PersistentArgs a) {
         // may keep the trip count in a vector register.
         const int P = __builtin_amdgcn_readfirstlane(abs ? (a.bail + 3) & ~3 : 1);
         const bool mandel = F.mode == kModeMandelbrot;
+        int32_t* const done_at = kProgress && a.done ? a.done + F.index : nullptr;
 #define JR_ROWS(A_, ARGS_)                                                               \
     do {                                                                                 \
-        if (abs && !mandel) rows_tile<A_, K, 0, COLOR, S::rows, DD>(ARGS_, F, t, P, list); \
-        else if (abs) rows_tile<A_, K, 1, COLOR, S::rows, DD>(ARGS_, F, t, P, list);       \
-        else if (!mandel) rows_tile<A_, 1, 0, COLOR, S::rows, 0>(ARGS_, F, t, P, list);    \
-        else rows_tile<A_, 1, 1, COLOR, S::rows, 0>(ARGS_, F, t, P, list);                 \
+        if (abs && !mandel) rows_tile<A_, K, 0, COLOR, S::rows, DD>(ARGS_, F, t, P, list, done_at); \
+        else if (abs) rows_tile<A_, K, 1, COLOR, S::rows, DD>(ARGS_, F, t, P, list, done_at);       \
+        else if (!mandel) rows_tile<A_, 1, 0, COLOR, S::rows, 0>(ARGS_, F, t, P, list, done_at);    \
+        else rows_tile<A_, 1, 1, COLOR, S::rows, 0>(ARGS_, F, t, P, list, done_at);                 \
     } while (0)
         // quadratic maps: kernels that also hold the general maps call tiles
         // that are not inlined, which take the arguments in place
@@ -1516,8 +1547,8 @@ __global__ __launch_bounds__(64 * WPB) void jr_rows(PersistentArgs a) {
         // rational maps: Julia images in FP64 or FP32 (the host checks)
 #define JR_ROWS_R(A_)                                                              \
     do {                                                                           \
-        if (abs) rows_tile<A_, K, 0, COLOR, S::rows, DD>(ka, F, t, P, list);      \
-        else rows_tile<A_, 1, 0, COLOR, S::rows, 0>(ka, F, t, P, list);           \
+        if (abs) rows_tile<A_, K, 0, COLOR, S::rows, DD>(ka, F, t, P, list, done_at);      \
+        else rows_tile<A_, 1, 0, COLOR, S::rows, 0>(ka, F, t, P, list, done_at);           \
     } while (0)
         if ((DTMASK & kRationalBit) && F.map == kMapRational) {
             if (F.dtype == kFP32)
@@ -1541,6 +1572,12 @@ __global__ __launch_bounds__(64 * WPB) void jr_rows(PersistentArgs a) {
 #undef JR_ROWS_R
 #undef JR_ROWS_Q
     }
+}
+
+// Zeroes n words (progress counters) before a launch that counts.
+__global__ __launch_bounds__(256) void jr_zero_words(int32_t* p, int64_t n) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k < n) p[k] = 0;
 }
 
 // Zeroes the kQueues counters before a persistent launch (a kernel, not a
@@ -1590,6 +1627,7 @@ __global__ __launch_bounds__(256) void jr_cardioid_table(CardioidArgs g) {
     f.ci = ni / a;
     f.out_offset = g.out_offset0 + (int64_t)k * g.frame_px;
     f.tile_begin = (int64_t)k * g.tiles_per_frame;
+    f.index = (int32_t)k;
     g.dst[k] = f;
 }
 
@@ -1682,6 +1720,11 @@ static TiledFn pick_rows_mask(int dtmask, bool one_wave, int defer) {
     if (defer && dtmask == (1 << kFP64))
         return one_wave ? jr_rows<K, 1 << kFP64, 1, 1> : jr_rows<K, 1 << kFP64, 4, 1>;
     constexpr int kGR = 7 | kGeneralBit | kRationalBit;
+    if (dtmask & kProgressBit) {  // any frames, counted
+        constexpr int kGRP = kGR | kProgressBit;
+        if (dtmask & kColorBit) return jr_rows<K, kGRP | kColorBit, 4, 0>;
+        return one_wave ? jr_rows<K, kGRP, 1, 0> : jr_rows<K, kGRP, 4, 0>;
+    }
     if (dtmask & kRationalBit) {
         if (dtmask & kColorBit) return jr_rows<K, kGR | kColorBit, 4, 0>;
         return one_wave ? jr_rows<K, kGR, 1, 0> : jr_rows<K, kGR, 4, 0>;
@@ -1722,6 +1765,10 @@ static TiledFn pick(int unroll, int defer, int dtmask, int hybrid) {
 }
 
 static TiledFn pick_plain(int dtmask) {
+    if (dtmask & kProgressBit)
+        return (dtmask & kColorBit)
+                   ? jr_plain_batch<7 | kGeneralBit | kRationalBit | kProgressBit | kColorBit>
+                   : jr_plain_batch<7 | kGeneralBit | kRationalBit | kProgressBit>;
     if (dtmask & kRationalBit)
         return (dtmask & kColorBit) ? jr_plain_batch<7 | kGeneralBit | kRationalBit | kColorBit>
                                     : jr_plain_batch<7 | kGeneralBit | kRationalBit>;
@@ -1747,6 +1794,7 @@ hipError_t launch_plain_batch(int dtmask, const PersistentArgs& args, hipStream_
     if (args.palette_len > kPaletteMax) return hipErrorInvalidValue;
     if (args.total_tiles > 0x7fffffffLL) return hipErrorInvalidValue;
     if (args.palette_len > 0) dtmask |= kColorBit;
+    if (args.done) dtmask |= kProgressBit;
     hipLaunchKernelGGL(pick_plain(dtmask), dim3((unsigned)args.total_tiles), dim3(256),
                        palette_bytes(args), stream, args);
     return hipGetLastError();
@@ -1758,8 +1806,9 @@ hipError_t launch_plain_batch(int dtmask, const PersistentArgs& args, hipStream_
 // four waves stage the palette once).
 static bool one_wave_launch(int dtmask, const PersistentArgs& args) {
     if (args.palette_len > 0) dtmask |= kColorBit;
+    // (the counting kernels' colour variant has four-wave workgroups)
     const bool small_palette = dtmask == ((1 << kFP32) | kColorBit) &&
-                               args.palette_len <= kOneWavePalette;
+                               args.palette_len <= kOneWavePalette && !args.done;
     return args.rows && !args.persistent && (!(dtmask & kColorBit) || small_palette) &&
            args.total_tiles <= 0x7fffffffLL;
 }
@@ -1774,6 +1823,10 @@ hipError_t launch_tiled(int unroll, int defer, int dtmask, int blocks, const Per
     blocks = launch_workgroups(dtmask, args, blocks);
     if (args.palette_len > 0) dtmask |= kColorBit;
     const unsigned threads = one_wave ? 64u : 256u;
+    if (args.done) {
+        if (!args.rows) return hipErrorInvalidValue;  // progress: rows and plain kernels
+        dtmask |= kProgressBit;
+    }
     TiledFn fn = args.rows ? pick_rows(unroll, dtmask, one_wave, defer)
                            : pick(unroll, defer, dtmask, args.hybrid);
     if (!fn || args.palette_len > kPaletteMax) return hipErrorInvalidValue;
@@ -1809,6 +1862,14 @@ hipError_t launch_cardioid_table(const CardioidArgs& g, hipStream_t stream) {
     if (g.frames < 1) return hipErrorInvalidValue;
     const unsigned blocks = (unsigned)((g.frames + 255) / 256);
     hipLaunchKernelGGL(jr_cardioid_table, dim3(blocks), dim3(256), 0, stream, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_words(int32_t* p, int64_t n, hipStream_t stream) {
+    if (n < 1 || p == nullptr) return hipErrorInvalidValue;
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(jr_zero_words, dim3((unsigned)blocks), dim3(256), 0, stream, p, n);
     return hipGetLastError();
 }
 

@@ -19,7 +19,14 @@ zooms).  This loop serves a stream of such requests on one GPU:
     others run overlaps with them on the device;
   * a request completes when the step holding its last rows has finished; its
     counts are copied out of the arena and the arena range is freed;
-  * latency = completion time - arrival time; p50/p99 and throughput are kept.
+  * latency = completion time - arrival time; p50/p99 and throughput are kept;
+  * failures stay with their requests: a request may carry a deadline (it
+    fails with DeadlineExceeded once the deadline passes before its last rows
+    are rendered, and its remaining rows are not rendered), a cancelled
+    Future's rows stop being scheduled, a full queue refuses new requests
+    with Overloaded, and a launch that raises fails only the requests of that
+    step.  An abandoned request's arena range is freed once no step in
+    flight still writes into it.
 
 The arithmetic of each frame is picked by a precision policy from its window
 width and cap.  Scheduling never changes a count, so every result equals the
@@ -33,7 +40,15 @@ from concurrent.futures import Future
 from dataclasses import dataclass, field
 from typing import Deque, Dict, List, Optional
 
-DTYPE_COST = {"fp32": 1.0, "fp64": 1.75, "ff": 20.0}
+DTYPE_COST = {"fp32": 1.0, "fp64": 1.75, "ff": 10.0}
+
+
+class DeadlineExceeded(TimeoutError):
+    """The request's deadline passed before its image was rendered."""
+
+
+class Overloaded(RuntimeError):
+    """The server's queue was full when the request arrived."""
 
 
 @dataclass
@@ -135,6 +150,9 @@ class _Req:
     next_row: int = 0
     last_step: int = -1      # step that holds the frame's last rows
     done_rows: int = 0
+    deadline: float = math.inf
+    launched: int = 0        # steps in flight that hold some of its rows
+    dead: bool = False       # abandoned: expired, cancelled or failed
 
 
 @dataclass
@@ -147,6 +165,10 @@ class Stats:
     latencies: List[float] = field(default_factory=list)
     unfinished: List[float] = field(default_factory=list)
     completed: int = 0
+    expired: int = 0         # failed with DeadlineExceeded
+    cancelled: int = 0       # cancelled by the client before completion
+    failed: int = 0          # failed by a launch that raised
+    refused: int = 0         # refused at submission (full queue)
     pixels: int = 0
     steps: int = 0
     t_first: float = math.inf
@@ -235,8 +257,13 @@ class Server:
     def __init__(self, backend, arena_elements: int, step_budget: Optional[float] = None,
                  max_inflight: int = 2, policy: Optional[PrecisionPolicy] = None,
                  copy_out: bool = True, schedule=None, step_target_s: float = 2e-3,
-                 rate: Optional[StepRate] = None, keep_log: bool = False):
+                 rate: Optional[StepRate] = None, keep_log: bool = False,
+                 max_queue: Optional[int] = None, timeout_s: Optional[float] = None):
         self.b = backend
+        # requests waiting for admission beyond this many are refused
+        self.max_queue = max_queue
+        # default deadline of a request: its arrival plus this many seconds
+        self.timeout_s = timeout_s
         self.alloc = ArenaAllocator(arena_elements)
         # a fixed budget (cost units per step), or None: step_target_s times
         # the learnt rate
@@ -262,7 +289,11 @@ class Server:
         self._thread = None
 
     # ------------------------------------------------------------- client side
-    def submit(self, frame, arrival: Optional[float] = None) -> Future:
+    def submit(self, frame, arrival: Optional[float] = None,
+               deadline: Optional[float] = None) -> Future:
+        """Queue a request.  ``deadline``: time on the backend's clock by
+        which the image must be rendered (default: arrival + timeout_s, or
+        none); past it the Future fails with DeadlineExceeded."""
         fut = Future()
         if frame.width * frame.height > self.alloc.capacity:
             fut.set_exception(ValueError("frame larger than the output arena"))
@@ -270,10 +301,16 @@ class Server:
         if getattr(frame, "dtype", None) in (None, "auto"):
             w = frame.window[1] - frame.window[0]
             frame.dtype = self.policy.pick(w, frame.max_iter)
+        t = self.b.now() if arrival is None else arrival
+        if deadline is None:
+            deadline = math.inf if self.timeout_s is None else t + self.timeout_s
         with self.lock:
+            if self.max_queue is not None and len(self.queue) >= self.max_queue:
+                self.stats.refused += 1
+                fut.set_exception(Overloaded("%d requests already waiting" % len(self.queue)))
+                return fut
             self._rid += 1
-            self.queue.append(_Req(self._rid, frame, self.b.now() if arrival is None else arrival,
-                                   fut))
+            self.queue.append(_Req(self._rid, frame, t, fut, deadline=deadline))
         return fut
 
     def pending(self) -> int:
@@ -284,17 +321,79 @@ class Server:
         """Record every request still pending at time t as unfinished, with
         the latency it has accumulated by t (the run is over)."""
         with self.lock:
-            waiting = list(self.queue) + list(self.active)
+            waiting = list(self.queue) + [r for r in self.active if not r.dead]
         for r in waiting:
             self.stats.unfinished.append(t - r.arrival)
             self.stats.t_first = min(self.stats.t_first, r.arrival)
 
     # ------------------------------------------------------------- scheduler
+    def _abandon(self, r: _Req, exc: Optional[BaseException]):
+        """Stop rendering r: fail its Future with exc (None: it was cancelled)
+        and free its arena range once no step in flight writes into it."""
+        if r.dead:
+            return
+        r.dead = True
+        if exc is None:
+            self.stats.cancelled += 1
+        else:
+            if isinstance(exc, DeadlineExceeded):
+                self.stats.expired += 1
+            else:
+                self.stats.failed += 1
+            if not r.future.done():
+                r.future.set_exception(exc)
+        self._reap(r)
+
+    def _reap(self, r: _Req):
+        if r.dead and r.launched == 0 and r.offset >= 0:
+            n = r.frame.width * r.frame.height
+            discard = getattr(self.b, "discard", None)
+            if discard is not None:
+                discard(r.offset, n)
+            with self.lock:
+                if r in self.active:
+                    self.active.remove(r)
+                self.alloc.release(r.offset, n)
+            r.offset = -1
+
+    def _expire(self):
+        """Drop queued requests that were cancelled or are past their
+        deadline; abandon admitted ones likewise (unless their last rows are
+        already rendered and being copied out)."""
+        with self.lock:
+            timed = any(r.deadline < math.inf for r in self.queue) or \
+                any(r.deadline < math.inf for r in self.active)
+        now = self.b.now() if timed else -math.inf
+        with self.lock:
+            keep = collections.deque()
+            for r in self.queue:
+                if r.future.cancelled():
+                    self.stats.cancelled += 1
+                elif now > r.deadline:
+                    self.stats.expired += 1
+                    r.future.set_exception(DeadlineExceeded(
+                        "request %d: deadline passed while queued" % r.rid))
+                else:
+                    keep.append(r)
+            self.queue = keep
+            active = list(self.active)
+        fetching = {id(r) for _, r, _ in self.fetching}
+        for r in active:
+            if r.dead or id(r) in fetching or (r.next_row >= r.frame.height and r.launched == 0):
+                continue
+            if r.future.cancelled():
+                self._abandon(r, None)
+            elif now > r.deadline:
+                self._abandon(r, DeadlineExceeded(
+                    "request %d: deadline passed after %d of %d rows"
+                    % (r.rid, r.next_row, r.frame.height)))
+
     def _admit(self):
         with self.lock:
             while self.queue:
                 r = self.queue[0]
                 if r.future.cancelled():
+                    self.stats.cancelled += 1
                     self.queue.popleft()
                     continue
                 off = self.alloc.alloc(r.frame.width * r.frame.height)
@@ -320,8 +419,9 @@ class Server:
         frames, offsets, rows, ending, rids = [], [], [], [], []
         units = 0.0
         budget = self.step_budget
+        reqs = []
         for r in self.active:
-            if r.next_row >= r.frame.height:
+            if r.dead or r.next_row >= r.frame.height:
                 continue
             f = r.frame
             rc = self._row_cost(f)
@@ -330,6 +430,7 @@ class Server:
             offsets.append(r.offset)
             rows.append((r.next_row, r.next_row + take))
             rids.append(r.rid)
+            reqs.append(r)
             r.next_row += take
             if r.next_row >= f.height:
                 r.last_step = self.step_id
@@ -338,28 +439,39 @@ class Server:
             units += take * rc
             if budget <= 0:
                 break
-        return frames, offsets, rows, ending, rids, units
+        return frames, offsets, rows, ending, rids, units, reqs
 
     def step(self) -> bool:
         """One scheduler pass; returns True when it did anything."""
         busy = False
+        self._expire()
         self._admit()
         if len(self.inflight) < self.max_inflight:
-            frames, offsets, rows, ending, rids, units = self._build_step()
+            frames, offsets, rows, ending, rids, units, reqs = self._build_step()
             if frames:
                 sidx = self.step_id % self.max_inflight
                 t = self.b.now()
                 before = [s[0] for s in self.inflight]
-                h = self.b.launch(frames, offsets, rows, sidx, self.schedule)
+                try:
+                    h = self.b.launch(frames, offsets, rows, sidx, self.schedule)
+                except Exception as e:   # the step's requests fail; the loop goes on
+                    for r in reqs:
+                        self._abandon(r, e)
+                    return True
+                for r in reqs:
+                    r.launched += 1
                 rec = StepRecord(self.step_id, sidx, rids, units, t, before, h)
-                self.inflight.append((self.step_id, sidx, h, ending, rec))
+                self.inflight.append((self.step_id, sidx, h, ending, rec, reqs))
                 if self.keep_log:
                     self.log.append(rec)
                 self.step_id += 1
                 self.stats.steps += 1
                 busy = True
         while self.inflight and self.b.done(self.inflight[0][2]):
-            _, sidx, h, ending, rec = self.inflight.popleft()
+            _, sidx, h, ending, rec, reqs = self.inflight.popleft()
+            for r in reqs:
+                r.launched -= 1
+                self._reap(r)
             seconds = getattr(self.b, "seconds", None)
             if seconds is not None:
                 rec.seconds = seconds(h)
@@ -368,6 +480,8 @@ class Server:
                 if self.fixed_budget is None and rec.units >= 0.5 * self.step_budget:
                     self.rate.update(rec.units, rec.seconds)
             for r in ending:
+                if r.dead:
+                    continue
                 if self.copy_out:
                     h, out = self.b.fetch(r.offset, r.frame, sidx)
                 else:

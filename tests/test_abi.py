@@ -295,6 +295,12 @@ def test_colored_batch_validates_frames_and_plan_palette():
     assert "#define JR_PALETTE_MAX 8192" in open(HEADER).read()
 
 
+def test_plan_progress_rejects_a_null_plan():
+    assert jr.lib.jr_plan_set_progress(None, FAKE_OUT, None) == jr.JR_EINVAL
+    assert "plan is null" in jr.last_error()
+    assert jr.lib.jr_plan_set_progress(None, None, None) == jr.JR_EINVAL
+
+
 def test_image_schedules_pick_by_cap_and_size():
     """The per-size table of one-image calls (jr_set_image_schedule), queried
     without a device."""

@@ -51,6 +51,36 @@ def test_results_alone_equal_in_mix():
     assert len(dts) >= 2
 
 
+def test_deadlines_and_cancellation_on_the_device():
+    """A large slow request whose deadline passes while its rows are in
+    flight fails with DeadlineExceeded and stops being rendered; a cancelled
+    one likewise; the requests around them, which reuse the freed arena, equal
+    the same requests alone."""
+    from paper_1611_03079_amd.serve import DeadlineExceeded
+    import time
+    slow = Frame(complex(-0.8, 0.156), (-0.61, -0.59, 0.09, 0.11), 640, 480, 20000, "fp64")
+    slow2 = Frame(complex(-0.8, 0.156), (-0.60, -0.58, 0.10, 0.12), 640, 480, 20000, "fp64")
+    small = [r.frame for r in _stream(12, 21)]
+    cap = 2 * 640 * 480 + 2 * 320 * 240
+    b = GpuBackend(cap)
+    srv = Server(b, cap, step_budget=2e6)
+    f_slow = srv.submit(slow, deadline=time.perf_counter() + 0.002)
+    f_cancel = srv.submit(slow2)
+    futs = [srv.submit(f) for f in small[:6]]
+    for _ in range(4):
+        srv.step()
+    assert f_cancel.cancel()
+    futs += [srv.submit(f) for f in small[6:]]
+    srv.run_until_idle(timeout=100)
+    with pytest.raises(DeadlineExceeded):
+        f_slow.result(timeout=1)
+    assert f_cancel.cancelled()
+    assert srv.stats.expired == 1 and srv.stats.cancelled == 1
+    assert srv.stats.completed == len(small) and srv.alloc.used == 0
+    for f, fu in zip(small, futs):
+        np.testing.assert_array_equal(fu.result().cpu().numpy(), _alone(f))
+
+
 def test_open_loop_arrivals():
     reqs = _stream(40, 9)
     cap = 4 * 320 * 240

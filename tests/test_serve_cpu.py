@@ -8,21 +8,27 @@ import pytest
 
 import oracle
 from workloads import Frame
-from paper_1611_03079_amd.serve import ArenaAllocator, PrecisionPolicy, Server
+from paper_1611_03079_amd.serve import (ArenaAllocator, DeadlineExceeded, Overloaded,
+                                        PrecisionPolicy, Server)
 
 
 class FakeBackend:
-    def __init__(self, capacity, polls=2):
+    def __init__(self, capacity, polls=2, fail_launch=None):
         self.arena = np.full(capacity, -1, dtype=np.int32)
         self.polls = polls
         self.clock = 0.0
         self.launches = []
+        self.fail_launch = fail_launch   # index of a launch that raises
+        self.calls = 0
 
     def now(self):
         self.clock += 1.0
         return self.clock
 
     def launch(self, frames, offsets, rows, stream_idx, schedule=None):
+        self.calls += 1
+        if self.fail_launch == self.calls - 1:
+            raise RuntimeError("launch failed")
         self.launches.append([(id(f), r) for f, r in zip(frames, rows)])
         for f, o, (r0, r1) in zip(frames, offsets, rows):
             img = oracle.render(f.c, f.window, f.width, f.height, f.max_iter, f.dtype, f.mode)
@@ -40,6 +46,10 @@ class FakeBackend:
         out = self.arena[offset: offset + n].reshape(frame.height, frame.width).copy()
         self.arena[offset: offset + n] = -1   # the range may be handed out again
         return [0], out
+
+    def discard(self, offset, n):
+        """An abandoned request's range, freed without a copy."""
+        self.arena[offset: offset + n] = -1
 
 
 def frames(n, w=24, h=18):
@@ -121,6 +131,110 @@ def test_cancelled_request_is_not_rendered():
     rendered = {fid for l in b.launches for fid, _ in l}
     assert id(fr[2]) not in rendered
     assert futs[0].result() is not None and futs[1].result() is not None
+
+
+def rendered_rows(b, frame):
+    return sorted(r for l in b.launches for fid, r in l if fid == id(frame))
+
+
+def test_deadline_passes_while_queued():
+    """A request whose deadline passes before it is admitted fails with
+    DeadlineExceeded and is never rendered; the others complete."""
+    fr = frames(3)
+    b = FakeBackend(600)              # one frame at a time: the others queue
+    srv = Server(b, 600, step_budget=1e9)
+    futs = [srv.submit(f) for f in fr[:2]]
+    late = srv.submit(fr[2], deadline=b.clock + 3)
+    srv.run_until_idle(timeout=30)
+    with pytest.raises(DeadlineExceeded):
+        late.result(timeout=1)
+    assert rendered_rows(b, fr[2]) == []
+    for f, fu in zip(fr, futs):
+        np.testing.assert_array_equal(fu.result(), oracle.render(
+            f.c, f.window, f.width, f.height, f.max_iter, f.dtype))
+    assert srv.stats.expired == 1 and srv.stats.completed == 2 and srv.alloc.used == 0
+
+
+def big_frame():
+    return Frame(complex(-0.8, 0.156), (-1.5, 1.5, -1.5, 1.5), 40, 64, 100, "fp32")
+
+
+def test_deadline_passes_mid_frame():
+    """A frame split over many steps whose deadline passes part way: it fails,
+    its remaining rows are not launched, its range is freed only after its
+    last launched step has finished (no row is rendered twice when the range
+    is reused), and a frame submitted after it completes correctly."""
+    f, g = big_frame(), frames(1)[0]
+    b = FakeBackend(40 * 64 + 1000, polls=1)
+    srv = Server(b, 40 * 64 + 1000, step_budget=40 * 104 * 5)   # about 5 rows per step
+    fu = srv.submit(f, deadline=b.clock + 8)
+    for _ in range(3):
+        srv.step()
+    fg = srv.submit(g)
+    srv.run_until_idle(timeout=30)
+    with pytest.raises(DeadlineExceeded):
+        fu.result(timeout=1)
+    rows = rendered_rows(b, f)
+    assert 0 < len(rows) and rows[-1][1] < 64
+    np.testing.assert_array_equal(fg.result(), oracle.render(g.c, g.window, g.width, g.height,
+                                                             g.max_iter, g.dtype))
+    assert srv.stats.expired == 1 and srv.alloc.used == 0 and (b.arena == -1).all()
+
+
+def test_timeout_s_sets_every_deadline():
+    b = FakeBackend(600)
+    srv = Server(b, 600, step_budget=1e9, timeout_s=2.0)
+    futs = [srv.submit(f) for f in frames(3)]
+    srv.run_until_idle(timeout=30)
+    assert isinstance(futs[2].exception(timeout=1), DeadlineExceeded)
+    assert srv.stats.expired >= 1 and srv.alloc.used == 0
+
+
+def test_cancel_an_admitted_request():
+    """Cancelling a Future whose frame is part rendered stops its rows and
+    frees its range; nothing else is disturbed."""
+    f, g = big_frame(), frames(1)[0]
+    b = FakeBackend(40 * 64 + 1000, polls=1)
+    srv = Server(b, 40 * 64 + 1000, step_budget=40 * 104 * 5)
+    fu = srv.submit(f)
+    fg = srv.submit(g)
+    for _ in range(3):
+        srv.step()
+    assert fu.cancel()
+    srv.run_until_idle(timeout=30)
+    assert rendered_rows(b, f)[-1][1] < 64
+    np.testing.assert_array_equal(fg.result(), oracle.render(g.c, g.window, g.width, g.height,
+                                                             g.max_iter, g.dtype))
+    assert srv.stats.cancelled == 1 and srv.alloc.used == 0 and (b.arena == -1).all()
+
+
+def test_failed_launch_fails_only_its_requests():
+    """The second launch raises: the requests with rows in it fail with that
+    error, the loop goes on, and later requests complete."""
+    fr = frames(4, 30, 20)
+    b = FakeBackend(4000, polls=1, fail_launch=1)
+    srv = Server(b, 4000, step_budget=30 * 90 * 8)     # a few frames' rows per step
+    futs = [srv.submit(f) for f in fr]
+    srv.run_until_idle(timeout=30)
+    failed = [k for k, fu in enumerate(futs) if fu.exception(timeout=1) is not None]
+    assert failed and all(str(futs[k].exception()) == "launch failed" for k in failed)
+    for k, (f, fu) in enumerate(zip(fr, futs)):
+        if k not in failed:
+            np.testing.assert_array_equal(fu.result(), oracle.render(
+                f.c, f.window, f.width, f.height, f.max_iter, f.dtype))
+    assert srv.stats.failed == len(failed) and srv.stats.completed == 4 - len(failed)
+    assert srv.alloc.used == 0 and (b.arena == -1).all()
+
+
+def test_full_queue_refuses():
+    b = FakeBackend(600)
+    srv = Server(b, 600, max_queue=2)
+    futs = [srv.submit(f) for f in frames(3)]
+    with pytest.raises(Overloaded):
+        futs[2].result(timeout=1)
+    srv.run_until_idle(timeout=30)
+    assert futs[0].result() is not None and futs[1].result() is not None
+    assert srv.stats.refused == 1
 
 
 def test_oversized_frame_is_rejected():
