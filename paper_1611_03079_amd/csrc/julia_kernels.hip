@@ -1389,13 +1389,24 @@ __device__ void rows_tile(const Args& a, CFrame& F, int64_t t, int P, uint32_t* 
                 n = (it && !esc) ? n + K : n;
                 it = it && !esc && !capped;
             } else {
-                int lead = 0;
+                // Escape is absorbing (or K = 1): a running lane escapes in
+                // this block exactly when its last test fails, and its count
+                // is then n plus the tests it passed; a block in which no
+                // running lane escapes spends no instruction on counts.
+                bool in[K];
 #pragma unroll
-                for (int u = 0; u < K; ++u) lead += A::check_step(z, c, deg) ? 1 : 0;
-                const bool stop = (lead < K) || (n + K >= mi);
-                cnt = (it && stop) ? min(n + lead, mi) : cnt;
-                fi = fi || (it && stop);
-                it = it && !stop;
+                for (int u = 0; u < K; ++u) in[u] = A::check_step(z, c, deg);
+                const bool esc = it && !in[K - 1];
+                const bool capped = n + K >= mi;
+                if (__ballot(esc) != 0) {
+                    int lead = 0;
+#pragma unroll
+                    for (int u = 0; u < K - 1; ++u) lead += in[u] ? 1 : 0;
+                    cnt = esc ? min(n + lead, mi) : cnt;
+                }
+                cnt = (it && !esc && capped) ? mi : cnt;  // inside through the cap
+                fi = fi || esc || (it && capped);
+                it = it && !esc && !capped;
                 n += K;
             }
             running = __ballot(it);
