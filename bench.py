@@ -93,8 +93,10 @@ def measured_traffic(kernel: str, workload: str, schedule: dict):
 # counts (template arguments as rocprofv3 prints them).
 def kernel_instance(sched):
     if sched.kernel == "rows":
-        # one-wave workgroups for dispatched tiles, four waves with the queues
-        return "jr_rows<%d, 2, %d>" % (sched.unroll, 4 if sched.persistent else 1)
+        # one-wave workgroups for dispatched tiles, four waves with the queues;
+        # the last argument: deferred drain blocks
+        return "jr_rows<%d, 2, %d, %d>" % (sched.unroll, 4 if sched.persistent else 1,
+                                           1 if sched.defer else 0)
     if sched.kernel == "plain":
         return "jr_plain_batch<2>"
     return "jr_tiled<%d, %d, 2, %d>" % (sched.unroll, sched.defer, int(sched.kernel == "hybrid"))
@@ -345,7 +347,9 @@ def extra_legs(args, torch, jr, wl, frames, sched, ms_headline, iters):
         fr = wl.parameter_path(dtype=dt)
         dsched, dsrc = tuned_schedule_or_default(jr, "parameter_path_" + dt)
         plan = jr.Plan(fr, dsched)
-        ms_d, kms_d = time_plan_steps(torch, plan, 5, 1, graph=False)
+        plan.capture()
+        settle_clocks(torch, plan, 0.3)
+        ms_d, kms_d = time_plan_steps(torch, plan, 10, 2, graph=True)
         it_d = count_sum(torch, plan.views)
         info_d = plan.info()
         plan.close()
@@ -540,6 +544,9 @@ def run_leg(args, torch, jr, wl):
         dt = args.leg.rsplit("_", 1)[1]
         fr = [wl.single_4096(s, it, dt) for it in (100, 1000) for s in range(4)]
         outs = [torch.empty((f.height, f.width), dtype=torch.int32, device="cuda") for f in fr]
+        t0 = time.perf_counter()  # settle the clock, as settle_clocks does
+        while time.perf_counter() - t0 < SETTLE_S:
+            time_renders(jr, torch, fr, outs, 1, plain=args.plain)
         time_renders(jr, torch, fr, outs, args.warmup, plain=args.plain)
         ms = time_renders(jr, torch, fr, outs, args.steps, plain=args.plain)
         iters = count_sum(torch, outs)
@@ -550,7 +557,9 @@ def run_leg(args, torch, jr, wl):
         sc = jr.Schedule(kernel="plain") if args.plain else tuned_schedule_or_default(
             jr, args.leg)[0]
         plan = jr.Plan(fr, sc)
-        ms, _ = time_plan_steps(torch, plan, args.steps, args.warmup, graph=False)
+        plan.capture()
+        settle_clocks(torch, plan)
+        ms, _ = time_plan_steps(torch, plan, args.steps, args.warmup, graph=True)
         iters = count_sum(torch, plan.views)
         plan.close()
         sched = sc.__dict__ if sc else "library default"
