@@ -197,3 +197,39 @@ def test_stop_while_running_then_resume(sched):
     for k in range(0, len(frames), 3):
         samples_ok(k)
     plan.close()
+
+
+def test_counters_of_a_cardioid_plan_and_a_colour_store():
+    """A plan whose table is generated on the device counts its frames in
+    path order; a plan storing colours counts through the colour variant of
+    the progress kernels, and its colours equal the oracle's."""
+    import workloads as wl
+    g = wl.growing_cardioid_path(24, 12, 3.9, 3.6, 120, 70, 120, "fp32")
+    path = jr.CardioidPath(g.step, g.a0, g.da, g.window, g.frames, g.width, g.height,
+                           g.max_iter, g.dtype)
+    plan = jr.Plan.cardioid(path, ROWS)
+    done = torch.zeros(g.frames, dtype=torch.int32, device="cuda")
+    plan.set_progress(done)
+    plan.launch()
+    torch.cuda.synchronize()
+    assert done.cpu().tolist() == [g.width * g.height] * g.frames
+    for k in (0, 7, g.frames - 1):
+        f = Frame(oracle.cardioid_constant(g.step, g.a0, g.da, k), g.window, g.width, g.height,
+                  g.max_iter, g.dtype)
+        np.testing.assert_array_equal(plan.views[k].cpu().numpy(), oracle_image(f))
+    plan.close()
+    frames = mixed_frames()
+    palette = (np.arange(300, dtype=np.uint64) * 2654435761 % 2 ** 32).astype(np.uint32)
+    for sched in (ROWS, PLAIN):
+        plan = jr.Plan(frames, sched)
+        plan.set_palette(torch.from_numpy(palette.view(np.int32).copy()).cuda())
+        done = torch.zeros(len(frames), dtype=torch.int32, device="cuda")
+        plan.set_progress(done)
+        plan.launch()
+        torch.cuda.synchronize()
+        assert done.cpu().tolist() == [f.pixels for f in frames]
+        for k, f in enumerate(frames):
+            want = oracle.colorize(oracle_image(f), palette)
+            got = plan.views[k].cpu().numpy().view(np.uint32)
+            np.testing.assert_array_equal(got, want, err_msg="frame %d" % k)
+        plan.close()
