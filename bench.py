@@ -427,11 +427,22 @@ def extra_legs(args, torch, jr, wl, frames, sched, ms_headline, iters):
         it_s = count_sum(torch, outs)
         ms_pl = time_renders(jr, torch, fr, outs, reps, plain=True)
         peak = PEAK_FP32_TFLOPS if dt == "fp32" else PEAK_FP64_TFLOPS
+        # each image alone (seed, cap): its mean count and both rates
+        per = {}
+        for k, (f, o) in enumerate(zip(fr, outs)):
+            t_t = time_renders(jr, torch, [f], [o], reps, plain=False)
+            it_f = int(o.sum(dtype=torch.int64).item())
+            t_p = time_renders(jr, torch, [f], [o], reps, plain=True)
+            per["seed%d_cap%d" % (k % 4, f.max_iter)] = {
+                "mean_count": round(it_f / f.pixels, 3), "tuned_ms": round(t_t, 4),
+                "plain_ms": round(t_p, 4),
+                "gpixel_iter_s": round(it_f / (t_t * 1e-3) / 1e9, 1),
+                "plain_gpixel_iter_s": round(it_f / (t_p * 1e-3) / 1e9, 1)}
         ex["single_4096_%s" % dt] = {
             "gpixel_iter_s": round(it_s / (ms_t * 1e-3) / 1e9, 2),
             "plain_gpixel_iter_s": round(it_s / (ms_pl * 1e-3) / 1e9, 2),
             "frac_vector_peak": round(FLOP_PER_ITER * it_s / (ms_t * 1e-3) / 1e12 / peak, 4),
-            "images": len(fr), "pixel_iters": it_s}
+            "images": len(fr), "pixel_iters": it_s, "per_image": per}
         del outs
     # 512x512 FP64: launch-bound latency, tuned and plain
     f1 = wl.single_512("fp64")
@@ -497,32 +508,33 @@ def extra_legs(args, torch, jr, wl, frames, sched, ms_headline, iters):
     # percentiles at the latency they had when the run was cut off.
     ex["serving"] = serving_sweep(args, torch, wl)
     # the paper's timing study (Figure 1): square images of side 10 .. 10000,
-    # C = -0.8 + 0.156i, window [-1.5, 1.5]^2, cap 100, FP64: GPU time per
-    # image (tuned and plain, synchronised, launch included) beside the
-    # single-threaded oracle on this host
+    # C = -0.8 + 0.156i, window [-1.5, 1.5]^2, cap 100, FP64 and FP32: GPU
+    # time per image (tuned and plain, synchronised, launch included) beside
+    # the single-threaded oracle on this host in the same arithmetic
     if not args.no_cpu:
         import oracle
-    sweep = {}
-    for f in wl.square_sweep("fp64"):
-        o = torch.empty((f.height, f.width), dtype=torch.int32, device="cuda")
-        row = {}
-        for plain in (False, True):
-            jr.render(f.c, f.window, f.width, f.height, 100, "fp64", out=o, plain=plain)
-            torch.cuda.synchronize()
-            reps = 20 if f.width <= 1000 else 5
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                jr.render(f.c, f.window, f.width, f.height, 100, "fp64", out=o, plain=plain)
-            torch.cuda.synchronize()
-            row["gpu_plain_ms" if plain else "gpu_tuned_ms"] = round(
-                (time.perf_counter() - t0) * 1e3 / reps, 4)
-        if not args.no_cpu:
-            t0 = time.perf_counter()
-            oracle.render(f.c, f.window, f.width, f.height, 100, "fp64")
-            row["cpu_oracle_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
-        sweep["side_%d" % f.width] = row
-        del o
-    ex["figure1_square_sweep_fp64"] = sweep
+    for dt in ("fp64", "fp32"):
+        sweep = {}
+        for f in wl.square_sweep(dt):
+            o = torch.empty((f.height, f.width), dtype=torch.int32, device="cuda")
+            row = {}
+            for plain in (False, True):
+                jr.render(f.c, f.window, f.width, f.height, 100, dt, out=o, plain=plain)
+                torch.cuda.synchronize()
+                reps = 20 if f.width <= 1000 else 5
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    jr.render(f.c, f.window, f.width, f.height, 100, dt, out=o, plain=plain)
+                torch.cuda.synchronize()
+                row["gpu_plain_ms" if plain else "gpu_tuned_ms"] = round(
+                    (time.perf_counter() - t0) * 1e3 / reps, 4)
+            if not args.no_cpu:
+                t0 = time.perf_counter()
+                oracle.render(f.c, f.window, f.width, f.height, 100, dt)
+                row["cpu_oracle_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
+            sweep["side_%d" % f.width] = row
+            del o
+        ex["figure1_square_sweep_%s" % dt] = sweep
     # pixels whose FP32 / float-float count differs from FP64 (GPU vs GPU)
     mism = {}
     for dt in ("fp32", "ff"):
