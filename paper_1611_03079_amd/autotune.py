@@ -338,7 +338,8 @@ def apply_cache(cache: Dict[str, dict], max_iter: int = 100, pixels: int = 1 << 
 # workloads rendered one image per launch (tuned and filed per image)
 SINGLES = {"single_4096_fp32_cap100", "single_4096_fp32_cap1000", "single_4096_fp64_cap100",
            "single_4096_fp64_cap1000", "single_512_fp64", "single_small_fp64",
-           "single_1000_fp64", "single_10000_fp64"}
+           "single_1000_fp64", "single_10000_fp64", "single_512_fp32", "single_small_fp32",
+           "single_1000_fp32", "single_10000_fp32"}
 
 
 def standard_workloads():
@@ -358,6 +359,12 @@ def standard_workloads():
         "single_small_fp64": wl.square_sweep("fp64", sides=(32, 100, 200)),
         "single_1000_fp64": wl.square_sweep("fp64", sides=(1000, 2000)),
         "single_10000_fp64": wl.square_sweep("fp64", sides=(10000,)),
+        # the same sizes in FP32: without them FP32 images below 4M pixels
+        # would take the 4096^2 images' schedule
+        "single_512_fp32": [wl.single_512("fp32")],
+        "single_small_fp32": wl.square_sweep("fp32", sides=(32, 100, 200)),
+        "single_1000_fp32": wl.square_sweep("fp32", sides=(1000, 2000)),
+        "single_10000_fp32": wl.square_sweep("fp32", sides=(10000,)),
         # searched on its first 64 frames, confirmed on all 1024 (CONFIRM)
         "uneven_fp32_ff": wl.uneven_batch(0, n=64),
         "cardioid_path_fp32": wl.cardioid_path(64),
