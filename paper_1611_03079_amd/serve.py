@@ -36,7 +36,7 @@ import collections
 import math
 import threading
 import time
-from concurrent.futures import Future
+from concurrent.futures import Future, InvalidStateError
 from dataclasses import dataclass, field
 from typing import Deque, Dict, List, Optional
 
@@ -45,6 +45,16 @@ DTYPE_COST = {"fp32": 1.0, "fp64": 1.75, "ff": 10.0}
 
 class DeadlineExceeded(TimeoutError):
     """The request's deadline passed before its image was rendered."""
+
+
+def _fail(fut: Future, exc: BaseException):
+    """Fail a Future unless it is already done or the client cancelled it
+    (which may happen at any moment from another thread)."""
+    try:
+        if not fut.done():
+            fut.set_exception(exc)
+    except InvalidStateError:
+        pass
 
 
 class Overloaded(RuntimeError):
@@ -340,8 +350,7 @@ class Server:
                 self.stats.expired += 1
             else:
                 self.stats.failed += 1
-            if not r.future.done():
-                r.future.set_exception(exc)
+            _fail(r.future, exc)
         self._reap(r)
 
     def _reap(self, r: _Req):
@@ -371,7 +380,7 @@ class Server:
                     self.stats.cancelled += 1
                 elif now > r.deadline:
                     self.stats.expired += 1
-                    r.future.set_exception(DeadlineExceeded(
+                    _fail(r.future, DeadlineExceeded(
                         "request %d: deadline passed while queued" % r.rid))
                 else:
                     keep.append(r)
@@ -500,8 +509,11 @@ class Server:
                 with self.lock:
                     self.active.remove(r)
                     self.alloc.release(r.offset, r.frame.width * r.frame.height)
-                if not r.future.cancelled():
-                    r.future.set_result(out)
+                try:
+                    if not r.future.done():
+                        r.future.set_result(out)
+                except InvalidStateError:
+                    pass  # cancelled by the client just now
                 busy = True
             else:
                 keep.append((h, r, out))
