@@ -356,15 +356,20 @@ def extra_legs(args, torch, jr, wl, frames, sched, ms_headline, iters):
         outs = [torch.empty((f.height, f.width), dtype=torch.int32, device="cuda") for f in fr]
         ms_dp = time_renders(jr, torch, fr, outs, 1, plain=True)
         del outs
-        peak = PEAK_FP64_TFLOPS if dt == "fp64" else PEAK_FP32_UNPACKED_TFLOPS
+        # float-float counts its useful flops against the FP32 vector peak
+        # (its hardware operation count is in profiles/)
+        peak = PEAK_FP64_TFLOPS if dt == "fp64" else PEAK_FP32_TFLOPS
+        useful_tf = FLOP_PER_ITER * it_d / (kms_d * 1e-3) / 1e12
         ex["parameter_path_%s" % dt] = {
             "gpixel_iter_s": round(it_d / (ms_d * 1e-3) / 1e9, 2), "ms_per_step": round(ms_d, 4),
             "kernel_ms": round(kms_d, 4), "pixel_iters": it_d,
             "plain_per_frame_ms": round(ms_dp, 4), "vs_plain": round(ms_dp / ms_d, 3),
-            "useful_flop_frac_of_peak": round(FLOP_PER_ITER * it_d / (kms_d * 1e-3) / 1e12 / peak,
-                                              4),
-            "peak_tflops": peak, "schedule": (dsched.__dict__ if dsched else dsrc),
+            "useful_flop_frac_of_peak": round(useful_tf / peak, 4), "peak_tflops": peak,
+            "schedule": (dsched.__dict__ if dsched else dsrc),
             "workgroups": info_d["workgroups"]}
+        if dt == "ff":
+            ex["parameter_path_ff"]["useful_flop_frac_of_unpacked_fp32"] = round(
+                useful_tf / PEAK_FP32_UNPACKED_TFLOPS, 4)
     # Section 3's prescribed path with a growing cardioid: 256 frames of
     # 1920x1080, four trips of 64 frames while a goes from 3.9 to 3.5, FP32,
     # cap 100; the constants are generated on the device in every step (one
