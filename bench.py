@@ -300,6 +300,34 @@ def host_cpu():
     return model, os.cpu_count(), allowed
 
 
+def uneven_cpu_sample(frames, iters_by_dtype, per_frame=128):
+    """The single-threaded oracle on a deterministic sample of the uneven
+    batch: `per_frame` pixels of every frame (positions from a generator
+    seeded by the frame's index), timed per dtype.  Each dtype's sampled
+    rate, applied to that dtype's pixel-iterations in the whole batch (the
+    GPU's counts, equal to the oracle's), gives the extrapolated time of the
+    whole batch on one core; it is labelled as extrapolated."""
+    import numpy as np
+    import oracle
+    t = {}
+    it = {}
+    for k, f in enumerate(frames):
+        rng = np.random.default_rng(k)
+        ii = rng.integers(0, f.width, per_frame).astype(np.int32)
+        jj = rng.integers(0, f.height, per_frame).astype(np.int32)
+        t0 = time.perf_counter()
+        c = oracle.render_pixels(f.c, f.window, f.width, f.height, f.max_iter, ii, jj, f.dtype)
+        t[f.dtype] = t.get(f.dtype, 0.0) + time.perf_counter() - t0
+        it[f.dtype] = it.get(f.dtype, 0) + int(c.sum(dtype=np.int64))
+    rate = {dt: it[dt] / t[dt] for dt in t}
+    whole_s = sum(iters_by_dtype[dt] / rate[dt] for dt in iters_by_dtype)
+    return {"sample": "%d pixels of each of the %d frames, single thread" % (per_frame, len(frames)),
+            "sample_seconds": round(sum(t.values()), 2),
+            "rate_gpixel_iter_s_by_dtype": {dt: round(r / 1e9, 4) for dt, r in rate.items()},
+            "whole_batch_seconds_one_core_extrapolated": round(whole_s, 1),
+            "extrapolated": True}
+
+
 def cpu_baseline(frames, seconds):
     """The oracle on whole rows of the headline workload (FP32 formulation):
     single-threaded for `seconds`, then one host thread per core (at most 16,
@@ -469,7 +497,10 @@ def extra_legs(args, torch, jr, wl, frames, sched, ms_headline, iters):
     usched, _ = tuned_schedule(jr, "uneven_fp32_ff", ub)
     plan = jr.Plan(ub, usched)
     ms_u, _ = time_plan_steps(torch, plan, 1, 1, graph=False)
-    it_u = count_sum(torch, plan.views)
+    it_dt = {}
+    for f, v in zip(ub, plan.views):
+        it_dt[f.dtype] = it_dt.get(f.dtype, 0) + int(v.sum(dtype=torch.int64).item())
+    it_u = sum(it_dt.values())
     ms_up = time_renders(jr, torch, ub, plan.views, 1, plain=True)
     plan.close()
     del plan
@@ -478,7 +509,10 @@ def extra_legs(args, torch, jr, wl, frames, sched, ms_headline, iters):
         "gpixel_iter_s": round(it_u / (ms_u * 1e-3) / 1e9, 2), "ms": round(ms_u, 3),
         "plain_per_frame_ms": round(ms_up, 3), "vs_plain": round(ms_up / ms_u, 3),
         "frames": len(ub), "pixels": sum(f.pixels for f in ub), "pixel_iters": it_u,
-        "schedule": usched.__dict__}
+        "pixel_iters_by_dtype": it_dt, "schedule": usched.__dict__}
+    if not args.no_cpu:
+        ex["uneven_batch_1024_frames_fp32_ff"]["cpu_oracle_extrapolated"] = \
+            uneven_cpu_sample(ub, it_dt)
     # general map Z^3 + C: 32 frames of 1920x1080, one launch, against the
     # plain kernel launched per frame
     gp = wl.general_path(32, 3)
