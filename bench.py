@@ -518,7 +518,9 @@ def extra_legs(args, torch, jr, wl, frames, sched, ms_headline, iters):
     gp = wl.general_path(32, 3)
     gsched, _ = tuned_schedule(jr, "general_deg3_fp32", gp)
     plan = jr.Plan(gp, gsched)
-    ms_g, _ = time_plan_steps(torch, plan, 5, 1, graph=False)
+    plan.capture()
+    settle_clocks(torch, plan, 0.3)
+    ms_g, _ = time_plan_steps(torch, plan, 10, 2, graph=True)
     it_g = count_sum(torch, plan.views)
     plan.close()
     outs = [torch.empty((f.height, f.width), dtype=torch.int32, device="cuda") for f in gp]
@@ -538,6 +540,35 @@ def extra_legs(args, torch, jr, wl, frames, sched, ms_headline, iters):
         "gpixel_iter_s": round(it_g / (ms_g * 1e-3) / 1e9, 2), "ms": round(ms_g, 3),
         "plain_per_frame_ms": round(ms_gp, 3), "vs_plain": round(ms_gp / ms_g, 3),
         "schedule": gsched.__dict__, "pixel_iters": it_g}
+    # rational two-parameter maps Z^2 + C + lam / Z^2: 32 frames of 1920x1080
+    # along the parameter path's circle, FP32 and FP64, one launch against
+    # the plain kernel launched per frame
+    for dt in ("fp32", "fp64"):
+        rp = wl.rational_path(32, 2, dtype=dt)
+        rsched, rsrc = tuned_schedule_or_default(jr, "rational_deg2_" + dt)
+        plan = jr.Plan(rp, rsched)
+        plan.capture()
+        settle_clocks(torch, plan, 0.3)
+        ms_r, _ = time_plan_steps(torch, plan, 10, 2, graph=True)
+        it_r = count_sum(torch, plan.views)
+        plan.close()
+        outs = [torch.empty((f.height, f.width), dtype=torch.int32, device="cuda") for f in rp]
+
+        def plain_rational():
+            for f, o in zip(rp, outs):
+                jr.render(f.c, f.window, f.width, f.height, f.max_iter, f.dtype, out=o,
+                          plain=True, degree=2, lam=f.lam)
+        plain_rational()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plain_rational()
+        torch.cuda.synchronize()
+        ms_rp = (time.perf_counter() - t0) * 1e3
+        del outs
+        ex["rational_map_degree2_32_frames_" + dt] = {
+            "gpixel_iter_s": round(it_r / (ms_r * 1e-3) / 1e9, 2), "ms": round(ms_r, 3),
+            "plain_per_frame_ms": round(ms_rp, 3), "vs_plain": round(ms_rp / ms_r, 3),
+            "schedule": (rsched.__dict__ if rsched else rsrc), "pixel_iters": it_r}
     # serving: open-loop Poisson arrivals at the specified rates, each for
     # --serve-seconds or --serve-requests requests, whichever ends first,
     # with the calibrated precision policy (FP32 where it stays within 0.5%

@@ -369,6 +369,8 @@ def standard_workloads():
         "uneven_fp32_ff": wl.uneven_batch(0, n=64),
         "cardioid_path_fp32": wl.cardioid_path(64),
         "general_deg3_fp32": wl.general_path(32, 3),
+        "rational_deg2_fp32": wl.rational_path(32, 2, dtype="fp32"),
+        "rational_deg2_fp64": wl.rational_path(32, 2, dtype="fp64"),
     }
 
 

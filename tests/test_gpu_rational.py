@@ -125,3 +125,32 @@ def test_large_rational_frame_sampled():
     want = oracle.render_pixels(f.c, f.window, f.width, f.height, f.max_iter, ii, jj, "fp64",
                                 "julia", 2, lam=f.lam)
     np.testing.assert_array_equal(out.cpu().numpy()[jj, ii], want)
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "fp64"])
+def test_rational_path_in_the_bench_launch(dtype):
+    """The benchmark's rational workload: 32 frames of 1920 x 1080 of
+    Z^2 + C_k + lam_k / Z^2 in one launch with the autotune cache's schedule
+    (or the library default), each frame on 2000 sampled pixels against the
+    oracle, and every 8th frame whole."""
+    import workloads as wl
+    from paper_1611_03079_amd import autotune as at
+    frames = wl.rational_path(32, 2, dtype=dtype)
+    e = at.load_cache().get("_workloads", {}).get("rational_deg2_" + dtype)
+    sched = jr.Schedule(**e["schedule"]) if e else None
+    plan = jr.Plan(frames, sched)
+    plan.capture()
+    plan.replay()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(17)
+    for k, (f, v) in enumerate(zip(frames, plan.views)):
+        img = v.cpu().numpy()
+        if k % 8 == 0:
+            np.testing.assert_array_equal(img, ref(f), err_msg="frame %d" % k)
+            continue
+        ii = rng.integers(0, f.width, 2000).astype(np.int32)
+        jj = rng.integers(0, f.height, 2000).astype(np.int32)
+        want = oracle.render_pixels(f.c, f.window, f.width, f.height, f.max_iter, ii, jj, dtype,
+                                    "julia", 2, lam=f.lam)
+        np.testing.assert_array_equal(img[jj, ii], want, err_msg="frame %d" % k)
+    plan.close()

@@ -159,6 +159,24 @@ def general_path(n: int = 32, degree: int = 3, radius: float = 0.6, width: int =
 
 
 # --------------------------------------------------------------------------
+# Rational path: n frames of Z^d + C_k + lam_k / Z^d, C_k on the parameter
+# path's circle (|C| = 0.7885) and lam_k = lam_radius exp(-2 pi i k / n)
+# turning the other way; the parameter path's window.  |C| + |lam| / 2^d <= 1.9,
+# so escape is absorbing in every frame.
+# --------------------------------------------------------------------------
+def rational_path(n: int = 32, degree: int = 2, lam_radius: float = 0.002, width: int = 1920,
+                  height: int = 1080, max_iter: int = 100, dtype: str = "fp32",
+                  window=(-1.78, 1.78, -1.0, 1.0)) -> List[Frame]:
+    out = []
+    for k in range(n):
+        t = 2.0 * math.pi * k / n
+        c = complex(0.7885 * math.cos(t), 0.7885 * math.sin(t))
+        lam = complex(lam_radius * math.cos(-t), lam_radius * math.sin(-t))
+        out.append(Frame(c, window, width, height, max_iter, dtype, "julia", degree, lam))
+    return out
+
+
+# --------------------------------------------------------------------------
 # Uneven batch: square side ~ U{256..4096}; C uniform on the unit disk,
 # accepted when its Mandelbrot orbit from 0 survives 20 steps; cap from
 # {100, 500, 2000}; FP32 or float-float with probability 1/2 each.
