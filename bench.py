@@ -569,6 +569,27 @@ def extra_legs(args, torch, jr, wl, frames, sched, ms_headline, iters):
             "gpixel_iter_s": round(it_r / (ms_r * 1e-3) / 1e9, 2), "ms": round(ms_r, 3),
             "plain_per_frame_ms": round(ms_rp, 3), "vs_plain": round(ms_rp / ms_r, 3),
             "schedule": (rsched.__dict__ if rsched else rsrc), "pixel_iters": it_r}
+    # Mandelbrot zoom (Section 3): 64 frames of 1920x1080, the window from 3
+    # down to 1e-5 wide around a boundary point, cap 1000, FP64, one launch
+    # against the plain kernel launched per frame
+    mz = wl.mandelbrot_zoom(64)
+    msched, msrc = tuned_schedule_or_default(jr, "mandelbrot_zoom_fp64")
+    plan = jr.Plan(mz, msched)
+    plan.capture()
+    settle_clocks(torch, plan, 0.3)
+    ms_m, kms_m = time_plan_steps(torch, plan, 10, 2, graph=True)
+    it_m = count_sum(torch, plan.views)
+    plan.close()
+    outs = [torch.empty((f.height, f.width), dtype=torch.int32, device="cuda") for f in mz]
+    ms_mp = time_renders(jr, torch, mz, outs, 1, plain=True)
+    del outs
+    ex["mandelbrot_zoom_64_frames_fp64"] = {
+        "gpixel_iter_s": round(it_m / (ms_m * 1e-3) / 1e9, 2), "ms": round(ms_m, 3),
+        "kernel_ms": round(kms_m, 3), "plain_per_frame_ms": round(ms_mp, 3),
+        "vs_plain": round(ms_mp / ms_m, 3),
+        "useful_flop_frac_of_peak": round(FLOP_PER_ITER * it_m / (kms_m * 1e-3) / 1e12
+                                          / PEAK_FP64_TFLOPS, 4),
+        "schedule": (msched.__dict__ if msched else msrc), "pixel_iters": it_m}
     # serving: open-loop Poisson arrivals at the specified rates, each for
     # --serve-seconds or --serve-requests requests, whichever ends first,
     # with the calibrated precision policy (FP32 where it stays within 0.5%

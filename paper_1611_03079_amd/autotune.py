@@ -371,6 +371,7 @@ def standard_workloads():
         "general_deg3_fp32": wl.general_path(32, 3),
         "rational_deg2_fp32": wl.rational_path(32, 2, dtype="fp32"),
         "rational_deg2_fp64": wl.rational_path(32, 2, dtype="fp64"),
+        "mandelbrot_zoom_fp64": wl.mandelbrot_zoom(64),
     }
 
 

@@ -368,3 +368,18 @@ def test_batch_arena_is_checked_before_any_launch(make):
         jr.render_batch(fr, arena=arena)
     with pytest.raises(ValueError):
         jr.Plan(fr, arena=arena)
+
+
+def test_workload_recipes_of_the_extra_legs():
+    """The Mandelbrot zoom's windows shrink geometrically from 3 to 1e-5 wide
+    around their centre; the rational path keeps |C| + |lam| / 4 <= 1.9
+    (escape absorbing) in every frame."""
+    import workloads as wl
+    frames = wl.mandelbrot_zoom(64)
+    widths = [f.window[1] - f.window[0] for f in frames]
+    assert abs(widths[0] - 3.0) < 1e-12 and abs(widths[-1] - 1e-5) < 1e-15
+    ratios = [b / a for a, b in zip(widths, widths[1:])]
+    assert max(ratios) - min(ratios) < 1e-9
+    assert all(f.mode == "mandelbrot" and f.max_iter == 1000 for f in frames)
+    for f in wl.rational_path(32, 2):
+        assert abs(f.c) + abs(f.lam) / 4 <= 1.9

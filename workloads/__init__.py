@@ -159,6 +159,26 @@ def general_path(n: int = 32, degree: int = 3, radius: float = 0.6, width: int =
 
 
 # --------------------------------------------------------------------------
+# Mandelbrot zoom (Section 3's minimap and deep zooms on M): n frames of the
+# Mandelbrot image, the window's width shrinking geometrically from w0 to w1
+# around a boundary point in the seahorse valley; cap 1000, FP64.
+# --------------------------------------------------------------------------
+ZOOM_CENTRE = complex(-0.743643887037151, 0.131825904205330)
+
+
+def mandelbrot_zoom(n: int = 64, w0: float = 3.0, w1: float = 1e-5, width: int = 1920,
+                    height: int = 1080, max_iter: int = 1000, dtype: str = "fp64",
+                    centre: complex = ZOOM_CENTRE) -> List[Frame]:
+    out = []
+    for k in range(n):
+        w = w0 * (w1 / w0) ** (k / (n - 1) if n > 1 else 0.0)
+        h = w * height / width
+        win = (centre.real - w / 2, centre.real + w / 2, centre.imag - h / 2, centre.imag + h / 2)
+        out.append(Frame(0j, win, width, height, max_iter, dtype, "mandelbrot"))
+    return out
+
+
+# --------------------------------------------------------------------------
 # Rational path: n frames of Z^d + C_k + lam_k / Z^d, C_k on the parameter
 # path's circle (|C| = 0.7885) and lam_k = lam_radius exp(-2 pi i k / n)
 # turning the other way; the parameter path's window.  |C| + |lam| / 2^d <= 1.9,
