@@ -40,6 +40,12 @@ from concurrent.futures import Future, InvalidStateError
 from dataclasses import dataclass, field
 from typing import Deque, Dict, List, Optional
 
+# Relative cost of one pixel-iteration by arithmetic, in FP32 units, for the
+# step budget: about what the batched kernels take per pixel-iteration on the
+# parameter path (FP64 about 2x FP32, float-float about 7.5x), rounded up
+# for float-float, whose long orbits dominate a step that holds them.  The
+# budget's scale is learnt from measured step times; only these ratios are
+# fixed.
 DTYPE_COST = {"fp32": 1.0, "fp64": 1.75, "ff": 10.0}
 
 
