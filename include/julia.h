@@ -25,7 +25,13 @@
  *                y' = fma(x+x, y, ci); Z_0 and C are the binary64 values
  *                rounded to binary32.
  *       JR_FF    float-float (a value is hi + lo of two binary32 numbers),
- *                error-free sums and products, for narrow (deep-zoom) windows.
+ *                for narrow (deep-zoom) windows.  Z^2 + C: the double-word
+ *                square (TwoProd of hi plus a fused 2*hi*lo), the double-word
+ *                product for (2x)*y and the "sloppy" double-word sum (TwoSum
+ *                of the high words, the low words added to its error, one
+ *                Fast2Sum); escape when not (hi < 4 or (hi = 4 and lo <= 0))
+ *                for the sum of the two squares.  The general maps use the
+ *                accurate double-word sum and product throughout.
  *     The three give the same count on most pixels; FP32 and FF differ from
  *     FP64 on a small fraction of pixels near the set's boundary.
  *   - Memory: `out` / `out_base` are DEVICE pointers owned by the caller
