@@ -300,31 +300,30 @@ def host_cpu():
     return model, os.cpu_count(), allowed
 
 
-def uneven_cpu_sample(frames, iters_by_dtype, per_frame=128):
+def uneven_cpu_sample(frames, per_frame=128):
     """The single-threaded oracle on a deterministic sample of the uneven
     batch: `per_frame` pixels of every frame (positions from a generator
-    seeded by the frame's index), timed per dtype.  Each dtype's sampled
-    rate, applied to that dtype's pixel-iterations in the whole batch (the
-    GPU's counts, equal to the oracle's), gives the extrapolated time of the
-    whole batch on one core; it is labelled as extrapolated."""
+    seeded by the frame's index), each frame's sample time scaled by its
+    pixel count over the sample's, summed: the extrapolated time of the whole
+    batch on one core, labelled as extrapolated.  Uses the oracle's own
+    counts only."""
     import numpy as np
     import oracle
-    t = {}
-    it = {}
+    t, it, whole = {}, {}, 0.0
     for k, f in enumerate(frames):
         rng = np.random.default_rng(k)
         ii = rng.integers(0, f.width, per_frame).astype(np.int32)
         jj = rng.integers(0, f.height, per_frame).astype(np.int32)
         t0 = time.perf_counter()
         c = oracle.render_pixels(f.c, f.window, f.width, f.height, f.max_iter, ii, jj, f.dtype)
-        t[f.dtype] = t.get(f.dtype, 0.0) + time.perf_counter() - t0
+        dt_s = time.perf_counter() - t0
+        t[f.dtype] = t.get(f.dtype, 0.0) + dt_s
         it[f.dtype] = it.get(f.dtype, 0) + int(c.sum(dtype=np.int64))
-    rate = {dt: it[dt] / t[dt] for dt in t}
-    whole_s = sum(iters_by_dtype[dt] / rate[dt] for dt in iters_by_dtype)
+        whole += dt_s * f.pixels / per_frame
     return {"sample": "%d pixels of each of the %d frames, single thread" % (per_frame, len(frames)),
             "sample_seconds": round(sum(t.values()), 2),
-            "rate_gpixel_iter_s_by_dtype": {dt: round(r / 1e9, 4) for dt, r in rate.items()},
-            "whole_batch_seconds_one_core_extrapolated": round(whole_s, 1),
+            "rate_gpixel_iter_s_by_dtype": {dt: round(it[dt] / t[dt] / 1e9, 4) for dt in t},
+            "whole_batch_seconds_one_core_extrapolated": round(whole, 1),
             "extrapolated": True}
 
 
@@ -512,7 +511,7 @@ def extra_legs(args, torch, jr, wl, frames, sched, ms_headline, iters):
         "pixel_iters_by_dtype": it_dt, "schedule": usched.__dict__}
     if not args.no_cpu:
         ex["uneven_batch_1024_frames_fp32_ff"]["cpu_oracle_extrapolated"] = \
-            uneven_cpu_sample(ub, it_dt)
+            uneven_cpu_sample(ub)
     # general map Z^3 + C: 32 frames of 1920x1080, one launch, against the
     # plain kernel launched per frame
     gp = wl.general_path(32, 3)
