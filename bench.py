@@ -160,7 +160,7 @@ def serving_sweep(args, torch, wl):
     from paper_1611_03079_amd.serve import GpuBackend, PrecisionPolicy, Server, run_open_loop
     out = {}
     policies = (("calibrated", PrecisionPolicy(), (50, 100, 200, 500, 1000, 2000, 4000)),
-                ("three_way_ff", PrecisionPolicy.specified(), (50, 200, 1000)))
+                ("three_way_ff", PrecisionPolicy.specified(), (50, 200, 1000, 2000)))
     for pname, pol, rates in policies:
         sat = None
         for rate in rates:
