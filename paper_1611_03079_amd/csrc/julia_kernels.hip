@@ -1462,9 +1462,44 @@ __device__ void rows_tile(const Args& a, CFrame& F, int64_t t, int P, uint32_t* 
             };
             // The first trip always runs (P >= 4) and is written out apart
             // from the loop, so it reads the rows' starting values where they
-            // are instead of from copies made for the loop.
+            // are instead of from copies made for the loop.  In FP64 it ends
+            // early, after its second or third test, once every pixel of the
+            // group has escaped (light regions escape within a test or two;
+            // no pixel survives, so `done` need not be a multiple of 4).  The
+            // same early end made FP32 groups slower and is left out there.
+            constexpr bool kEarly = std::is_same<A, ArF64>::value;
+            auto first_trip = [&]() {
+                if constexpr (kEarly) {
+#pragma unroll
+                    for (int g = 0; g < G; ++g) l[g] += A::check_step(z[g], c[g], deg) ? 1 : 0;
+#pragma unroll
+                    for (int k = 2; k <= 3; ++k) {
+                        uint64_t alive = 0;
+#pragma unroll
+                        for (int g = 0; g < G; ++g) {
+                            const bool in = A::check_step(z[g], c[g], deg);
+                            l[g] += in ? 1 : 0;
+                            alive |= __ballot(in);
+                        }
+                        if ((alive & cols) == 0) return -k;  // all escaped after k tests
+                    }
+                    int still = 0;
+#pragma unroll
+                    for (int g = 0; g < G; ++g) {
+                        const bool in = A::check_step(z[g], c[g], deg);
+                        l[g] += in ? 1 : 0;
+                        still += __popcll(__ballot(in) & cols);
+                    }
+                    return still;
+                } else {
+                    return trip();
+                }
+            };
             int done = 4;
-            if (trip() > handoff) {
+            const int s1 = first_trip();
+            if (s1 < 0) {
+                done = -s1;  // every pixel escaped: no survivors
+            } else if (s1 > handoff) {
 #pragma unroll 1
                 while (done < P) {
                     done += 4;
