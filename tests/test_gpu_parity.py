@@ -149,6 +149,37 @@ def test_cap_edge_cases_rows(dtype):
             np.testing.assert_array_equal(views[0], ref(f), err_msg="cap %d %s" % (it, s))
 
 
+def test_fp64_groups_ending_their_first_trip_early():
+    """FP64 row pairs whose pixels have all escaped by the second or third
+    test of the first trip end it there.  With C = 0 a pixel's count is
+    fixed by |Z0| alone (0 beyond 2, 1 down to 2^(1/2), 2 down to 2^(1/4)),
+    so these windows hold whole row pairs of largest count 0, 1 and 2 next
+    to pairs that run on; caps straddle the ends (0..5), tiles are ragged,
+    and one batch mixes in an FP32 frame (pairs there too, no early end)."""
+    frames = [Frame(0j, (0.9, 2.3, -0.3, 0.3), 150, 45, 0, "fp64"),
+              Frame(0j, (1.2, 1.4, -0.05, 0.05), 64, 9, 0, "fp64"),
+              Frame(0j, (1.45, 1.95, -0.2, 0.2), 70, 8, 0, "fp64"),
+              Frame(0j, (2.1, 3.0, -1.0, 1.0), 65, 6, 0, "fp64")]
+    # the oracle's largest count over each pair of rows in each 64-column block
+    pair_max = set()
+    for f in frames:
+        img = ref(Frame(f.c, f.window, f.width, f.height, 100, f.dtype))
+        for j in range(0, f.height - 1, 2):
+            for i in range(0, f.width, 64):
+                pair_max.add(int(img[j:j + 2, i:i + 64].max()))
+    assert {0, 1, 2} <= pair_max and max(pair_max) > 4, pair_max
+    scheds = [jr.Schedule(64, 16, 8, 0, 16, 0, 16, "cost", "rows", 4, 0),
+              jr.Schedule(64, 8, 4, 0, 16, 0, 16, "table", "rows", 12, 128),
+              jr.Schedule(37, 5, 4, 0, 32, 1, 8, "table", "rows", 8, 0)]
+    for cap in (0, 1, 2, 3, 4, 5, 100):
+        fs = [Frame(f.c, f.window, f.width, f.height, cap, f.dtype) for f in frames]
+        fs.append(Frame(0j, (0.9, 2.3, -0.3, 0.3), 97, 11, cap, "fp32"))
+        for s in scheds:
+            _, views = batch(fs, s)
+            for f, v in zip(fs, views):
+                np.testing.assert_array_equal(v, ref(f), err_msg="cap %d %s %s" % (cap, f, s))
+
+
 # ------------------------------------------------------------------ batches
 def mixed_frames():
     return [
