@@ -41,12 +41,12 @@ from dataclasses import dataclass, field
 from typing import Deque, Dict, List, Optional
 
 # Relative cost of one pixel-iteration by arithmetic, in FP32 units, for the
-# step budget: about what the batched kernels take per pixel-iteration on the
-# parameter path (FP64 about 2x FP32, float-float about 7.5x), rounded up
+# step budget: what the batched kernels take per pixel-iteration on the
+# parameter path (FP64 about 2.1x FP32, float-float about 7.3x), rounded up
 # for float-float, whose long orbits dominate a step that holds them.  The
 # budget's scale is learnt from measured step times; only these ratios are
 # fixed.
-DTYPE_COST = {"fp32": 1.0, "fp64": 1.75, "ff": 10.0}
+DTYPE_COST = {"fp32": 1.0, "fp64": 2.1, "ff": 10.0}
 
 
 class DeadlineExceeded(TimeoutError):
@@ -79,8 +79,8 @@ class PrecisionPolicy:
     least 0.1 wide with caps up to 1000, and on more (0.69% to 93%) for
     narrower windows or larger caps; float-float on at most 0.28% down to
     1e-9.  The default routes everything that FP32 does not cover to FP64:
-    on MI355X FP64 is exact and costs about 1.75 times FP32, float-float about
-    13 times.  `specified()` is the three-way policy with float-float between
+    on MI355X FP64 is exact and costs about 2.1 times FP32 per iteration on
+    the parameter path, float-float about 7.3 times.  `specified()` is the three-way policy with float-float between
     1e-5 and the FP32 region."""
     fp32_min_width: float = 0.1
     fp32_max_iter: int = 1000

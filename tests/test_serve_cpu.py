@@ -323,7 +323,7 @@ def test_step_budget_follows_measured_step_times():
     rows = sorted(b.rows)
     assert rows[0][0] == 0 and rows[-1][1] == 4000
     assert all(a[1] == c[0] for a, c in zip(rows, rows[1:]))
-    assert Server._row_cost(f) == 200 * 3004 * 1.75
+    assert Server._row_cost(f) == 200 * 3004 * 2.1
 
 
 def test_step_rate_rises_slowly_and_is_capped():
