@@ -309,7 +309,9 @@ class Server:
                deadline: Optional[float] = None) -> Future:
         """Queue a request.  ``deadline``: time on the backend's clock by
         which the image must be rendered (default: arrival + timeout_s, or
-        none); past it the Future fails with DeadlineExceeded."""
+        none); past it the Future fails with DeadlineExceeded.  A frame whose
+        dtype is "auto" (or None) gets the policy's pick written into its
+        dtype field, so the caller can see which arithmetic rendered it."""
         fut = Future()
         if frame.width * frame.height > self.alloc.capacity:
             fut.set_exception(ValueError("frame larger than the output arena"))
