@@ -675,8 +675,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU; --gpus %d is not supported: the path has no "
-              "exchange between GPUs (DESIGN.md describes how it would shard)" % args.gpus,
-              file=sys.stderr)
+              "exchange between GPUs (several GPUs would each render their own share "
+              "of the frames)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1611_03079_amd as jr
