@@ -127,6 +127,9 @@ def parse():
                         "in one launch per step (autotuned schedule, or --plain)")
     p.add_argument("--plain", action="store_true",
                    help="with --leg: the one-thread-per-pixel comparator kernel")
+    p.add_argument("--leg-schedule", default=None,
+                   help="with --leg: this schedule (a JSON object of Schedule fields) "
+                        "instead of the autotuned one, for every call of the leg")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run an elementwise device copy of 1 GiB (read 1 GiB, write 1 GiB) "
                         "whose FETCH_SIZE / WRITE_SIZE counters calibrate the traffic figures")
@@ -232,11 +235,11 @@ def time_plan_steps(torch, plan, steps, warmup, graph=True):
     return (t1 - t0) * 1e3 / steps, kms
 
 
-def time_renders(jr, torch, frames, outs, reps, plain):
+def time_renders(jr, torch, frames, outs, reps, plain, schedule=None):
     def one():
         for f, o in zip(frames, outs):
             jr.render(f.c, f.window, f.width, f.height, f.max_iter, f.dtype, out=o,
-                      plain=plain, mode=f.mode)
+                      plain=plain, mode=f.mode, schedule=schedule)
     one()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -642,22 +645,28 @@ def extra_legs(args, torch, jr, wl, frames, sched, ms_headline, iters):
 def run_leg(args, torch, jr, wl):
     """One workload alone, for profiling: `steps` timed repetitions after
     `warmup`; prints one JSON line with its rate."""
+    forced = None
+    if args.leg_schedule is not None:
+        if args.plain:
+            sys.exit("--leg-schedule and --plain exclude each other")
+        forced = jr.Schedule(**json.loads(args.leg_schedule))
     if args.leg.startswith("single_4096"):
         dt = args.leg.rsplit("_", 1)[1]
         fr = [wl.single_4096(s, it, dt) for it in (100, 1000) for s in range(4)]
         outs = [torch.empty((f.height, f.width), dtype=torch.int32, device="cuda") for f in fr]
         t0 = time.perf_counter()  # settle the clock, as settle_clocks does
         while time.perf_counter() - t0 < SETTLE_S:
-            time_renders(jr, torch, fr, outs, 1, plain=args.plain)
-        time_renders(jr, torch, fr, outs, args.warmup, plain=args.plain)
-        ms = time_renders(jr, torch, fr, outs, args.steps, plain=args.plain)
+            time_renders(jr, torch, fr, outs, 1, plain=args.plain, schedule=forced)
+        time_renders(jr, torch, fr, outs, args.warmup, plain=args.plain, schedule=forced)
+        ms = time_renders(jr, torch, fr, outs, args.steps, plain=args.plain, schedule=forced)
         iters = count_sum(torch, outs)
-        sched = "plain" if args.plain else "per-image schedules from the autotune cache"
+        sched = ("plain" if args.plain else forced.__dict__ if forced is not None
+                 else "per-image schedules from the autotune cache")
     else:
         dt = args.leg.rsplit("_", 1)[1]
         fr = wl.parameter_path(dtype=dt)
-        sc = jr.Schedule(kernel="plain") if args.plain else tuned_schedule_or_default(
-            jr, args.leg)[0]
+        sc = jr.Schedule(kernel="plain") if args.plain else forced if forced is not None \
+            else tuned_schedule_or_default(jr, args.leg)[0]
         plan = jr.Plan(fr, sc)
         plan.capture()
         settle_clocks(torch, plan)
