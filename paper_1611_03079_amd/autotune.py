@@ -31,6 +31,7 @@ no schedule is passed.
 import json
 import math
 import os
+import time
 from dataclasses import asdict, replace
 from typing import Dict, List, Optional, Sequence, Tuple
 
@@ -54,8 +55,8 @@ def cap_bucket(max_iter: int) -> str:
     return "cap<=128" if max_iter <= 128 else "cap<=1024" if max_iter <= 1024 else "cap>1024"
 
 
-PIXEL_EDGES = [("px<64K", 1 << 16), ("px<512K", 1 << 19), ("px<4M", 1 << 22),
-               ("px<64M", 64 << 20)]
+PIXEL_EDGES = [("px<16K", 1 << 14), ("px<64K", 1 << 16), ("px<512K", 1 << 19),
+               ("px<4M", 1 << 22), ("px<64M", 64 << 20)]
 
 
 def pixel_bucket(pixels: int) -> str:
@@ -72,13 +73,48 @@ def cache_key(device: str, dtype: str, max_iter: int, pixels: int, batch: bool =
     return "|".join(parts + (["batch"] if batch else []))
 
 
+# Below this many pixels a render() call's host work and launch outweigh its
+# kernel: such images are timed as their caller waits for them, by the wall
+# clock over back-to-back render() calls.
+WALL_PIXELS = 1 << 16
+
+
 def time_singles(frames, schedule: jr.Schedule, reps: int = 3) -> float:
     """Sum over the frames of the time of each rendered on its own.  A single
     image under a plain schedule runs the two-dimensional one-thread-per-pixel
-    kernel (julia_render_plain), which is what is timed for it."""
+    kernel (julia_render_plain), which is what is timed for it.  Images below
+    WALL_PIXELS are timed by time_render_wall."""
+    if all(f.pixels < WALL_PIXELS for f in frames):
+        return sum(time_render_wall(f, schedule, reps=reps) for f in frames)
     if schedule.kernel == "plain":
         return sum(time_render_plain(f, reps=reps) for f in frames)
     return sum(time_plan([f], schedule, reps=reps) for f in frames)
+
+
+def time_render_wall(f, schedule: jr.Schedule, reps: int = 3, calls: int = 50) -> float:
+    """Wall time (ms) per render() call of one frame under `schedule`: the
+    median over `reps` runs of `calls` back-to-back calls, synchronised once
+    at the end of each run (host work, launch and kernel)."""
+    import torch
+    out = torch.empty((f.height, f.width), dtype=torch.int32, device="cuda")
+    plain = schedule.kernel == "plain"
+
+    def one():
+        jr.render(f.c, f.window, f.width, f.height, f.max_iter, f.dtype, out=out,
+                  plain=plain, schedule=None if plain else schedule, mode=f.mode,
+                  degree=f.degree)
+
+    one()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        for _ in range(calls):
+            one()
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3 / calls)
+    times.sort()
+    return times[len(times) // 2]
 
 
 def time_render_plain(f, reps: int = 3, span_ms: float = 5.0) -> float:
@@ -337,9 +373,9 @@ def apply_cache(cache: Dict[str, dict], max_iter: int = 100, pixels: int = 1 << 
 # ------------------------------------------------------------------ command line
 # workloads rendered one image per launch (tuned and filed per image)
 SINGLES = {"single_4096_fp32_cap100", "single_4096_fp32_cap1000", "single_4096_fp64_cap100",
-           "single_4096_fp64_cap1000", "single_512_fp64", "single_small_fp64",
-           "single_1000_fp64", "single_10000_fp64", "single_512_fp32", "single_small_fp32",
-           "single_1000_fp32", "single_10000_fp32"}
+           "single_4096_fp64_cap1000", "single_512_fp64", "single_tiny_fp64", "single_small_fp64",
+           "single_1000_fp64", "single_10000_fp64", "single_512_fp32", "single_tiny_fp32",
+           "single_small_fp32", "single_1000_fp32", "single_10000_fp32"}
 
 
 def standard_workloads():
@@ -356,13 +392,15 @@ def standard_workloads():
         "single_4096_fp64_cap1000": [wl.single_4096(s, 1000, "fp64") for s in range(2)],
         "single_512_fp64": [wl.single_512("fp64")],
         # the other sizes of the square sweep, one pixel bucket each
-        "single_small_fp64": wl.square_sweep("fp64", sides=(32, 100, 200)),
+        "single_tiny_fp64": wl.square_sweep("fp64", sides=(10, 32, 100)),
+        "single_small_fp64": wl.square_sweep("fp64", sides=(200,)),
         "single_1000_fp64": wl.square_sweep("fp64", sides=(1000, 2000)),
         "single_10000_fp64": wl.square_sweep("fp64", sides=(10000,)),
         # the same sizes in FP32: without them FP32 images below 4M pixels
         # would take the 4096^2 images' schedule
         "single_512_fp32": [wl.single_512("fp32")],
-        "single_small_fp32": wl.square_sweep("fp32", sides=(32, 100, 200)),
+        "single_tiny_fp32": wl.square_sweep("fp32", sides=(10, 32, 100)),
+        "single_small_fp32": wl.square_sweep("fp32", sides=(200,)),
         "single_1000_fp32": wl.square_sweep("fp32", sides=(1000, 2000)),
         "single_10000_fp32": wl.square_sweep("fp32", sides=(10000,)),
         # searched on its first 64 frames, confirmed on all 1024 (CONFIRM)

@@ -341,11 +341,12 @@ def test_autotune_buckets():
     pixel bucket, and the limits handed to the library are each bucket's
     largest pixel count."""
     from paper_1611_03079_amd import autotune as at
-    names = [at.pixel_bucket(s * s) for s in (100, 512, 1000, 4096, 10000)]
-    assert names == ["px<64K", "px<512K", "px<4M", "px<64M", "px>=64M"]
+    names = [at.pixel_bucket(s * s) for s in (100, 200, 512, 1000, 4096, 10000)]
+    assert names == ["px<16K", "px<64K", "px<512K", "px<4M", "px<64M", "px>=64M"]
     lim = at.PIXEL_LIMITS
     for name in names:
         assert at.pixel_bucket(lim[name]) == name
+    assert at.pixel_bucket(lim["px<16K"] + 1) == "px<64K"
     assert at.pixel_bucket(lim["px<64K"] + 1) == "px<512K"
     assert at.cap_bucket(100) == "cap<=128" and at.cap_bucket(129) == "cap<=1024"
     assert at.cache_key("gfx950", "fp64", 100, 512 * 512) == "gfx950|fp64|cap<=128|px<512K"
