@@ -119,12 +119,13 @@ def parse():
                         "one-thread-per-pixel kernel, or the refill stream (64x64 tiles, "
                         "counted blocks of 8), for profiling comparisons")
     p.add_argument("--leg", choices=("headline", "single_4096_fp64", "single_4096_fp32",
-                                      "parameter_path_fp64", "parameter_path_ff"),
+                                      "parameter_path_fp64", "parameter_path_ff", "figure1"),
                    default="headline",
                    help="run one workload alone (for profiling): the 8 single 4096^2 "
                         "images (seeds 0..3, caps 100 and 1000) rendered one call each, "
                         "tuned or with --plain; or a parameter path in FP64 / float-float "
-                        "in one launch per step (autotuned schedule, or --plain)")
+                        "in one launch per step (autotuned schedule, or --plain); or the timing "
+                        "study of square images (figure1)")
     p.add_argument("--plain", action="store_true",
                    help="with --leg: the one-thread-per-pixel comparator kernel")
     p.add_argument("--leg-schedule", default=None,
@@ -604,30 +605,7 @@ def extra_legs(args, torch, jr, wl, frames, sched, ms_headline, iters):
     # C = -0.8 + 0.156i, window [-1.5, 1.5]^2, cap 100, FP64 and FP32: GPU
     # time per image (tuned and plain, synchronised, launch included) beside
     # the single-threaded oracle on this host in the same arithmetic
-    if not args.no_cpu:
-        import oracle
-    for dt in ("fp64", "fp32"):
-        sweep = {}
-        for f in wl.square_sweep(dt):
-            o = torch.empty((f.height, f.width), dtype=torch.int32, device="cuda")
-            row = {}
-            for plain in (False, True):
-                jr.render(f.c, f.window, f.width, f.height, 100, dt, out=o, plain=plain)
-                torch.cuda.synchronize()
-                reps = 20 if f.width <= 1000 else 5
-                t0 = time.perf_counter()
-                for _ in range(reps):
-                    jr.render(f.c, f.window, f.width, f.height, 100, dt, out=o, plain=plain)
-                torch.cuda.synchronize()
-                row["gpu_plain_ms" if plain else "gpu_tuned_ms"] = round(
-                    (time.perf_counter() - t0) * 1e3 / reps, 4)
-            if not args.no_cpu:
-                t0 = time.perf_counter()
-                oracle.render(f.c, f.window, f.width, f.height, 100, dt)
-                row["cpu_oracle_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
-            sweep["side_%d" % f.width] = row
-            del o
-        ex["figure1_square_sweep_%s" % dt] = sweep
+    ex.update(figure1_sweep(args, torch, jr, wl))
     # pixels whose FP32 / float-float count differs from FP64 (GPU vs GPU)
     mism = {}
     for dt in ("fp32", "ff"):
@@ -642,6 +620,41 @@ def extra_legs(args, torch, jr, wl, frames, sched, ms_headline, iters):
     return ex
 
 
+def figure1_sweep(args, torch, jr, wl):
+    """The paper's timing study (Figure 1): wall time per render() call of
+    square images, tuned and plain, each the median of five runs of
+    back-to-back calls synchronised at the end (launch and host work
+    included), beside the single-threaded oracle in the same arithmetic."""
+    if not args.no_cpu:
+        import oracle
+    ex = {}
+    for dt in ("fp64", "fp32"):
+        sweep = {}
+        for f in wl.square_sweep(dt):
+            o = torch.empty((f.height, f.width), dtype=torch.int32, device="cuda")
+            row = {}
+            for plain in (False, True):
+                jr.render(f.c, f.window, f.width, f.height, 100, dt, out=o, plain=plain)
+                torch.cuda.synchronize()
+                reps = 20 if f.width <= 1000 else 5
+                runs = []
+                for _ in range(5):
+                    t0 = time.perf_counter()
+                    for _ in range(reps):
+                        jr.render(f.c, f.window, f.width, f.height, 100, dt, out=o, plain=plain)
+                    torch.cuda.synchronize()
+                    runs.append((time.perf_counter() - t0) * 1e3 / reps)
+                row["gpu_plain_ms" if plain else "gpu_tuned_ms"] = round(sorted(runs)[2], 4)
+            if not args.no_cpu:
+                t0 = time.perf_counter()
+                oracle.render(f.c, f.window, f.width, f.height, 100, dt)
+                row["cpu_oracle_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
+            sweep["side_%d" % f.width] = row
+            del o
+        ex["figure1_square_sweep_%s" % dt] = sweep
+    return ex
+
+
 def run_leg(args, torch, jr, wl):
     """One workload alone, for profiling: `steps` timed repetitions after
     `warmup`; prints one JSON line with its rate."""
@@ -650,6 +663,9 @@ def run_leg(args, torch, jr, wl):
         if args.plain:
             sys.exit("--leg-schedule and --plain exclude each other")
         forced = jr.Schedule(**json.loads(args.leg_schedule))
+    if args.leg == "figure1":
+        print(json.dumps({"leg": "figure1", **figure1_sweep(args, torch, jr, wl)}), flush=True)
+        return
     if args.leg.startswith("single_4096"):
         dt = args.leg.rsplit("_", 1)[1]
         fr = [wl.single_4096(s, it, dt) for it in (100, 1000) for s in range(4)]
