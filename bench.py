@@ -627,6 +627,7 @@ def figure1_sweep(args, torch, jr, wl):
     included), beside the single-threaded oracle in the same arithmetic."""
     if not args.no_cpu:
         import oracle
+        oracle.render(0j, (-1.0, 1.0, -1.0, 1.0), 2, 2, 1, "fp64")  # load it before timing
     ex = {}
     for dt in ("fp64", "fp32"):
         sweep = {}
